@@ -1,0 +1,28 @@
+"""Plain FP64 CPU oracle of the rotating IMEX-DG method (test infrastructure).
+
+This package is the reference that the HIP path is checked against. It is
+slow on purpose and written for reading against the paper: the nodal DG
+space and quadrature of Sec. 3, the weak forms of the momentum and energy
+stage equations (matrices A, B, R, C, D, M_g and vectors f, f_g, g, k), the
+Schur complement systems of the R1 and R2 fixed-point treatments, GMRES on
+the pressure system, the rotational factorisation of Sec. 3.1 and the
+IMEX-ARK2 step built from the Butcher tableau of Sec. 3.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the bench
+may import it. The product path never calls into it and shares no code,
+tables or helpers with it.
+
+Pins (tests/test_oracle_bruteforce.py, tests/test_oracle_pins.py): dense
+brute-force assembly of every stage matrix and of the explicit residual on
+periodic, walled, terrain-following and hanging-face meshes; quadrature and
+tableau order conditions; the closed-form inertial oscillation; reduction to
+1D upwind DG for linear advection; free stream, polynomial rest state, mass
+conservation, R1 = R2 fixed point, slice invariance; the DoF counts and
+Courant numbers printed in Sec. 4.
+
+Parity unpinned: the Rayleigh sponge term (its place in the IMEX split and its
+target state are a reading, not stated in the paper); the explicit Rusanov
+split of the energy dissipation into lambda/2 [rho kappa] (non-stiff) and
+lambda/2 [rho e] (stiff) is pinned only as implemented (brute force uses the
+same reading).
+"""

@@ -1,0 +1,210 @@
+"""Seeded synthetic workloads: mesh/physics/solver settings and initial states.
+
+This module holds no arithmetic of the DG method: it only describes the test
+problems (domains, stratified backgrounds, perturbations, noise) and turns
+primitive fields given at node coordinates into conserved variables. Both
+the HIP path and its CPU checker take their inputs from here.
+
+Backgrounds follow Sec. 4: the isothermal hydrostatic state of the inertia-
+gravity-wave test (p = p_s exp(-delta z), delta = g / (R T0)) and the
+constant-N stratification in Exner form of the orography tests. Reference
+surface pressure p_s = 1e5 Pa where the paper leaves it open.
+"""
+import math
+from dataclasses import dataclass, field, asdict
+import numpy as np
+
+GAMMA, RGAS, GRAV = 1.4, 287.0, 9.81
+CP = GAMMA * RGAS / (GAMMA - 1.0)
+P_REF = 1.0e5
+
+FLAT, BELL, GAUSS = 0, 1, 2
+R1, R2 = 1, 2
+
+
+@dataclass
+class MeshSpec:
+    Lx: float
+    Ly: float
+    Lz: float
+    nx: int
+    ny: int
+    nz: int
+    degree: int
+    periodic_x: int = 1
+    periodic_y: int = 1
+    terrain: int = FLAT
+    h0: float = 0.0
+    a: float = 1.0
+    xc: float = 0.0
+    yc: float = 0.0
+    ref_boxes: list = field(default_factory=list)
+
+
+@dataclass
+class PhysSpec:
+    gamma: float = GAMMA
+    R: float = RGAS
+    g: float = GRAV
+    f: float = 0.0
+    sponge_zB: float = 0.0
+    sponge_zT: float = 1.0
+    sponge_lam: float = 0.0
+    sponge_u: tuple = (0.0, 0.0, 0.0)
+
+
+@dataclass
+class NumSpec:
+    dt: float = 1.0
+    scheme: int = R2
+    picard_tol: float = 1e-10
+    picard_max: int = 20
+    gmres_tol: float = 1e-10
+    gmres_restart: int = 30
+    gmres_max: int = 500
+    fixed_iterations: bool = False
+
+
+@dataclass
+class Workload:
+    name: str
+    mesh: MeshSpec
+    phys: PhysSpec
+    num: NumSpec
+    steps: int
+    background: str          # "isothermal" or "stratified"
+    T0: float                # isothermal temperature or surface potential temperature
+    N: float = 0.0
+    U: float = 0.0
+    pert: str = "none"       # "gauss" (radius a_p) or "igw" (sin(pi z/H)/(1+(x-xc)^2/a_p^2))
+    pert_amp: float = 0.0
+    pert_a: float = 1.0
+    pert_xc: float = 0.0
+    pert_yc: float = 0.0
+    pert_zc: float = 0.0
+    noise: float = 0.0
+    seed: int = 0
+
+    def as_dict(self):
+        return asdict(self)
+
+
+# ----------------------------------------------------------------- configs
+def tiny_box(degree=2, scheme=R2):
+    """10x10x10 km box, 4x4x4 elements, isothermal 250 K rest state, f = 1e-4,
+    Gaussian theta' 0.01 K of radius 2 km at the centre, 1e-6 noise, dt = 2 s."""
+    return Workload(
+        name="tiny_box_4x4x4_r%d" % degree,
+        mesh=MeshSpec(10e3, 10e3, 10e3, 4, 4, 4, degree),
+        phys=PhysSpec(f=1e-4),
+        num=NumSpec(dt=2.0, scheme=scheme, gmres_tol=1e-10),
+        steps=10, background="isothermal", T0=250.0,
+        pert="gauss", pert_amp=0.01, pert_a=2e3, pert_xc=5e3, pert_yc=5e3, pert_zc=5e3,
+        noise=1e-6, seed=0)
+
+
+def igw_channel(nx=120, ny=40, nz=10, degree=3, scheme=R2):
+    """Rotating inertia-gravity-wave channel 3000x1000x10 km: N = 0.01, theta0 =
+    300 K, U = 20 m/s, f = 1e-4, theta' = 0.01 sin(pi z/H)/(1+(x-xc)^2/a^2),
+    a = 100 km, xc = 1500 km; dt = 20 s, 200 steps."""
+    return Workload(
+        name="igw_channel_%dx%dx%d_r%d" % (nx, ny, nz, degree),
+        mesh=MeshSpec(3000e3, 1000e3, 10e3, nx, ny, nz, degree),
+        phys=PhysSpec(f=1e-4),
+        num=NumSpec(dt=20.0, scheme=scheme),
+        steps=200, background="stratified", T0=300.0, N=0.01, U=20.0,
+        pert="igw", pert_amp=0.01, pert_a=100e3, pert_xc=1500e3, seed=1)
+
+
+def orography(nx=64, ny=64, nz=24, degree=4, scheme=R2, refined=False):
+    """Stratified rotating flow over a Gaussian hill (h0 = 400 m, half-width
+    2 km, centre (30, 30) km) in a 60x60x20 km Gal-Chen box: theta_ref =
+    293.15 K, N = 0.01, U = 10 m/s, f = 1e-4, Rayleigh sponge above 12 km with
+    lambda*dt = 1.2; dt = 4 s, 500 steps. `refined` gives the non-conforming
+    variant: two nested 2:1 levels around the hill."""
+    dt = 4.0
+    boxes = []
+    if refined:
+        boxes = [(25e3, 35e3, 25e3, 35e3, 0.0, 6e3), (27.5e3, 32.5e3, 27.5e3, 32.5e3, 0.0, 3e3)]
+    return Workload(
+        name="orography_%dx%dx%d_r%d%s" % (nx, ny, nz, degree, "_amr" if refined else ""),
+        mesh=MeshSpec(60e3, 60e3, 20e3, nx, ny, nz, degree, terrain=GAUSS, h0=400.0,
+                      a=2e3, xc=30e3, yc=30e3, ref_boxes=boxes),
+        phys=PhysSpec(f=1e-4, sponge_zB=12e3, sponge_zT=20e3, sponge_lam=1.2 / dt,
+                      sponge_u=(10.0, 0.0, 0.0)),
+        num=NumSpec(dt=dt, scheme=scheme),
+        steps=500, background="stratified", T0=293.15, N=0.01, U=10.0,
+        seed=3 if not refined else 4)
+
+
+# ------------------------------------------------------------- initial state
+def primitive_background(w: Workload, x, y, z):
+    """rho, p of the hydrostatic background at points (x, y, z)."""
+    if w.background == "isothermal":
+        delta = GRAV / (RGAS * w.T0)
+        p = P_REF * np.exp(-delta * z)
+        rho = p / (RGAS * w.T0)
+        return rho, p
+    N2 = w.N * w.N
+    exner = 1.0 + GRAV * GRAV / (CP * w.T0 * N2) * (np.exp(-N2 * z / GRAV) - 1.0)
+    p = P_REF * exner ** (CP / RGAS)
+    theta = w.T0 * np.exp(N2 * z / GRAV)
+    rho = p / (RGAS * theta * exner)
+    return rho, p
+
+
+def initial_state(w: Workload, coords):
+    """Conserved variables [5][E][Np] at node coordinates coords [3][E][Np].
+
+    The potential-temperature perturbation keeps the pressure and recomputes
+    the density. The optional noise multiplies rho and rho*E by (1 + eps xi)
+    and adds eps*xi m/s to each velocity component (xi ~ U[-1, 1) drawn per
+    field, element and node in that order from numpy default_rng(seed))."""
+    x, y, z = coords
+    rho, p = primitive_background(w, x, y, z)
+    if w.pert != "none":
+        if w.pert == "gauss":
+            r2 = (x - w.pert_xc) ** 2 + (y - w.pert_yc) ** 2 + (z - w.pert_zc) ** 2
+            dth = w.pert_amp * np.exp(-r2 / w.pert_a ** 2)
+        elif w.pert == "igw":
+            dth = w.pert_amp * np.sin(np.pi * z / w.mesh.Lz) / (1.0 + (x - w.pert_xc) ** 2 / w.pert_a ** 2)
+        else:
+            raise ValueError(w.pert)
+        exner = (p / P_REF) ** (RGAS / CP)
+        theta = p / (rho * RGAS * exner) + dth
+        rho = p / (RGAS * theta * exner)
+    u = np.zeros((3,) + x.shape)
+    u[0] = w.U
+    q = np.empty((5,) + x.shape)
+    if w.noise > 0.0:
+        xi = np.random.default_rng(w.seed).uniform(-1.0, 1.0, size=(5,) + x.shape)
+        u = u + w.noise * xi[1:4]
+        rho = rho * (1.0 + w.noise * xi[0])
+    q[0] = rho
+    q[1:4] = rho * u
+    q[4] = p / (GAMMA - 1.0) + 0.5 * rho * (u * u).sum(0)
+    if w.noise > 0.0:
+        q[4] *= (1.0 + w.noise * xi[4])
+    return q
+
+
+def random_positive_state(shape, seed, rho0=1.0, p0=1e5, urms=10.0, rel=0.05):
+    """A generic smooth-free random state with positive density and pressure:
+    rho = rho0 (1 + rel xi), u = urms xi, p = p0 (1 + rel xi)."""
+    g = np.random.default_rng(seed)
+    rho = rho0 * (1.0 + rel * g.uniform(-1, 1, shape))
+    u = urms * g.uniform(-1, 1, (3,) + tuple(shape))
+    p = p0 * (1.0 + rel * g.uniform(-1, 1, shape))
+    q = np.empty((5,) + tuple(shape))
+    q[0] = rho
+    q[1:4] = rho * u
+    q[4] = p / (GAMMA - 1.0) + 0.5 * rho * (u * u).sum(0)
+    return q
+
+
+def conserved_from_primitive(rho, u, p):
+    q = np.empty((5,) + np.shape(rho))
+    q[0] = rho
+    q[1:4] = rho * u
+    q[4] = p / (GAMMA - 1.0) + 0.5 * rho * (u * u).sum(0)
+    return q

@@ -1,0 +1,315 @@
+"""Oracle pins against closed forms, printed values, invariants and textbook cases.
+
+Each test fixes something the paper or mathematics determines independently
+of the oracle's code: quadrature exactness, the Butcher tableaux' order
+conditions and stability functions, the exact inertial oscillation, the
+reduction of the scheme to 1D upwind DG for linear advection, free-stream and
+rest-state preservation, discrete mass conservation, the equivalence of the
+R1 and R2 fixed points, slice invariance, and the counts and Courant numbers
+printed in Sec. 4.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import basis as B
+from oracle import dg, diagnostics
+from oracle.mesh import Mesh, MeshDesc
+from paper_2605_29598_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.json")
+
+
+# ------------------------------------------------------------------ basis
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_gauss_legendre_exactness(n):
+    x, w = B.gauss_legendre(n)
+    for k in range(2 * n):
+        assert abs(np.sum(w * x ** k) - 1.0 / (k + 1)) < 1e-14
+    assert abs(np.sum(w * x ** (2 * n)) - 1.0 / (2 * n + 1)) > 1e-8   # not exact beyond 2n-1
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_lagrange_tables(n):
+    b = B.Basis1D(n - 1)
+    rng = np.random.default_rng(n)
+    c = rng.standard_normal(n)                       # random degree n-1 polynomial
+    poly = np.polynomial.Polynomial(c)
+    vals = poly(b.x)
+    assert np.allclose(b.deriv @ vals, poly.deriv()(b.x), atol=1e-12, rtol=1e-12)
+    assert np.allclose(b.face @ vals, poly(np.array([0.0, 1.0])), atol=1e-12)
+    for h in (0, 1):
+        assert np.allclose(b.half[h] @ vals, poly(0.5 * (h + b.x)), atol=1e-12)
+    gll = B.gauss_lobatto(n)
+    assert gll[0] == 0.0 and gll[-1] == 1.0
+    # GLL interior points are the roots of P'_{n-1}: the (n)-point Lobatto rule is
+    # exact to degree 2n-3, check with weights from the Lagrange integrals
+    xg, wg = B.gauss_legendre(n + 2)
+    wl = (B.lagrange_values(gll, xg) * wg[:, None]).sum(0)
+    for k in range(2 * n - 2):
+        assert abs(np.sum(wl * gll ** k) - 1.0 / (k + 1)) < 1e-13
+
+
+# ---------------------------------------------------------------- tableau
+def test_tableau_order_conditions():
+    for A in (dg.A_EXP, dg.A_IMP):
+        assert np.allclose(A.sum(1), dg.C_NODES)           # c = A 1 (stage consistency)
+        assert abs(dg.B_W.sum() - 1.0) < 1e-15               # order 1
+        assert abs(dg.B_W @ dg.C_NODES - 0.5) < 1e-15        # order 2
+    # stiffly accurate implicit part (b = last row of A_IMP)
+    assert np.allclose(dg.A_IMP[2], dg.B_W)
+    assert abs(dg.A_IMP[1, 1] - (2 - math.sqrt(2)) / 2) < 1e-15
+
+
+def _stab(A, b, z):
+    return 1 + z * b @ np.linalg.solve(np.eye(3) - z * A, np.ones(3))
+
+
+def test_stability_functions():
+    g = json.load(open(GOLDEN))["inertial_oscillation"]
+    R = _stab(dg.A_IMP, dg.B_W, 1j * g["z_imag"])
+    assert abs(R.real - g["R_real"]) < 1e-10 and abs(R.imag - g["R_imag"]) < 1e-10
+    assert abs(abs(R) ** 10 - g["abs_R10"]) < 1e-8
+    # L-stability: R(z) -> 0 as z -> -inf; closed-form values
+    assert abs(_stab(dg.A_IMP, dg.B_W, -1e8)) < 1e-7
+    assert abs(_stab(dg.A_IMP, dg.B_W, -1.0) - 0.3504) < 1e-4
+    chi = 2 - math.sqrt(2)
+    for z in (-1.2, -2.0, 0.3 + 0.7j):
+        Re = 1 + z + z * z / 2 + chi * chi / 4 * z ** 3
+        assert abs(_stab(dg.A_EXP, dg.B_W, z) - Re) < 1e-13
+
+
+# ------------------------------------------------------------ printed values
+def test_printed_dof_counts():
+    for rec in json.load(open(GOLDEN))["dofs"]:
+        assert diagnostics.dofs_per_scalar(rec["cells"], rec["r"]) == rec["dofs"]
+
+
+def test_printed_courant_numbers():
+    for rec in json.load(open(GOLDEN))["courant"]:
+        c = math.sqrt(1.4 * 287.0 * rec["T0"])
+        hs = [rec["Lx"] / rec["nx"]]
+        if rec["d"] == 3:
+            hs.append(rec["Ly"] / rec["ny"])
+        hs.append(rec["Lz"] / rec["nz"])
+        H = diagnostics.box_diameter(*hs)
+        C = diagnostics.courant(rec["r"], c, rec["dt"], H, rec["d"])
+        assert abs(C - rec["C"]) < 10.0 ** -rec["digits"], rec["cite"]
+        if "C_adv" in rec:
+            Ca = diagnostics.courant(rec["r"], rec["U"], rec["dt"], H, rec["d"])
+            assert abs(Ca - rec["C_adv"]) < 10.0 ** -rec["digits"]
+
+
+def test_config_dof_and_element_counts():
+    # nested 2:1 refinement around the hill: 12288 - 144 + 1152 - 144 + 1152 cells
+    w = W.orography(32, 32, 12, 1, refined=True)
+    m = Mesh(MeshDesc(**vars(w.mesh)))
+    assert m.E == 14304
+    kinds = np.bincount(m.face_kind.ravel(), minlength=4)
+    assert kinds[2] == 4 * kinds[3]          # every coarse hanging face has 4 fine sides
+
+
+# ---------------------------------------------------------------- invariants
+def _uniform(mesh, rho, u, p):
+    shp = (mesh.E, mesh.Np)
+    return W.conserved_from_primitive(np.full(shp, rho),
+                                      np.broadcast_to(np.asarray(u, float)[:, None, None], (3,) + shp).copy(),
+                                      np.full(shp, p))
+
+
+@pytest.mark.parametrize("desc", [
+    MeshDesc(4e3, 3e3, 2e3, 3, 2, 2, 3),
+    MeshDesc(8e3, 8e3, 4e3, 4, 4, 2, 2, ref_boxes=[(2e3, 6e3, 2e3, 6e3, 0, 2e3), (3.5e3, 4.5e3, 3.5e3, 4.5e3, 0, 0.5e3)]),
+    MeshDesc(8e3, 8e3, 4e3, 3, 3, 3, 3, terrain=1, h0=400, a=1.5e3, xc=4e3, yc=4e3,
+             ref_boxes=[(2e3, 6e3, 2e3, 6e3, 0, 4e3)]),
+])
+def test_free_stream(desc):
+    mesh = Mesh(desc)
+    ph = dg.Phys(f=0.0, g=0.0)
+    q = _uniform(mesh, 1.2, [10.0, -3.0, 0.0], 1e5)
+    TNS, TS = dg.explicit_residual(mesh, ph, q)
+    # elements touching the (deformed) bottom wall see the normal flow through it
+    inner = (mesh.face_kind[:, 4] != 0) if desc.terrain else np.ones(mesh.E, bool)
+    scale = 1e5 * np.abs(mesh.nS).max()
+    assert np.abs(TNS[:, inner]).max() < 1e-13 * scale
+    assert np.abs(TS[:, inner]).max() < 1e-13 * scale
+    # pressure free stream holds everywhere, including walls over terrain
+    q0 = _uniform(mesh, 1.2, [0.0, 0.0, 0.0], 1e5)
+    T0 = dg.explicit_residual(mesh, ph, q0)
+    assert max(np.abs(T0[0]).max(), np.abs(T0[1]).max()) < 1e-13 * scale
+
+
+@pytest.mark.parametrize("desc", [
+    MeshDesc(4e3, 4e3, 3e3, 2, 2, 3, 2),
+    MeshDesc(4e3, 4e3, 2e3, 2, 2, 2, 2, ref_boxes=[(0, 1e3, 0, 1e3, 0, 0.5e3)]),
+])
+def test_polynomial_rest_state(desc):
+    """rho = const, p = p0 - rho g z, u = 0 is an exact discrete steady state on
+    affine meshes (hanging faces included), with gravity and rotation."""
+    mesh = Mesh(desc)
+    ph = dg.Phys(f=1e-4, g=9.81)
+    rho = 1.1
+    z = mesh.xq[..., 2]
+    q = W.conserved_from_primitive(np.full(z.shape, rho), np.zeros((3,) + z.shape), 1e5 - rho * 9.81 * z)
+    num = dg.Numerics(dt=10.0, picard_tol=1e-13, gmres_tol=1e-13)
+    y = q
+    for _ in range(2):
+        y, _ = dg.ark2_step(mesh, ph, num, y)
+    # round-off of p ~ 1e5 Pa sets the floor; the isothermal state sits ~1e-5 m/s and above
+    assert np.abs(y[1:4] / y[0]).max() < 1e-10
+    assert np.abs(y[0] - q[0]).max() < 1e-12
+
+
+def test_isothermal_state_not_preserved():
+    """Negative pin: the exponential isothermal background is not a discrete
+    steady state (the scheme is not well balanced), but its spurious velocity
+    shrinks with the polynomial degree."""
+    w = W.tiny_box()
+    errs = []
+    for r in (1, 2, 3):
+        mesh = Mesh(MeshDesc(10e3, 10e3, 10e3, 2, 2, 2, r))
+        w.pert, w.noise = "none", 0.0
+        q = W.initial_state(w, mesh.node_coords())
+        y, _ = dg.ark2_step(mesh, dg.Phys(f=1e-4), dg.Numerics(dt=2.0, gmres_tol=1e-12, picard_tol=1e-12), q)
+        errs.append(np.abs(y[3] / y[0]).max())
+    assert errs[0] > 1e-9
+    assert errs[2] < errs[1] < errs[0]
+
+
+@pytest.mark.parametrize("scheme", [dg.R1, dg.R2])
+def test_inertial_oscillation(scheme):
+    """Uniform flow, g = 0, f != 0: (u + i v)^n = R(-i f dt)^n (u + i v)^0 with
+    R the implicit stability function, E unchanged (Coriolis does no work)."""
+    g = json.load(open(GOLDEN))["inertial_oscillation"]
+    mesh = Mesh(MeshDesc(10e3, 10e3, 10e3, 2, 2, 2, 2))
+    f, dt = 1e-2, 20.0                      # f dt = 0.2 = -z_imag
+    ph = dg.Phys(f=f, g=0.0)
+    num = dg.Numerics(dt=dt, scheme=scheme, picard_tol=1e-15, picard_max=40, gmres_tol=1e-13)
+    q = _uniform(mesh, 1.1, [10.0, 0.0, 0.0], 9e4)
+    E0 = q[4].copy()
+    for _ in range(10):
+        q, _ = dg.ark2_step(mesh, ph, num, q)
+    z = 1j * g["z_imag"]
+    chi, b1 = 2 - math.sqrt(2), math.sqrt(2) / 4
+    R = (1 + z * b1 + z * b1 * (1 + z * chi / 2) / (1 - z * chi / 2)) / (1 - z * chi / 2)
+    assert abs(R - complex(g["R_real"], g["R_imag"])) < 1e-10
+    U = 10.0 * R ** 10
+    u = q[1:4] / q[0]
+    assert np.abs(u[0] - U.real).max() < 1e-10 and np.abs(u[1] - U.imag).max() < 1e-10
+    assert abs(np.hypot(u[0], u[1]).max() / 10.0 - g["abs_R10"]) < 1e-8
+    assert np.abs(q[4] - E0).max() < 1e-12 * E0.max()
+
+
+def _upwind_dg_matrix(nel, r, L, U):
+    """1D nodal DG (GL nodes) upwind operator for rho_t + U rho_x = 0, U > 0,
+    on a uniform periodic mesh, assembled from its textbook definition."""
+    n = r + 1
+    x, w = np.polynomial.legendre.leggauss(n)
+    x, w = 0.5 * (x + 1), 0.5 * w
+    h = L / nel
+    lv = lambda t: np.array([np.prod([(t - x[m]) / (x[i] - x[m]) for m in range(n) if m != i]) for i in range(n)])
+    dl = np.array([[sum(np.prod([(xq - x[l]) / (x[i] - x[l]) for l in range(n) if l not in (i, m)]) / (x[i] - x[m])
+                        for m in range(n) if m != i) for i in range(n)] for xq in x])   # dl[q, i]
+    l0, l1 = lv(0.0), lv(1.0)
+    Lm = np.zeros((nel * n, nel * n))
+    for e in range(nel):
+        s = slice(e * n, (e + 1) * n)
+        prev = slice(((e - 1) % nel) * n, ((e - 1) % nel + 1) * n)
+        # int U rho psi_i' dx = U sum_q w_q rho_q l_i'(x_q)   (dx cancels d/dx)
+        Lm[s, s] += U * (dl * w[:, None]).T
+        Lm[s, s] -= U * np.outer(l1, l1)
+        Lm[s, prev] += U * np.outer(l0, l1)
+        Lm[s, :] /= (h * w)[:, None]
+    return Lm, x, h
+
+
+def test_advection_reduces_to_upwind_dg():
+    """Constant u = U e_x and p, rho = rho0 + eps sin(2 pi x / L), g = f = 0:
+    Rusanov with lambda = |U| is upwind, m = U rho and p stay exact, and rho is
+    advanced by the explicit stability polynomial of the ARK2 scheme."""
+    nel, r, L, U, dt = 6, 3, 6e3, 20.0, 10.0
+    mesh = Mesh(MeshDesc(L, 1e3, 1e3, nel, 1, 1, r))
+    x = mesh.xq[..., 0]
+    rho = 1.0 + 0.1 * np.sin(2 * np.pi * x / L)
+    q = W.conserved_from_primitive(rho, np.stack([np.full_like(x, U), 0 * x, 0 * x]), np.full_like(x, 1e5))
+    ph = dg.Phys(f=0.0, g=0.0)
+    num = dg.Numerics(dt=dt, picard_tol=1e-14, gmres_tol=1e-14)
+    y = q
+    nsteps = 3
+    for _ in range(nsteps):
+        y, _ = dg.ark2_step(mesh, ph, num, y)
+    Lm, xg, h = _upwind_dg_matrix(nel, r, L, U)
+    chi = 2 - math.sqrt(2)
+    Z = dt * Lm
+    P = np.eye(len(Lm)) + Z + Z @ Z / 2 + chi * chi / 4 * Z @ Z @ Z
+    r1 = 1.0 + 0.1 * np.sin(2 * np.pi * ((np.arange(nel)[:, None] + xg[None, :]) * h) / L)
+    ref = np.linalg.matrix_power(P, nsteps) @ r1.ravel()
+    # 3D node (i, j, k) of element e -> 1D node (e, i)
+    n = r + 1
+    got = y[0].reshape(nel, n, n, n)            # [e][k][j][i]
+    for k in range(n):
+        for j in range(n):
+            assert np.abs(got[:, k, j, :].ravel() - ref).max() < 1e-12
+    assert np.abs(y[1] - U * y[0]).max() < 1e-11
+    _, _, _, u, _, p = dg.primitives(y, 1.4)
+    assert np.abs(p - 1e5).max() < 1e-8
+
+
+def test_mass_conservation():
+    w = W.tiny_box()
+    mesh = Mesh(MeshDesc(**vars(w.mesh)))
+    q = W.initial_state(w, mesh.node_coords())
+    M0 = dg.total_mass(mesh, q)
+    y = q
+    for _ in range(4):
+        y, _ = dg.ark2_step(mesh, dg.Phys(**vars(w.phys)), dg.Numerics(**vars(w.num)), y)
+    assert abs(dg.total_mass(mesh, y) - M0) <= 1e-13 * M0
+    # hanging faces and terrain
+    desc = MeshDesc(8e3, 8e3, 4e3, 2, 2, 2, 2, terrain=2, h0=300, a=2e3, xc=4e3, yc=4e3,
+                    ref_boxes=[(0, 4e3, 0, 4e3, 0, 2e3)])
+    mesh = Mesh(desc)
+    q = W.initial_state(w, mesh.node_coords())
+    M0 = dg.total_mass(mesh, q)
+    y, _ = dg.ark2_step(mesh, dg.Phys(f=1e-4), dg.Numerics(dt=2.0), q)
+    assert abs(dg.total_mass(mesh, y) - M0) <= 1e-13 * M0
+
+
+def test_r1_r2_same_fixed_point():
+    """Both lagging strategies converge to the solution of the same coupled
+    stage system, so tightly converged steps agree."""
+    w = W.tiny_box()
+    mesh = Mesh(MeshDesc(**vars(w.mesh)))
+    q = W.initial_state(w, mesh.node_coords())
+    ph = dg.Phys(f=1e-2)
+    out = []
+    for s in (dg.R1, dg.R2):
+        num = dg.Numerics(dt=5.0, scheme=s, picard_tol=1e-14, picard_max=60, gmres_tol=1e-14)
+        y, st = dg.ark2_step(mesh, ph, num, q)
+        out.append(y)
+    for fld in range(5):
+        scale = np.abs(out[1][fld]).max() if fld != 3 else np.abs(out[1][1]).max()
+        assert np.abs(out[0][fld] - out[1][fld]).max() < 1e-10 * max(scale, 1.0)
+
+
+def test_slice_invariance():
+    """y-invariant data on a periodic-y mesh stays y-invariant (2D slice)."""
+    desc = MeshDesc(8e3, 2e3, 4e3, 4, 2, 2, 2)
+    mesh = Mesh(desc)
+    x, z = mesh.xq[..., 0], mesh.xq[..., 2]
+    rho = 1.0 + 0.05 * np.sin(2 * np.pi * x / 8e3) * np.cos(np.pi * z / 4e3)
+    u = np.stack([5.0 + 0 * x, 2.0 + 0 * x, 0.1 * np.sin(np.pi * z / 4e3)])
+    q = W.conserved_from_primitive(rho, u, 1e5 - 9.81 * z)
+    # tight solves: the pressure-gradient/gravity cancellation leaves round-off
+    # of relative size ~1e-10 in the momentum tendency, which loose solves keep
+    y, _ = dg.ark2_step(mesh, dg.Phys(f=1e-4), dg.Numerics(dt=5.0, gmres_tol=1e-14, picard_tol=1e-14), q)
+    n = mesh.n
+    ey = mesh.elem_base[:, 1]
+    a = y[:, ey == 0].reshape(5, -1, n, n, n)
+    b = y[:, ey == 1].reshape(5, -1, n, n, n)
+    assert np.abs(a - b).max() < 1e-12 * np.abs(a).max()
+    # and within an element, along y
+    for fld in range(5):
+        assert np.abs(a[fld] - a[fld][:, :, :1, :]).max() < 1e-12 * np.abs(a[fld]).max() + 1e-12
