@@ -1,0 +1,197 @@
+/*
+ * imexdg.h - C-ABI of the MI355X rotating IMEX-DG hot path.
+ *
+ * The library evaluates the matrix-free DG operators of a rotating,
+ * compressible Euler solver (gravity, f-plane Coriolis) and advances it with
+ * the second-order IMEX additive Runge-Kutta scheme of Sec. 3 of the paper:
+ * explicit advective residual, implicit acoustic pressure Schur complement
+ * solved by GMRES inside the R1 / R2 Picard iterations, with
+ * (A + R)^{-1} = (I + beta J)^{-1} A^{-1} applied pointwise (Sec. 3.1).
+ *
+ * Conventions shared by every call:
+ *  - All floating-point data are IEEE binary64 unless stated otherwise.
+ *  - A field is an array [E][Np] with Np = (r+1)^3 nodal values per element;
+ *    multi-field arrays are field-major, e.g. the conserved state is
+ *    [5][E][Np] = (rho, rho*u, rho*v, rho*w, rho*E).
+ *  - Nodes are the tensor Gauss-Legendre points of each element (the nodal
+ *    basis of Sec. 3); node index i + n*(j + n*k), n = r+1, x index fastest.
+ *  - Elements: base cells numbered bz + nz*(bx + nx*by) (vertical fastest);
+ *    a refined base cell is replaced by its leaves, depth first, children
+ *    numbered cz + 2*(cx + 2*cy).
+ *  - "Dual" vectors are weak-form integrals against the basis functions
+ *    (e.g. S p); "nodal" vectors hold values at the nodes (tendencies
+ *    f = M^{-1} T, states).
+ *  - Device pointers are caller-owned device memory (on the device current
+ *    when the solver was created) and must not alias unless stated. Work is
+ *    queued on the solver's HIP stream; a call that returns host values
+ *    synchronises that stream.
+ *  - Every function returns IMX_OK (0) or an error code and never aborts or
+ *    prints; imx_last_error() describes the last failure on this thread.
+ */
+#ifndef IMEXDG_H
+#define IMEXDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IMX_OK = 0,
+    IMX_EINVAL = 1,      /* invalid argument or unsupported configuration */
+    IMX_ENOMEM = 2,      /* workspace too small / host allocation failed */
+    IMX_EHIP = 3,        /* HIP runtime error */
+    IMX_ENOCONV = 4,     /* Picard or GMRES iteration cap reached without convergence */
+    IMX_ENONFINITE = 5,  /* NaN or Inf detected */
+    IMX_EREJECT = 6,     /* server: request can never fit the budget */
+    IMX_ESTATE = 7       /* call not valid in the object's current state */
+} imx_status;
+
+enum { IMX_R1 = 1, IMX_R2 = 2 };            /* fixed-point treatment of R u and M_g u */
+enum { IMX_FP64 = 0, IMX_MIXED = 1 };       /* arithmetic of the Krylov inner loop */
+enum { IMX_FLAT = 0, IMX_BELL = 1, IMX_GAUSS = 2 };
+
+typedef struct imx_mesh imx_mesh;
+typedef struct imx_solver imx_solver;
+
+/* Box [0,Lx]x[0,Ly]x[0,Lz] with nx*ny*nz base hexahedra of degree `degree`
+ * (1..4). Periodic in x / y when flagged, slip walls otherwise and always at
+ * z = 0 and z = Lz. terrain != IMX_FLAT deforms the box with the Gal-Chen
+ * map z = h + zeta (Lz - h) / Lz over the surface
+ *   bell:     h = h0 / (1 + d^2/a^2)       (Sec. 4.3)
+ *   gaussian: h = h0 exp(-d^2/a^2)
+ * with d the (minimum-image, in periodic directions) horizontal distance to
+ * (xc, yc); the map is represented by its degree-r interpolant at the
+ * Gauss-Lobatto points of each base cell. ref_boxes holds n_ref boxes
+ * {x0,x1,y0,y1,z0,z1}: box i refines every level-i leaf that overlaps it with
+ * positive volume (static 2:1 refinement, hanging faces, Sec. 4.3). */
+typedef struct {
+    double Lx, Ly, Lz;
+    int nx, ny, nz, degree;
+    int periodic_x, periodic_y;
+    int terrain;
+    double h0, a, xc, yc;
+    int n_ref;
+    const double* ref_boxes;     /* host, n_ref*6 doubles, read during the call */
+} imx_mesh_desc;
+
+/* Physical constants (Sec. 2, Sec. 4) and the optional Rayleigh sponge of
+ * Sec. 4.3: lambda(z) = sponge_lambda sin^2(pi/2 (z - zB)/(zT - zB)) for
+ * z >= zB, relaxing the momentum towards rho * sponge_u in the explicit
+ * (non-stiff) part; sponge_lambda = 0 switches it off. */
+typedef struct {
+    double gamma, R, g, f;
+    double sponge_zB, sponge_zT, sponge_lambda;
+    double sponge_u[3];
+} imx_phys;
+
+/* Solver settings. GMRES(gmres_restart) on the M-preconditioned pressure
+ * Schur system in the L2(M) inner product stops when its residual falls to
+ * gmres_tol times the norm of the right-hand side, after gmres_max
+ * iterations (per solve), or on breakdown; the Picard loop stops when the
+ * relative variation of (u, p) (velocity weighted by the acoustic impedance)
+ * is below picard_tol or after picard_max iterations. fixed_iterations != 0
+ * runs exactly picard_max Picard and gmres_max GMRES iterations (parity
+ * mode). precision IMX_MIXED runs the Krylov inner loop in binary32 inside an
+ * outer binary64 defect correction that stops at gmres_tol; inner_tol is the
+ * relative residual reduction asked of each binary32 inner solve. */
+typedef struct {
+    double dt;
+    int scheme;                  /* IMX_R1 or IMX_R2 */
+    int precision;               /* IMX_FP64 or IMX_MIXED */
+    double picard_tol;
+    int picard_max;
+    double gmres_tol;
+    int gmres_restart;           /* 1..32 */
+    int gmres_max;
+    int fixed_iterations;
+    double inner_tol;
+} imx_numerics;
+
+typedef struct {
+    int picard_iters;
+    int gmres_iters;             /* total Krylov iterations (all precisions) */
+    double gmres_relres;         /* last true relative residual */
+    double picard_variation;     /* last relative Picard variation */
+} imx_solve_stats;
+
+typedef struct {
+    int steps;
+    int picard_iters;
+    int gmres_iters;
+    double mass;                 /* total mass after the last step (binary64) */
+} imx_step_stats;
+
+/* ---------------------------------------------------------------- mesh */
+/* Builds the mesh and its geometry on the host. Errors: IMX_EINVAL for bad
+ * sizes, unbalanced refinement or inverted elements. */
+imx_status imx_mesh_create(const imx_mesh_desc* desc, imx_mesh** out);
+/* Number of elements, nodes per element, number of coarse hanging faces and
+ * whether the geometry is deformed (per-point Jacobians). */
+imx_status imx_mesh_info(const imx_mesh* mesh, int64_t* n_elem, int* nodes_per_elem,
+                         int64_t* n_hanging_faces, int* deformed);
+/* Physical coordinates of every node, host array [3][E][Np] owned by the caller. */
+imx_status imx_mesh_node_coords(const imx_mesh* mesh, double* xyz_host);
+/* Diagonal of the mass matrix (quadrature weight times det J) at every node,
+ * host array [E][Np]. */
+imx_status imx_mesh_mass_diag(const imx_mesh* mesh, double* m_host);
+void imx_mesh_destroy(imx_mesh* mesh);
+
+/* -------------------------------------------------------------- solver */
+/* Creates a solver for `mesh` (which must outlive it) on HIP stream
+ * `hip_stream` (NULL = default stream) of the current device. No device
+ * memory is allocated: query the workspace size and bind caller memory. */
+imx_status imx_solver_create(const imx_mesh* mesh, const imx_phys* phys, const imx_numerics* num,
+                             void* hip_stream, imx_solver** out);
+imx_status imx_solver_workspace_bytes(const imx_solver* s, size_t* bytes);
+/* Binds `bytes` of caller-owned device memory (>= the queried size, 256-byte
+ * aligned) as the solver's workspace and uploads tables and geometry. The
+ * memory must stay valid until imx_solver_destroy. */
+imx_status imx_solver_bind_workspace(imx_solver* s, void* dev_ptr, size_t bytes);
+/* Changes dt / tolerances / scheme / precision of a bound solver. */
+imx_status imx_solver_set_numerics(imx_solver* s, const imx_numerics* num);
+
+/* Copies the conserved state [5][E][Np] (device) into / out of the solver. */
+imx_status imx_set_state(imx_solver* s, const double* q_dev);
+imx_status imx_get_state(const imx_solver* s, double* q_dev);
+
+/* Explicit tendencies of Sec. 3 as nodal vectors f = M^{-1} T at state q:
+ * fNS [5][E][Np] (advection with Rusanov fluxes, sponge) and fS [4][E][Np]
+ * (momentum and energy: pressure with centred flux, enthalpy flux with
+ * Rusanov dissipation on rho e, gravity, Coriolis). */
+imx_status imx_explicit_residual(imx_solver* s, const double* q_dev, double* fNS_dev, double* fS_dev);
+
+/* Fixes the stage coefficients of the implicit operators for the implicit
+ * diagonal coefficient a_ll = (2 - sqrt(2))/2 of the tableau: stage density
+ * rho_l [E][Np], lagged pressure p^k [E][Np] and lagged velocity u^k
+ * [3][E][Np] (all nodal, device, copied). */
+imx_status imx_implicit_setup(imx_solver* s, const double* rho_l_dev, const double* p_lag_dev,
+                              const double* u_lag_dev);
+/* Dual vector S p of the pressure Schur complement of the current setup:
+ * R2: [D - (C^k + M_g)(A + R)^{-1} B] p, R1: [D - C^k A^{-1} B] p (Sec. 3). */
+imx_status imx_schur_apply(imx_solver* s, const double* p_dev, double* out_dev);
+/* One implicit stage solve (Picard + GMRES) for the stage density rho_l:
+ * F = f - f_g [3][E][Np] and G0 = g without the lagged implicit Rusanov term
+ * [E][Np] are dual vectors; p0 / u0 the initial iterate (nodal). On return
+ * p [E][Np] and u [3][E][Np] hold the last iterate. IMX_ENOCONV if the
+ * Picard loop hit picard_max without convergence (not in parity mode). */
+imx_status imx_implicit_solve(imx_solver* s, const double* rho_l_dev, const double* F_dev,
+                              const double* G0_dev, const double* p0_dev, const double* u0_dev,
+                              double* p_dev, double* u_dev, imx_solve_stats* stats);
+/* Advances the bound state by nsteps IMEX-ARK2 steps (Sec. 3). A step that
+ * fails (IMX_ENOCONV, IMX_ENONFINITE) leaves the state of the last completed
+ * step in place. */
+imx_status imx_step(imx_solver* s, int nsteps, imx_step_stats* stats);
+/* Total mass sum_K int_K rho (binary64); synchronises. */
+imx_status imx_total_mass(imx_solver* s, double* mass);
+void imx_solver_destroy(imx_solver* s);
+
+/* Description of the last error raised on the calling thread. */
+const char* imx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

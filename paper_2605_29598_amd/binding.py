@@ -1,0 +1,248 @@
+"""ctypes binding of libimexdg.so (argument marshalling only).
+
+Every function of include/imexdg.h is exposed under the same name; the Mesh
+and Solver classes wrap them with torch tensors supplying device memory and
+the current HIP stream. Loading fails loudly when the library is not built:
+there is no fallback implementation.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+from . import workloads as W
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libimexdg.so")
+
+IMX_OK, IMX_EINVAL, IMX_ENOMEM, IMX_EHIP, IMX_ENOCONV, IMX_ENONFINITE, IMX_EREJECT, IMX_ESTATE = range(8)
+IMX_R1, IMX_R2 = 1, 2
+IMX_FP64, IMX_MIXED = 0, 1
+
+_c_i64p = ctypes.POINTER(ctypes.c_int64)
+_c_ip = ctypes.POINTER(ctypes.c_int)
+_vp = ctypes.c_void_p
+
+
+class imx_mesh_desc(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_double), ("Ly", ctypes.c_double), ("Lz", ctypes.c_double),
+                ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("degree", ctypes.c_int),
+                ("periodic_x", ctypes.c_int), ("periodic_y", ctypes.c_int), ("terrain", ctypes.c_int),
+                ("h0", ctypes.c_double), ("a", ctypes.c_double), ("xc", ctypes.c_double), ("yc", ctypes.c_double),
+                ("n_ref", ctypes.c_int), ("ref_boxes", ctypes.POINTER(ctypes.c_double))]
+
+
+class imx_phys(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("R", ctypes.c_double), ("g", ctypes.c_double), ("f", ctypes.c_double),
+                ("sponge_zB", ctypes.c_double), ("sponge_zT", ctypes.c_double), ("sponge_lambda", ctypes.c_double),
+                ("sponge_u", ctypes.c_double * 3)]
+
+
+class imx_numerics(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("scheme", ctypes.c_int), ("precision", ctypes.c_int),
+                ("picard_tol", ctypes.c_double), ("picard_max", ctypes.c_int), ("gmres_tol", ctypes.c_double),
+                ("gmres_restart", ctypes.c_int), ("gmres_max", ctypes.c_int), ("fixed_iterations", ctypes.c_int),
+                ("inner_tol", ctypes.c_double)]
+
+
+class imx_solve_stats(ctypes.Structure):
+    _fields_ = [("picard_iters", ctypes.c_int), ("gmres_iters", ctypes.c_int),
+                ("gmres_relres", ctypes.c_double), ("picard_variation", ctypes.c_double)]
+
+
+class imx_step_stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("picard_iters", ctypes.c_int), ("gmres_iters", ctypes.c_int),
+                ("mass", ctypes.c_double)]
+
+
+# name -> (restype, argtypes); the exported symbol set of include/imexdg.h
+SIGNATURES = {
+    "imx_last_error": (ctypes.c_char_p, []),
+    "imx_mesh_create": (ctypes.c_int, [ctypes.POINTER(imx_mesh_desc), ctypes.POINTER(_vp)]),
+    "imx_mesh_info": (ctypes.c_int, [_vp, _c_i64p, _c_ip, _c_i64p, _c_ip]),
+    "imx_mesh_node_coords": (ctypes.c_int, [_vp, _vp]),
+    "imx_mesh_mass_diag": (ctypes.c_int, [_vp, _vp]),
+    "imx_mesh_destroy": (None, [_vp]),
+    "imx_solver_create": (ctypes.c_int, [_vp, ctypes.POINTER(imx_phys), ctypes.POINTER(imx_numerics), _vp,
+                                         ctypes.POINTER(_vp)]),
+    "imx_solver_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "imx_solver_bind_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    "imx_solver_set_numerics": (ctypes.c_int, [_vp, ctypes.POINTER(imx_numerics)]),
+    "imx_set_state": (ctypes.c_int, [_vp, _vp]),
+    "imx_get_state": (ctypes.c_int, [_vp, _vp]),
+    "imx_explicit_residual": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "imx_implicit_setup": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "imx_schur_apply": (ctypes.c_int, [_vp, _vp, _vp]),
+    "imx_implicit_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(imx_solve_stats)]),
+    "imx_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(imx_step_stats)]),
+    "imx_total_mass": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
+    "imx_solver_destroy": (None, [_vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """Loads the in-tree library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libimexdg.so is not built (run __graft_entry__.build()); "
+                               "there is no CPU fallback for the HIP path")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class IMXError(RuntimeError):
+    def __init__(self, code, where):
+        msg = lib().imx_last_error().decode(errors="replace")
+        super().__init__(f"{where}: status {code}: {msg}")
+        self.code = code
+
+
+def check(code, where):
+    if code != IMX_OK:
+        raise IMXError(code, where)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _desc(ms: W.MeshSpec):
+    boxes = np.ascontiguousarray(np.array(ms.ref_boxes, dtype=np.float64).reshape(-1))
+    d = imx_mesh_desc(ms.Lx, ms.Ly, ms.Lz, ms.nx, ms.ny, ms.nz, ms.degree, int(ms.periodic_x), int(ms.periodic_y),
+                      int(ms.terrain), ms.h0, ms.a, ms.xc, ms.yc, len(ms.ref_boxes),
+                      boxes.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if len(ms.ref_boxes) else None)
+    return d, boxes
+
+
+class Mesh:
+    def __init__(self, spec: W.MeshSpec):
+        self.spec = spec
+        d, self._boxes = _desc(spec)
+        h = _vp()
+        check(lib().imx_mesh_create(ctypes.byref(d), ctypes.byref(h)), "imx_mesh_create")
+        self.h = h
+        E, Np, nh, dfm = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int64(), ctypes.c_int()
+        check(lib().imx_mesh_info(h, ctypes.byref(E), ctypes.byref(Np), ctypes.byref(nh), ctypes.byref(dfm)),
+              "imx_mesh_info")
+        self.E, self.Np, self.n_hanging, self.deformed = E.value, Np.value, nh.value, bool(dfm.value)
+
+    def node_coords(self):
+        out = np.empty((3, self.E, self.Np))
+        check(lib().imx_mesh_node_coords(self.h, out.ctypes.data_as(_vp)), "imx_mesh_node_coords")
+        return out
+
+    def mass_diag(self):
+        out = np.empty((self.E, self.Np))
+        check(lib().imx_mesh_mass_diag(self.h, out.ctypes.data_as(_vp)), "imx_mesh_mass_diag")
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.imx_mesh_destroy(self.h)
+            self.h = None
+
+
+def phys_struct(p: W.PhysSpec):
+    return imx_phys(p.gamma, p.R, p.g, p.f, p.sponge_zB, p.sponge_zT, p.sponge_lam, (ctypes.c_double * 3)(*p.sponge_u))
+
+
+def num_struct(n: W.NumSpec, precision=IMX_FP64, inner_tol=1e-3):
+    return imx_numerics(n.dt, n.scheme, precision, n.picard_tol, n.picard_max, n.gmres_tol, n.gmres_restart,
+                        n.gmres_max, int(n.fixed_iterations), inner_tol)
+
+
+class Solver:
+    """A solver bound to a torch-allocated device workspace on `device`."""
+
+    def __init__(self, mesh: Mesh, phys: W.PhysSpec, num: W.NumSpec, device="cuda:0", precision=IMX_FP64,
+                 inner_tol=1e-3):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available")
+        self.mesh = mesh
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        ph, nm = phys_struct(phys), num_struct(num, precision, inner_tol)
+        h = _vp()
+        with torch.cuda.device(self.device):
+            check(lib().imx_solver_create(mesh.h, ctypes.byref(ph), ctypes.byref(nm),
+                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                  "imx_solver_create")
+        self.h = h
+        nb = ctypes.c_size_t()
+        check(lib().imx_solver_workspace_bytes(h, ctypes.byref(nb)), "imx_solver_workspace_bytes")
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        check(lib().imx_solver_bind_workspace(h, ctypes.c_void_p(base + off), nb.value),
+              "imx_solver_bind_workspace")
+        self.E, self.Np = mesh.E, mesh.Np
+
+    def _t(self, *shape):
+        return torch.empty(shape, dtype=torch.float64, device=self.device)
+
+    def set_numerics(self, num: W.NumSpec, precision=IMX_FP64, inner_tol=1e-3):
+        nm = num_struct(num, precision, inner_tol)
+        check(lib().imx_solver_set_numerics(self.h, ctypes.byref(nm)), "imx_solver_set_numerics")
+
+    def set_state(self, q):
+        q = torch.as_tensor(q, dtype=torch.float64, device=self.device).contiguous()
+        check(lib().imx_set_state(self.h, _ptr(q)), "imx_set_state")
+        self._hold = q
+
+    def get_state(self):
+        out = self._t(5, self.E, self.Np)
+        check(lib().imx_get_state(self.h, _ptr(out)), "imx_get_state")
+        return out
+
+    def explicit_residual(self, q):
+        q = torch.as_tensor(q, dtype=torch.float64, device=self.device).contiguous()
+        fNS, fS = self._t(5, self.E, self.Np), self._t(4, self.E, self.Np)
+        check(lib().imx_explicit_residual(self.h, _ptr(q), _ptr(fNS), _ptr(fS)), "imx_explicit_residual")
+        return fNS, fS
+
+    def implicit_setup(self, rho_l, p_lag, u_lag):
+        ts = [torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous() for a in (rho_l, p_lag, u_lag)]
+        check(lib().imx_implicit_setup(self.h, *[_ptr(t) for t in ts]), "imx_implicit_setup")
+        self.stream.synchronize()
+
+    def schur_apply(self, p):
+        p = torch.as_tensor(p, dtype=torch.float64, device=self.device).contiguous()
+        out = self._t(self.E, self.Np)
+        check(lib().imx_schur_apply(self.h, _ptr(p), _ptr(out)), "imx_schur_apply")
+        return out
+
+    def implicit_solve(self, rho_l, F, G0, p0, u0):
+        ts = [torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous() for a in (rho_l, F, G0, p0, u0)]
+        p, u = self._t(self.E, self.Np), self._t(3, self.E, self.Np)
+        st = imx_solve_stats()
+        code = lib().imx_implicit_solve(self.h, *[_ptr(t) for t in ts], _ptr(p), _ptr(u), ctypes.byref(st))
+        check(code, "imx_implicit_solve")
+        return p, u, st
+
+    def step(self, nsteps=1):
+        st = imx_step_stats()
+        check(lib().imx_step(self.h, int(nsteps), ctypes.byref(st)), "imx_step")
+        return st
+
+    def total_mass(self):
+        m = ctypes.c_double()
+        check(lib().imx_total_mass(self.h, ctypes.byref(m)), "imx_total_mass")
+        return m.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            try:
+                self.stream.synchronize()
+            except Exception:
+                pass
+            _lib.imx_solver_destroy(self.h)
+            self.h = None

@@ -1,0 +1,58 @@
+// Internal declarations of the IMEX-DG library (host side).
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/imexdg.h"
+
+namespace imx {
+
+enum FaceKind : int { WALL = 0, CONF = 1, FINE = 2, COARSE = 3 };
+
+void set_error(const std::string& msg);
+
+// 1D tables of the nodal Gauss-Legendre basis of degree r (n = r + 1 points)
+// on the reference interval [0, 1].
+struct Basis1D {
+    int n = 0;
+    std::vector<double> x, w;       // GL points and weights
+    std::vector<double> D;          // D[q*n + i] = l_i'(x_q)
+    std::vector<double> face;       // face[s*n + i] = l_i(s)
+    std::vector<double> half;       // half[(h*n + a)*n + i] = l_i((h + x_a)/2)
+    std::vector<double> gll;        // Gauss-Lobatto points (geometry support points)
+    void build(int degree);
+};
+
+// Lagrange polynomials of `nodes` (and their derivatives) at t.
+void lagrange(const std::vector<double>& nodes, double t, double* val, double* der);
+
+struct Mesh {
+    imx_mesh_desc desc{};
+    std::vector<double> boxes;
+    int r = 0, n = 0, Np = 0, Nf = 0;
+    int64_t E = 0;
+    int Lmax = 0;
+    bool deformed = false;
+    Basis1D basis;
+    std::vector<int> base, level, sub;       // [E*3], [E], [E*3]
+    // faces: kind, neighbour (CONF/FINE: element, COARSE: hanging index), aux
+    // (FINE: subface | coarse hanging index << 2)
+    std::vector<int> fkind, fnbr, faux;      // [E*6]
+    std::vector<int> hang;                   // [nh*4] fine neighbours of coarse faces
+    int64_t nh = 0;
+    // geometry
+    std::vector<double> h;                   // [E*3] element sizes (affine part)
+    std::vector<double> WJ;                  // [E*Np] quadrature weight * det J
+    std::vector<double> G;                   // [9][E][Np] W detJ dxi_d/dx_c, deformed only
+    std::vector<double> nS;                  // [E][6][3][Nf] W2 * outward area vector, deformed only
+    std::vector<double> xyz;                 // [3][E][Np]
+};
+
+imx_status build_mesh(const imx_mesh_desc& d, Mesh& m);
+
+}  // namespace imx
+
+struct imx_mesh {
+    imx::Mesh m;
+};

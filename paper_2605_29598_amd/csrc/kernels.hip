@@ -1,0 +1,776 @@
+// HIP kernels (gfx950) of the rotating IMEX-DG hot path.
+//
+// Element kernels: a workgroup holds EPB elements with one lane per node; the
+// nodal basis sits at the Gauss-Legendre points, so volume terms are
+// pointwise plus one 1D derivative contraction per direction (staged in LDS)
+// and face traces are one contraction along the face normal. Faces are
+// handled element by element: conforming and periodic neighbours are read
+// from global memory, slip walls use the mirror state, and a face between
+// two refinement levels is integrated on the four fine subfaces (the coarse
+// trace is interpolated onto them, and the coarse side integrates with the
+// transposed interpolation). Both sides of a face evaluate the numerical flux
+// from the same inputs with the same arithmetic.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace imx {
+
+// ------------------------------------------------------------------ tables
+HostTab make_tab(const Basis1D& b) {
+    HostTab t{};
+    t.n = b.n;
+    for (int i = 0; i < b.n * b.n; ++i) t.D[i] = b.D[i];
+    for (int i = 0; i < 2 * b.n; ++i) t.f[i] = b.face[i];
+    for (int i = 0; i < 2 * b.n * b.n; ++i) t.H[i] = b.half[i];
+    for (int i = 0; i < b.n; ++i) t.w[i] = b.w[i];
+    return t;
+}
+
+template <int N, typename R>
+struct Tab {
+    R D[N][N];      // D[q][i] = l_i'(x_q)
+    R f[2][N];      // f[s][i] = l_i(s)
+    R H[2][N][N];   // H[h][a][i] = l_i((h + x_a)/2)
+    R w[N];
+};
+
+template <int N, typename R>
+static Tab<N, R> to_tab(const HostTab& h) {
+    Tab<N, R> t;
+    for (int q = 0; q < N; ++q)
+        for (int i = 0; i < N; ++i) t.D[q][i] = (R)h.D[q * N + i];
+    for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < N; ++i) t.f[s][i] = (R)h.f[s * N + i];
+    for (int hh = 0; hh < 2; ++hh)
+        for (int a = 0; a < N; ++a)
+            for (int i = 0; i < N; ++i) t.H[hh][a][i] = (R)h.H[(hh * N + a) * N + i];
+    for (int i = 0; i < N; ++i) t.w[i] = (R)h.w[i];
+    return t;
+}
+
+template <typename R>
+struct Geom {
+    int64_t E;
+    int deformed;
+    const int* kind;
+    const int* nbr;
+    const int* aux;
+    const int* hang;
+    const double* h;
+    const R* WJ;
+    const R* G;
+    const R* nS;
+};
+
+template <typename R>
+static Geom<R> geom(const DevMesh& m);
+template <>
+Geom<double> geom<double>(const DevMesh& m) {
+    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.WJ, m.G, m.nS};
+}
+template <>
+Geom<float> geom<float>(const DevMesh& m) {
+    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.WJf, m.Gf, m.nSf};
+}
+
+constexpr int epb_of(int N) { return N == 2 ? 16 : (N == 3 ? 9 : (N == 4 ? 4 : 2)); }
+constexpr int threads_of(int N) { return ((epb_of(N) * N * N * N + 63) / 64) * 64; }
+
+// Consecutive workgroups are dispatched round-robin over the 8 XCDs; give
+// every XCD a contiguous run of logical blocks so that neighbouring elements
+// meet in the same L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
+    const int64_t q = G >> 3, r = G & 7, x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
+template <int N>
+__device__ __forceinline__ int node_of(int d, int m, int a, int b) {
+    return d == 0 ? m + N * (a + N * b) : (d == 1 ? a + N * (m + N * b) : a + N * (b + N * m));
+}
+
+template <int N>
+__device__ __forceinline__ void split_node(int d, int node, int& m, int& pt) {
+    const int i = node % N, j = (node / N) % N, k = node / (N * N);
+    if (d == 0) { m = i; pt = j + N * k; }
+    else if (d == 1) { m = j; pt = i + N * k; }
+    else { m = k; pt = i + N * j; }
+}
+
+// value of a Q_r field (nodal array f of one element) at face point pt
+template <int N, typename R, typename P>
+__device__ __forceinline__ R face_value(const P* f, const R* fv, int d, int pt) {
+    const int a = pt % N, b = pt / N;
+    R acc = 0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) acc += fv[m] * (R)f[node_of<N>(d, m, a, b)];
+    return acc;
+}
+
+// face polynomial with GL values fv (LDS) at GL point pt of quarter h
+template <int N, typename R>
+__device__ __forceinline__ R sub_interp(const R* fv, const Tab<N, R>& T, int h, int pt) {
+    const int a = pt % N, b = pt / N, h1 = h & 1, h2 = h >> 1;
+    R acc = 0;
+#pragma unroll
+    for (int bb = 0; bb < N; ++bb) {
+        R s = 0;
+#pragma unroll
+        for (int aa = 0; aa < N; ++aa) s += T.H[h1][a][aa] * fv[aa + N * bb];
+        acc += T.H[h2][b][bb] * s;
+    }
+    return acc;
+}
+
+// transpose: contribution of subface values sv (quarter h) to coarse point pt
+template <int N, typename R>
+__device__ __forceinline__ R sub_interp_T(const R* sv, const Tab<N, R>& T, int h, int pt) {
+    const int a = pt % N, b = pt / N, h1 = h & 1, h2 = h >> 1;
+    R acc = 0;
+#pragma unroll
+    for (int bb = 0; bb < N; ++bb) {
+        R s = 0;
+#pragma unroll
+        for (int aa = 0; aa < N; ++aa) s += T.H[h1][aa][a] * sv[aa + N * bb];
+        acc += T.H[h2][bb][b] * s;
+    }
+    return acc;
+}
+
+// W2-weighted outward area vector of face f of element e at point pt
+template <int N, typename R>
+__device__ __forceinline__ void area(const Geom<R>& g, const Tab<N, R>& T, int64_t e, int f, int pt, R nS[3]) {
+    constexpr int NF = N * N;
+    if (g.deformed) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nS[c] = g.nS[((e * 6 + f) * 3 + c) * NF + pt];
+        return;
+    }
+    const int d = f >> 1, s = f & 1;
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const R A = T.w[pt % N] * T.w[pt / N] * (R)(g.h[3 * e + t1] * g.h[3 * e + t2]);
+    nS[0] = nS[1] = nS[2] = 0;
+    nS[d] = s ? A : -A;
+}
+
+// W detJ (d xi_d / d x_c) at a node
+template <int N, typename R>
+__device__ __forceinline__ R metric(const Geom<R>& g, int64_t e, int node, int d, int c, R wj) {
+    constexpr int NP = N * N * N;
+    if (g.deformed) return g.G[((size_t)(d * 3 + c) * g.E + e) * NP + node];
+    return d == c ? wj / (R)g.h[3 * e + d] : (R)0;
+}
+
+// sum_d (D_d^T G_d) at node, G in LDS [3][NP]
+template <int N, typename R>
+__device__ __forceinline__ R div_T(const R* G, const Tab<N, R>& T, int node) {
+    const int i = node % N, j = (node / N) % N, k = node / (N * N);
+    R acc = 0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) acc += T.D[q][i] * G[q + N * (j + N * k)];
+#pragma unroll
+    for (int q = 0; q < N; ++q) acc += T.D[q][j] * G[N * N * N + i + N * (q + N * k)];
+#pragma unroll
+    for (int q = 0; q < N; ++q) acc += T.D[q][k] * G[2 * N * N * N + i + N * (j + N * q)];
+    return acc;
+}
+
+// ---------------------------------------------------------- Euler fluxes
+// Normal fluxes seen from side A (area vector nS of side A): 0..4 non-stiff
+// (rho, m, E with Rusanov dissipation on rho, m, rho kappa), 5..7 stiff
+// pressure {p} nS, 8 stiff enthalpy {rho h u}.nS + Rusanov on rho e.
+template <typename R>
+__device__ __forceinline__ void euler_flux(const R* qa, const R* qbin, const R* nS, bool wall, R gam, R* fl) {
+    const R dS = sqrt(nS[0] * nS[0] + nS[1] * nS[1] + nS[2] * nS[2]);
+    const R nh[3] = {nS[0] / dS, nS[1] / dS, nS[2] / dS};
+    R qb[5];
+    if (wall) {
+        const R mn = qa[1] * nh[0] + qa[2] * nh[1] + qa[3] * nh[2];
+        qb[0] = qa[0];
+        qb[4] = qa[4];
+        for (int c = 0; c < 3; ++c) qb[1 + c] = qa[1 + c] - (R)2 * mn * nh[c];
+    } else {
+        for (int t = 0; t < 5; ++t) qb[t] = qbin[t];
+    }
+    const R gm1 = gam - (R)1;
+    R uA[3], uB[3];
+    for (int c = 0; c < 3; ++c) {
+        uA[c] = qa[1 + c] / qa[0];
+        uB[c] = qb[1 + c] / qb[0];
+    }
+    const R kA = (R)0.5 * (uA[0] * uA[0] + uA[1] * uA[1] + uA[2] * uA[2]);
+    const R kB = (R)0.5 * (uB[0] * uB[0] + uB[1] * uB[1] + uB[2] * uB[2]);
+    const R pA = gm1 * (qa[4] - qa[0] * kA);
+    const R pB = gm1 * (qb[4] - qb[0] * kB);
+    const R unA = uA[0] * nh[0] + uA[1] * nh[1] + uA[2] * nh[2];
+    const R unB = uB[0] * nh[0] + uB[1] * nh[1] + uB[2] * nh[2];
+    const R lam = fmax(fabs(unA), fabs(unB));
+    const R mnA = qa[1] * nS[0] + qa[2] * nS[1] + qa[3] * nS[2];
+    const R mnB = qb[1] * nS[0] + qb[2] * nS[1] + qb[3] * nS[2];
+    const R unSA = uA[0] * nS[0] + uA[1] * nS[1] + uA[2] * nS[2];
+    const R unSB = uB[0] * nS[0] + uB[1] * nS[1] + uB[2] * nS[2];
+    const R hl = (R)0.5 * lam * dS;
+    fl[0] = (R)0.5 * (mnA + mnB) + hl * (qa[0] - qb[0]);
+    for (int c = 0; c < 3; ++c)
+        fl[1 + c] = (R)0.5 * (qa[1 + c] * unSA + qb[1 + c] * unSB) + hl * (qa[1 + c] - qb[1 + c]);
+    fl[4] = (R)0.5 * (kA * mnA + kB * mnB) + hl * (qa[0] * kA - qb[0] * kB);
+    const R pavg = (R)0.5 * (pA + pB);
+    for (int c = 0; c < 3; ++c) fl[5 + c] = pavg * nS[c];
+    const R hA = gam / gm1 * pA, hB = gam / gm1 * pB;
+    fl[8] = (R)0.5 * (hA * unSA + hB * unSB) + hl * (pA - pB) / gm1;
+}
+
+// =====================================================================
+// Explicit residual: fNS = M^{-1} T_NS, fS = M^{-1} T_S (momentum, energy)
+// =====================================================================
+template <int N, typename R>
+__global__ void __launch_bounds__(threads_of(N))
+k_explicit(const R* __restrict__ q, R* __restrict__ fNS, R* __restrict__ fS, Geom<R> g, Tab<N, R> T,
+           PhysK ph, const double* __restrict__ sponge) {
+    constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
+    __shared__ R s_q[EPB][5][NP];
+    __shared__ R s_own[EPB][5][NF];
+    __shared__ R s_nb[EPB][5][NF];
+    __shared__ R s_fl[EPB][9][NF];
+    __shared__ R s_sub[EPB][4][9][NF];
+    __shared__ R s_G[EPB][3][NP];
+    const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
+    const int64_t e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+    const bool act = le < EPB && e < g.E;
+    const size_t fs = (size_t)g.E * NP;
+    const R gam = (R)ph.gamma;
+    if (act)
+        for (int t = 0; t < 5; ++t) s_q[le][t][node] = q[t * fs + e * NP + node];
+    __syncthreads();
+    R acc[9];
+    for (int o = 0; o < 9; ++o) acc[o] = 0;
+
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, s = f & 1;
+        const int kind = act ? g.kind[e * 6 + f] : -1;
+        const int nbr = act ? g.nbr[e * 6 + f] : 0;
+        const int aux = act ? g.aux[e * 6 + f] : 0;
+        if (act && node < NF) {
+            for (int t = 0; t < 5; ++t) s_own[le][t][node] = face_value<N>(&s_q[le][t][0], T.f[s], d, node);
+            if (kind == CONF || kind == FINE)
+                for (int t = 0; t < 5; ++t)
+                    s_nb[le][t][node] = face_value<N>(q + t * fs + (size_t)nbr * NP, T.f[1 - s], d, node);
+        }
+        __syncthreads();
+        if (act) {
+            const int nit = kind == COARSE ? 4 * NF : NF;
+            for (int it = node; it < nit; it += NP) {
+                const int hs = it / NF, pt = it - hs * NF;
+                R qa[5], qb[5], nS[3], fl[9];
+                bool wall = false;
+                if (kind == COARSE) {
+                    const int fn = g.hang[nbr * 4 + hs];
+                    for (int t = 0; t < 5; ++t) {
+                        qa[t] = sub_interp<N>(&s_own[le][t][0], T, hs, pt);
+                        qb[t] = face_value<N>(q + t * fs + (size_t)fn * NP, T.f[1 - s], d, pt);
+                    }
+                    area<N>(g, T, fn, f ^ 1, pt, nS);
+                    for (int c = 0; c < 3; ++c) nS[c] = -nS[c];
+                } else {
+                    for (int t = 0; t < 5; ++t) qa[t] = s_own[le][t][pt];
+                    if (kind == CONF)
+                        for (int t = 0; t < 5; ++t) qb[t] = s_nb[le][t][pt];
+                    else if (kind == FINE)
+                        for (int t = 0; t < 5; ++t) qb[t] = sub_interp<N>(&s_nb[le][t][0], T, aux & 3, pt);
+                    else
+                        wall = true;
+                    area<N>(g, T, e, f, pt, nS);
+                }
+                euler_flux<R>(qa, qb, nS, wall, gam, fl);
+                if (kind == COARSE)
+                    for (int o = 0; o < 9; ++o) s_sub[le][hs][o][pt] = fl[o];
+                else
+                    for (int o = 0; o < 9; ++o) s_fl[le][o][pt] = fl[o];
+            }
+        }
+        __syncthreads();
+        if (act && kind == COARSE && node < NF)
+            for (int o = 0; o < 9; ++o) {
+                R v = 0;
+                for (int h = 0; h < 4; ++h) v += sub_interp_T<N>(&s_sub[le][h][o][0], T, h, node);
+                s_fl[le][o][node] = v;
+            }
+        __syncthreads();
+        if (act) {
+            int m, pt;
+            split_node<N>(d, node, m, pt);
+            const R lf = T.f[s][m];
+            for (int o = 0; o < 9; ++o) acc[o] -= lf * s_fl[le][o][pt];
+        }
+    }
+
+    // volume terms
+    R rho = 1, u[3] = {0, 0, 0}, kin = 0, p = 0, wj = 1;
+    if (act) {
+        rho = s_q[le][0][node];
+        for (int c = 0; c < 3; ++c) u[c] = s_q[le][1 + c][node] / rho;
+        kin = (R)0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        p = (gam - (R)1) * (s_q[le][4][node] - rho * kin);
+        wj = g.WJ[e * NP + node];
+    }
+    for (int o = 0; o < 9; ++o) {
+        if (act) {
+            R F[3];
+            if (o == 0) {
+                for (int c = 0; c < 3; ++c) F[c] = s_q[le][1 + c][node];
+            } else if (o < 4) {
+                const R mo = s_q[le][o][node];
+                for (int c = 0; c < 3; ++c) F[c] = mo * u[c];
+            } else if (o == 4) {
+                for (int c = 0; c < 3; ++c) F[c] = kin * s_q[le][1 + c][node];
+            } else if (o < 8) {
+                for (int c = 0; c < 3; ++c) F[c] = (c == o - 5) ? p : (R)0;
+            } else {
+                const R rh = gam / (gam - (R)1) * p;
+                for (int c = 0; c < 3; ++c) F[c] = rh * u[c];
+            }
+            for (int dd = 0; dd < 3; ++dd) {
+                R v = 0;
+                for (int c = 0; c < 3; ++c) v += metric<N>(g, e, node, dd, c, wj) * F[c];
+                s_G[le][dd][node] = v;
+            }
+        }
+        __syncthreads();
+        if (act) acc[o] += div_T<N>(&s_G[le][0][0], T, node);
+        __syncthreads();
+    }
+    if (!act) return;
+    acc[5] += wj * rho * (R)ph.f * u[1];
+    acc[6] -= wj * rho * (R)ph.f * u[0];
+    acc[7] -= wj * rho * (R)ph.g;
+    acc[8] -= wj * rho * (R)ph.g * u[2];
+    if (ph.sponge) {
+        const R lam = (R)sponge[e * NP + node];
+        for (int c = 0; c < 3; ++c) acc[1 + c] -= wj * lam * (s_q[le][1 + c][node] - rho * (R)ph.su[c]);
+    }
+    for (int t = 0; t < 5; ++t) fNS[t * fs + e * NP + node] = acc[t] / wj;
+    for (int t = 0; t < 4; ++t) fS[t * fs + e * NP + node] = acc[5 + t] / wj;
+}
+
+// =====================================================================
+// Schur pass 1: w = P (Fh/rho - M^{-1} B p / rho) (+ R1 lag), face buffers
+// =====================================================================
+template <int N, typename R>
+__global__ void __launch_bounds__(threads_of(N))
+k_pass1(const R* __restrict__ p, const R* __restrict__ pscale, const R* __restrict__ Fh,
+        const R* __restrict__ rho, const R* __restrict__ pk, const R* __restrict__ uk, R* __restrict__ w,
+        R* __restrict__ FB, R* __restrict__ FBh, Geom<R> g, Tab<N, R> T, StageK sk) {
+    constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
+    __shared__ R s_p[EPB][NP];
+    __shared__ R s_pk[EPB][NP];
+    __shared__ R s_w[EPB][3][NP];
+    __shared__ R s_own[EPB][4][NF];
+    __shared__ R s_nb[EPB][NF];
+    __shared__ R s_fl[EPB][3][NF];
+    __shared__ R s_sub[EPB][4][3][NF];
+    __shared__ R s_G[EPB][3][NP];
+    const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
+    const int64_t e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+    const bool act = le < EPB && e < g.E;
+    const size_t fs = (size_t)g.E * NP;
+    const R gam = (R)sk.gamma;
+    const R sc = pscale ? pscale[0] : (R)1;
+    if (act) {
+        s_p[le][node] = p ? p[e * NP + node] : (R)0;
+        s_pk[le][node] = pk[e * NP + node];
+    }
+    __syncthreads();
+    R acc[3] = {0, 0, 0};
+    const R wj = act ? g.WJ[e * NP + node] : (R)1;
+    if (p) {
+        for (int f = 0; f < 6; ++f) {
+            const int d = f >> 1, s = f & 1;
+            const int kind = act ? g.kind[e * 6 + f] : -1;
+            const int nbr = act ? g.nbr[e * 6 + f] : 0;
+            const int aux = act ? g.aux[e * 6 + f] : 0;
+            if (act && node < NF) {
+                s_own[le][0][node] = sc * face_value<N>(&s_p[le][0], T.f[s], d, node);
+                if (kind == CONF || kind == FINE)
+                    s_nb[le][node] = sc * face_value<N>(p + (size_t)nbr * NP, T.f[1 - s], d, node);
+            }
+            __syncthreads();
+            if (act) {
+                const int nit = kind == COARSE ? 4 * NF : NF;
+                for (int it = node; it < nit; it += NP) {
+                    const int hs = it / NF, pt = it - hs * NF;
+                    R pa, pb, nS[3];
+                    if (kind == COARSE) {
+                        const int fn = g.hang[nbr * 4 + hs];
+                        pa = sub_interp<N>(&s_own[le][0][0], T, hs, pt);
+                        pb = sc * face_value<N>(p + (size_t)fn * NP, T.f[1 - s], d, pt);
+                        area<N>(g, T, fn, f ^ 1, pt, nS);
+                        for (int c = 0; c < 3; ++c) nS[c] = -nS[c];
+                    } else {
+                        pa = s_own[le][0][pt];
+                        pb = kind == CONF ? s_nb[le][pt]
+                                          : (kind == FINE ? sub_interp<N>(&s_nb[le][0], T, aux & 3, pt) : pa);
+                        area<N>(g, T, e, f, pt, nS);
+                    }
+                    const R avg = (R)0.5 * (pa + pb);
+                    for (int c = 0; c < 3; ++c) {
+                        if (kind == COARSE) s_sub[le][hs][c][pt] = avg * nS[c];
+                        else s_fl[le][c][pt] = avg * nS[c];
+                    }
+                }
+            }
+            __syncthreads();
+            if (act && kind == COARSE && node < NF)
+                for (int c = 0; c < 3; ++c) {
+                    R v = 0;
+                    for (int h = 0; h < 4; ++h) v += sub_interp_T<N>(&s_sub[le][h][c][0], T, h, node);
+                    s_fl[le][c][node] = v;
+                }
+            __syncthreads();
+            if (act) {
+                int m, pt;
+                split_node<N>(d, node, m, pt);
+                const R lf = T.f[s][m];
+                for (int c = 0; c < 3; ++c) acc[c] += lf * s_fl[le][c][pt];
+            }
+        }
+        const R pv = act ? sc * s_p[le][node] : (R)0;
+        for (int c = 0; c < 3; ++c) {
+            if (act)
+                for (int dd = 0; dd < 3; ++dd) s_G[le][dd][node] = metric<N>(g, e, node, dd, c, wj) * pv;
+            __syncthreads();
+            if (act) acc[c] -= div_T<N>(&s_G[le][0][0], T, node);
+            __syncthreads();
+        }
+    }
+    R wv[3] = {0, 0, 0};
+    if (act) {
+        const R r = rho[e * NP + node];
+        const R cdt = (R)sk.c_dt, beta = (R)sk.beta;
+        R v[3];
+        for (int c = 0; c < 3; ++c) {
+            const R mBp = cdt * acc[c] / wj;
+            v[c] = (Fh ? Fh[c * fs + e * NP + node] : (R)0) / r - mBp / r;
+        }
+        if (sk.scheme == 1) {
+            // the lagged rotation -A^{-1} R u^k = -beta J u^k belongs to the
+            // right-hand side F - R u^k, so it comes with Fh only
+            if (uk && Fh) {
+                v[0] += beta * uk[1 * fs + e * NP + node];
+                v[1] -= beta * uk[0 * fs + e * NP + node];
+            }
+            wv[0] = v[0];
+            wv[1] = v[1];
+            wv[2] = v[2];
+        } else {
+            const R si = (R)1 / ((R)1 + beta * beta);
+            wv[0] = si * (v[0] + beta * v[1]);
+            wv[1] = si * (-beta * v[0] + v[1]);
+            wv[2] = v[2];
+        }
+        for (int c = 0; c < 3; ++c) {
+            w[c * fs + e * NP + node] = wv[c];
+            s_w[le][c][node] = wv[c];
+        }
+    }
+    __syncthreads();
+    if (!FB) return;
+    // face buffers: (rho h)^k (w . nS) on this element's side of every face
+    const R hfac = gam / (gam - (R)1);
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, s = f & 1;
+        const int kind = act ? g.kind[e * 6 + f] : -1;
+        const int nbr = act ? g.nbr[e * 6 + f] : 0;
+        if (act && node < NF) {
+            s_own[le][0][node] = face_value<N>(&s_pk[le][0], T.f[s], d, node);
+            for (int c = 0; c < 3; ++c) s_own[le][1 + c][node] = face_value<N>(&s_w[le][c][0], T.f[s], d, node);
+        }
+        __syncthreads();
+        if (act && kind != WALL) {
+            const int nit = kind == COARSE ? 4 * NF : NF;
+            for (int it = node; it < nit; it += NP) {
+                const int hs = it / NF, pt = it - hs * NF;
+                R nS[3], vals[4];
+                if (kind == COARSE) {
+                    const int fn = g.hang[nbr * 4 + hs];
+                    for (int t = 0; t < 4; ++t) vals[t] = sub_interp<N>(&s_own[le][t][0], T, hs, pt);
+                    area<N>(g, T, fn, f ^ 1, pt, nS);
+                    for (int c = 0; c < 3; ++c) nS[c] = -nS[c];
+                    FBh[((size_t)nbr * 4 + hs) * NF + pt] =
+                        hfac * vals[0] * (vals[1] * nS[0] + vals[2] * nS[1] + vals[3] * nS[2]);
+                } else {
+                    for (int t = 0; t < 4; ++t) vals[t] = s_own[le][t][pt];
+                    area<N>(g, T, e, f, pt, nS);
+                    FB[((size_t)e * 6 + f) * NF + pt] =
+                        hfac * vals[0] * (vals[1] * nS[0] + vals[2] * nS[1] + vals[3] * nS[2]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// =====================================================================
+// Schur pass 2: out = alpha (Gp - p/(gamma-1) - M^{-1} C^k w - [R2] M^{-1} M_g w)
+// =====================================================================
+template <int N, typename R>
+__global__ void __launch_bounds__(threads_of(N))
+k_pass2(const R* __restrict__ Gp, const R* __restrict__ p, const R* __restrict__ pscale,
+        const R* __restrict__ w, const R* __restrict__ pk, const R* __restrict__ rho, const R* __restrict__ FB,
+        const R* __restrict__ FBh, R* __restrict__ out, R alpha, int dual, Geom<R> g, Tab<N, R> T, StageK sk) {
+    constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
+    __shared__ R s_fl[EPB][NF];
+    __shared__ R s_sub[EPB][4][NF];
+    __shared__ R s_G[EPB][3][NP];
+    const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
+    const int64_t e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+    const bool act = le < EPB && e < g.E;
+    const size_t fs = (size_t)g.E * NP;
+    const R gam = (R)sk.gamma;
+    R acc = 0;
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, s = f & 1;
+        const int kind = act ? g.kind[e * 6 + f] : -1;
+        const int nbr = act ? g.nbr[e * 6 + f] : 0;
+        const int aux = act ? g.aux[e * 6 + f] : 0;
+        if (act) {
+            const int nit = kind == COARSE ? 4 * NF : NF;
+            for (int it = node; it < nit; it += NP) {
+                const int hs = it / NF, pt = it - hs * NF;
+                if (kind == COARSE) {
+                    const int fn = g.hang[nbr * 4 + hs];
+                    s_sub[le][hs][pt] = (R)0.5 * (FBh[((size_t)nbr * 4 + hs) * NF + pt] -
+                                                  FB[((size_t)fn * 6 + (f ^ 1)) * NF + pt]);
+                } else if (kind == CONF) {
+                    s_fl[le][pt] = (R)0.5 * (FB[((size_t)e * 6 + f) * NF + pt] - FB[((size_t)nbr * 6 + (f ^ 1)) * NF + pt]);
+                } else if (kind == FINE) {
+                    s_fl[le][pt] = (R)0.5 * (FB[((size_t)e * 6 + f) * NF + pt] -
+                                             FBh[((size_t)(aux >> 2) * 4 + (aux & 3)) * NF + pt]);
+                } else {
+                    s_fl[le][pt] = 0;
+                }
+            }
+        }
+        __syncthreads();
+        if (act && kind == COARSE && node < NF) {
+            R v = 0;
+            for (int h = 0; h < 4; ++h) v += sub_interp_T<N>(&s_sub[le][h][0], T, h, node);
+            s_fl[le][node] = v;
+        }
+        __syncthreads();
+        if (act) {
+            int m, pt;
+            split_node<N>(d, node, m, pt);
+            acc += T.f[s][m] * s_fl[le][pt];
+        }
+        __syncthreads();
+    }
+    R wv[3] = {0, 0, 0}, wj = 1, rh = 0;
+    if (act) {
+        wj = g.WJ[e * NP + node];
+        for (int c = 0; c < 3; ++c) wv[c] = w[c * fs + e * NP + node];
+        rh = gam / (gam - (R)1) * pk[e * NP + node];
+        for (int dd = 0; dd < 3; ++dd) {
+            R v = 0;
+            for (int c = 0; c < 3; ++c) v += metric<N>(g, e, node, dd, c, wj) * wv[c];
+            s_G[le][dd][node] = rh * v;
+        }
+    }
+    __syncthreads();
+    if (!act) return;
+    acc -= div_T<N>(&s_G[le][0][0], T, node);
+    const R cdt = (R)sk.c_dt;
+    R res = Gp ? Gp[e * NP + node] : (R)0;
+    if (p) res -= (pscale ? pscale[0] : (R)1) * p[e * NP + node] / (gam - (R)1);
+    res -= cdt * acc / wj;
+    if (sk.scheme == 2) res -= cdt * (R)sk.g * rho[e * NP + node] * wv[2];
+    res *= alpha;
+    if (dual) res *= wj;
+    out[e * NP + node] = res;
+}
+
+// =====================================================================
+// Picard refresh: Gp = G0h - M^{-1} Lambda^k - rho kappa^k [- R1 gravity lag]
+// =====================================================================
+template <int N>
+__global__ void __launch_bounds__(threads_of(N))
+k_lambda(const double* __restrict__ pk, const double* __restrict__ uk, const double* __restrict__ rho,
+         const double* __restrict__ G0h, double* __restrict__ Gp, Geom<double> g, Tab<N, double> T, StageK sk) {
+    using R = double;
+    constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
+    __shared__ R s_q[EPB][4][NP];
+    __shared__ R s_own[EPB][4][NF];
+    __shared__ R s_nb[EPB][4][NF];
+    __shared__ R s_fl[EPB][NF];
+    __shared__ R s_sub[EPB][4][NF];
+    const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
+    const int64_t e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+    const bool act = le < EPB && e < g.E;
+    const size_t fs = (size_t)g.E * NP;
+    const R gm1 = sk.gamma - 1.0;
+    // fields 0..2: u^k, 3: p^k
+    auto src = [&](int t) -> const R* { return t < 3 ? uk + t * fs : pk; };
+    if (act)
+        for (int t = 0; t < 4; ++t) s_q[le][t][node] = src(t)[e * NP + node];
+    __syncthreads();
+    R acc = 0;
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, s = f & 1;
+        const int kind = act ? g.kind[e * 6 + f] : -1;
+        const int nbr = act ? g.nbr[e * 6 + f] : 0;
+        const int aux = act ? g.aux[e * 6 + f] : 0;
+        if (act && node < NF) {
+            for (int t = 0; t < 4; ++t) s_own[le][t][node] = face_value<N>(&s_q[le][t][0], T.f[s], d, node);
+            if (kind == CONF || kind == FINE)
+                for (int t = 0; t < 4; ++t)
+                    s_nb[le][t][node] = face_value<N>(src(t) + (size_t)nbr * NP, T.f[1 - s], d, node);
+        }
+        __syncthreads();
+        if (act) {
+            const int nit = kind == COARSE ? 4 * NF : NF;
+            for (int it = node; it < nit; it += NP) {
+                const int hs = it / NF, pt = it - hs * NF;
+                R a[4], b[4], nS[3];
+                if (kind == WALL) {
+                    s_fl[le][pt] = 0;
+                    continue;
+                }
+                if (kind == COARSE) {
+                    const int fn = g.hang[nbr * 4 + hs];
+                    for (int t = 0; t < 4; ++t) {
+                        a[t] = sub_interp<N>(&s_own[le][t][0], T, hs, pt);
+                        b[t] = face_value<N>(src(t) + (size_t)fn * NP, T.f[1 - s], d, pt);
+                    }
+                    area<N>(g, T, fn, f ^ 1, pt, nS);
+                    for (int c = 0; c < 3; ++c) nS[c] = -nS[c];
+                } else {
+                    for (int t = 0; t < 4; ++t) {
+                        a[t] = s_own[le][t][pt];
+                        b[t] = kind == CONF ? s_nb[le][t][pt] : sub_interp<N>(&s_nb[le][t][0], T, aux & 3, pt);
+                    }
+                    area<N>(g, T, e, f, pt, nS);
+                }
+                const R dS = sqrt(nS[0] * nS[0] + nS[1] * nS[1] + nS[2] * nS[2]);
+                const R unA = (a[0] * nS[0] + a[1] * nS[1] + a[2] * nS[2]) / dS;
+                const R unB = (b[0] * nS[0] + b[1] * nS[1] + b[2] * nS[2]) / dS;
+                const R lam = fmax(fabs(unA), fabs(unB));
+                const R v = 0.5 * lam * (a[3] - b[3]) / gm1 * dS;
+                if (kind == COARSE) s_sub[le][hs][pt] = v;
+                else s_fl[le][pt] = v;
+            }
+        }
+        __syncthreads();
+        if (act && kind == COARSE && node < NF) {
+            R v = 0;
+            for (int h = 0; h < 4; ++h) v += sub_interp_T<N>(&s_sub[le][h][0], T, h, node);
+            s_fl[le][node] = v;
+        }
+        __syncthreads();
+        if (act) {
+            int m, pt;
+            split_node<N>(d, node, m, pt);
+            acc += T.f[s][m] * s_fl[le][pt];
+        }
+        __syncthreads();
+    }
+    if (!act) return;
+    const R wj = g.WJ[e * NP + node];
+    const R r = rho[e * NP + node];
+    const R u0 = s_q[le][0][node], u1 = s_q[le][1][node], u2 = s_q[le][2][node];
+    R res = G0h[e * NP + node] - sk.c_dt * acc / wj - r * 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+    if (sk.scheme == 1) res -= sk.c_dt * sk.g * r * u2;
+    Gp[e * NP + node] = res;
+}
+
+// ------------------------------------------------------------ launchers
+template <typename R, int N>
+static void explicit_n(const DevMesh& m, const HostTab& t, const PhysK& ph, const R* q, R* fNS, R* fS,
+                       hipStream_t st) {
+    const int64_t nb = (m.E + epb_of(N) - 1) / epb_of(N);
+    hipLaunchKernelGGL((k_explicit<N, R>), dim3((unsigned)nb), dim3(threads_of(N)), 0, st, q, fNS, fS, geom<R>(m),
+                       to_tab<N, R>(t), ph, m.sponge);
+}
+
+template <typename R>
+void launch_explicit(const DevMesh& m, const HostTab& t, const PhysK& ph, const R* q, R* fNS, R* fS,
+                     hipStream_t st) {
+    switch (m.n) {
+        case 2: explicit_n<R, 2>(m, t, ph, q, fNS, fS, st); break;
+        case 3: explicit_n<R, 3>(m, t, ph, q, fNS, fS, st); break;
+        case 4: explicit_n<R, 4>(m, t, ph, q, fNS, fS, st); break;
+        case 5: explicit_n<R, 5>(m, t, ph, q, fNS, fS, st); break;
+    }
+}
+template void launch_explicit<double>(const DevMesh&, const HostTab&, const PhysK&, const double*, double*,
+                                      double*, hipStream_t);
+
+template <typename R, int N>
+static void pass1_n(const DevMesh& m, const HostTab& t, const StageK& sk, const R* p, const R* pscale,
+                    const R* Fh, const R* rho, const R* pk, const R* uk, R* w, R* FB, R* FBh, hipStream_t st) {
+    const int64_t nb = (m.E + epb_of(N) - 1) / epb_of(N);
+    hipLaunchKernelGGL((k_pass1<N, R>), dim3((unsigned)nb), dim3(threads_of(N)), 0, st, p, pscale, Fh, rho, pk, uk,
+                       w, FB, FBh, geom<R>(m), to_tab<N, R>(t), sk);
+}
+template <typename R>
+void launch_pass1(const DevMesh& m, const HostTab& t, const StageK& sk, const R* p, const R* pscale,
+                  const R* Fh, const R* rho, const R* pk, const R* uk, R* w, R* FB, R* FBh, hipStream_t st) {
+    switch (m.n) {
+        case 2: pass1_n<R, 2>(m, t, sk, p, pscale, Fh, rho, pk, uk, w, FB, FBh, st); break;
+        case 3: pass1_n<R, 3>(m, t, sk, p, pscale, Fh, rho, pk, uk, w, FB, FBh, st); break;
+        case 4: pass1_n<R, 4>(m, t, sk, p, pscale, Fh, rho, pk, uk, w, FB, FBh, st); break;
+        case 5: pass1_n<R, 5>(m, t, sk, p, pscale, Fh, rho, pk, uk, w, FB, FBh, st); break;
+    }
+}
+template void launch_pass1<double>(const DevMesh&, const HostTab&, const StageK&, const double*, const double*,
+                                   const double*, const double*, const double*, const double*, double*, double*,
+                                   double*, hipStream_t);
+template void launch_pass1<float>(const DevMesh&, const HostTab&, const StageK&, const float*, const float*,
+                                  const float*, const float*, const float*, const float*, float*, float*, float*,
+                                  hipStream_t);
+
+template <typename R, int N>
+static void pass2_n(const DevMesh& m, const HostTab& t, const StageK& sk, const R* Gp, const R* p,
+                    const R* pscale, const R* w, const R* pk, const R* rho, const R* FB, const R* FBh, R* out,
+                    double alpha, int dual, hipStream_t st) {
+    const int64_t nb = (m.E + epb_of(N) - 1) / epb_of(N);
+    hipLaunchKernelGGL((k_pass2<N, R>), dim3((unsigned)nb), dim3(threads_of(N)), 0, st, Gp, p, pscale, w, pk, rho,
+                       FB, FBh, out, (R)alpha, dual, geom<R>(m), to_tab<N, R>(t), sk);
+}
+template <typename R>
+void launch_pass2(const DevMesh& m, const HostTab& t, const StageK& sk, const R* Gp, const R* p,
+                  const R* pscale, const R* w, const R* pk, const R* rho, const R* FB, const R* FBh, R* out,
+                  double alpha, int dual, hipStream_t st) {
+    switch (m.n) {
+        case 2: pass2_n<R, 2>(m, t, sk, Gp, p, pscale, w, pk, rho, FB, FBh, out, alpha, dual, st); break;
+        case 3: pass2_n<R, 3>(m, t, sk, Gp, p, pscale, w, pk, rho, FB, FBh, out, alpha, dual, st); break;
+        case 4: pass2_n<R, 4>(m, t, sk, Gp, p, pscale, w, pk, rho, FB, FBh, out, alpha, dual, st); break;
+        case 5: pass2_n<R, 5>(m, t, sk, Gp, p, pscale, w, pk, rho, FB, FBh, out, alpha, dual, st); break;
+    }
+}
+template void launch_pass2<double>(const DevMesh&, const HostTab&, const StageK&, const double*, const double*,
+                                   const double*, const double*, const double*, const double*, const double*,
+                                   const double*, double*, double, int, hipStream_t);
+template void launch_pass2<float>(const DevMesh&, const HostTab&, const StageK&, const float*, const float*,
+                                  const float*, const float*, const float*, const float*, const float*,
+                                  const float*, float*, double, int, hipStream_t);
+
+template <int N>
+static void lambda_n(const DevMesh& m, const HostTab& t, const StageK& sk, const double* pk, const double* uk,
+                     const double* rho, const double* G0h, double* Gp, hipStream_t st) {
+    const int64_t nb = (m.E + epb_of(N) - 1) / epb_of(N);
+    hipLaunchKernelGGL((k_lambda<N>), dim3((unsigned)nb), dim3(threads_of(N)), 0, st, pk, uk, rho, G0h, Gp,
+                       geom<double>(m), to_tab<N, double>(t), sk);
+}
+void launch_lambda(const DevMesh& m, const HostTab& t, const StageK& sk, const double* pk, const double* uk,
+                   const double* rho, const double* G0h, double* Gp, hipStream_t st) {
+    switch (m.n) {
+        case 2: lambda_n<2>(m, t, sk, pk, uk, rho, G0h, Gp, st); break;
+        case 3: lambda_n<3>(m, t, sk, pk, uk, rho, G0h, Gp, st); break;
+        case 4: lambda_n<4>(m, t, sk, pk, uk, rho, G0h, Gp, st); break;
+        case 5: lambda_n<5>(m, t, sk, pk, uk, rho, G0h, Gp, st); break;
+    }
+}
+
+}  // namespace imx

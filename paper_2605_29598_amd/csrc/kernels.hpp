@@ -1,0 +1,121 @@
+// Device data views and kernel launchers of the IMEX-DG hot path.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace imx {
+
+// Geometry and connectivity on the device, in binary64 and (for the mixed
+// precision inner loop) binary32 shadows.
+struct DevMesh {
+    int64_t E = 0, nh = 0;
+    int n = 0, Np = 0, Nf = 0;
+    int deformed = 0;
+    const int* kind = nullptr;      // [E*6]
+    const int* nbr = nullptr;       // [E*6]
+    const int* aux = nullptr;       // [E*6]
+    const int* hang = nullptr;      // [nh*4]
+    const double* h = nullptr;      // [E*3]
+    const double* WJ = nullptr;     // [E*Np]
+    const double* G = nullptr;      // [9][E][Np]
+    const double* nS = nullptr;     // [E][6][3][Nf]
+    const double* sponge = nullptr; // [E*Np] or null
+    const float* WJf = nullptr;
+    const float* Gf = nullptr;
+    const float* nSf = nullptr;
+};
+
+struct PhysK {
+    double gamma, g, f;
+    double su[3];
+    int sponge;
+};
+
+struct StageK {
+    double c_dt;    // a_ll * dt
+    double beta;    // a_ll * dt * f
+    double gamma, g;
+    int scheme;     // 1: R1, 2: R2
+};
+
+// Tables of the 1D basis (host copy, converted per launch).
+struct HostTab {
+    int n;
+    double D[64], f[16], H[2 * 64], w[8];
+};
+HostTab make_tab(const Basis1D& b);
+
+// --- element kernels (templated on the floating type R = double / float)
+template <typename R>
+void launch_explicit(const DevMesh& m, const HostTab& t, const PhysK& ph, const R* q, R* fNS, R* fS,
+                     hipStream_t st);
+
+// w = P(Fh/rho - M^{-1}B(sc*p)/rho [+R1 lag]); writes w [3] and the face flux
+// buffers FB [E*6*Nf], FBh [nh*4*Nf] used by pass 2.
+template <typename R>
+void launch_pass1(const DevMesh& m, const HostTab& t, const StageK& sk, const R* p, const R* pscale,
+                  const R* Fh, const R* rho, const R* pk, const R* uk, R* w, R* FB, R* FBh,
+                  hipStream_t st);
+
+// out = alpha * (Gp - sc*p/(gamma-1) - M^{-1}C^k w - [R2] c g rho w_z) [* WJ if dual]
+template <typename R>
+void launch_pass2(const DevMesh& m, const HostTab& t, const StageK& sk, const R* Gp, const R* p,
+                  const R* pscale, const R* w, const R* pk, const R* rho, const R* FB, const R* FBh,
+                  R* out, double alpha, int dual, hipStream_t st);
+
+// Gp = G0h - M^{-1}Lambda^k - rho kappa^k [R1: - c g rho uk_z]
+void launch_lambda(const DevMesh& m, const HostTab& t, const StageK& sk, const double* pk, const double* uk,
+                   const double* rho, const double* G0h, double* Gp, hipStream_t st);
+
+// --- streaming kernels (binary64 state arithmetic)
+struct StageCoef {
+    double a[3], at[3];   // a_lm, a~_lm for m < l
+    int l;                // number of previous stages
+    double dt, c_dt, g, gamma;
+};
+void launch_stage_prepare(int64_t L, const double* y, const double* const* fNS, const double* const* fS,
+                          const double* yprev, const StageCoef& c, double* rho, double* Fh, double* G0h,
+                          double* p0, double* u0, hipStream_t st);
+void launch_finalize(int64_t L, const double* rho, const double* p, const double* u, double gamma, double* Y,
+                     hipStream_t st);
+void launch_final_update(int64_t L, const double* y, const double* const* fNS, const double* const* fS,
+                         const double* b, double dt, double* ynew, hipStream_t st);
+void launch_scale_div(int64_t L, int nf, const double* in, const double* WJ, double* out, hipStream_t st);
+
+// --- reductions: partial sums per block then a fixed-order final sum
+constexpr int RED_BLOCKS = 1024;
+constexpr int MAXV = 33;   // restart length <= 32
+// out[i] = sum WJ * V_i * z  (i < nv), V_i = V + i*ldv, all length L (R = double or float)
+template <typename R>
+void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R* WJ, double* partial,
+                 double* out, hipStream_t st);
+// z1 = z - sum_i c_i V_i with c_i = raw[i]*s[i]^2 ; then out[i] = sum WJ V_i z1 (if dots) or
+// out[0] = sum WJ z1^2 (norm)
+template <typename R>
+void launch_axpy_reduce(int64_t L, int nv, const R* V, int64_t ldv, const double* raw, const double* s,
+                        const R* z, R* z1, const R* WJ, int mode_norm, double* partial, double* out,
+                        hipStream_t st);
+// x += sum_i coef[i] V_i
+template <typename R>
+void launch_lincomb(int64_t L, int nv, const R* V, int64_t ldv, const double* coef, R* x, hipStream_t st);
+// out[0] = sum WJ a^2 ; (a may be null -> uses b) generic weighted dot of two vectors
+void launch_wdot(int64_t L, const double* a, const double* b, const double* WJ, double* partial, double* out,
+                 hipStream_t st);
+// Picard variation: out[0] = sum WJ (dp^2 + gamma p rho |du|^2), out[1] = sum WJ p^2
+void launch_picard_var(int64_t L, const double* p0, const double* u0, const double* p1, const double* u1,
+                       const double* rho, const double* WJ, double gamma, double* partial, double* out,
+                       hipStream_t st);
+// sum WJ rho (out[0]) and a non-finite flag over the state (out[1] = count)
+void launch_mass(int64_t L, const double* q, const double* WJ, double* partial, double* out, hipStream_t st);
+
+// conversions / vector helpers
+void launch_d2f(int64_t L, const double* in, float* out, hipStream_t st);
+void launch_f2d_add(int64_t L, const float* in, const double* scale, double* x, hipStream_t st);
+void launch_axpby(int64_t L, double a, const double* x, double b, const double* y, double* out, hipStream_t st);
+void launch_scale_store(int64_t L, const double* in, const double* s_ptr, int invert_sqrt, double* out,
+                        hipStream_t st);
+void launch_scale_store_f(int64_t L, const double* in, const double* s_ptr, float* out, hipStream_t st);
+
+}  // namespace imx

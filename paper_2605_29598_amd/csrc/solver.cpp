@@ -1,0 +1,699 @@
+// Host runtime of the IMEX-DG library: solver objects over a caller-owned
+// device workspace, the GMRES and Picard drivers of the implicit stages, the
+// IMEX-ARK2 step (Sec. 3) and the C-ABI entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace imx {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+#define HIPCHK(call)                                                        \
+    do {                                                                    \
+        hipError_t e_ = (call);                                             \
+        if (e_ != hipSuccess) {                                             \
+            set_error(std::string(#call) + ": " + hipGetErrorString(e_));   \
+            return IMX_EHIP;                                                \
+        }                                                                   \
+    } while (0)
+
+#define CHK(call)                         \
+    do {                                  \
+        imx_status s_ = (call);           \
+        if (s_ != IMX_OK) return s_;      \
+    } while (0)
+
+// Butcher tableaux of Sec. 3 (explicit / implicit), chi = 2 - sqrt(2), a32 = 1/2.
+struct Tableau {
+    double a[3][3], at[3][3], b[3];
+    Tableau() {
+        const double chi = 2.0 - std::sqrt(2.0);
+        std::memset(this, 0, sizeof(*this));
+        a[1][0] = chi;
+        a[2][0] = 0.5;
+        a[2][1] = 0.5;
+        at[1][0] = at[1][1] = chi / 2;
+        at[2][0] = at[2][1] = 0.5 - chi / 4;
+        at[2][2] = chi / 2;
+        b[0] = b[1] = 0.5 - chi / 4;
+        b[2] = chi / 2;
+    }
+};
+static const Tableau TAB;
+
+}  // namespace imx
+
+using namespace imx;
+
+struct imx_solver {
+    const Mesh* mesh = nullptr;
+    imx_phys phys{};
+    imx_numerics num{};
+    hipStream_t st = nullptr;
+    int device = 0;
+    int64_t E = 0, L = 0;
+    int Np = 0, Nf = 0, m = 30;
+    bool bound = false, mixed = false;
+    size_t ws_bytes = 0;
+    char* ws = nullptr;
+    DevMesh dm;
+    HostTab tab{};
+    // binary64 buffers
+    double *y = nullptr, *ybak = nullptr, *Y = nullptr;
+    double *fN[3] = {}, *fS[3] = {};
+    double *rho = nullptr, *Fh = nullptr, *G0h = nullptr, *Gp = nullptr;
+    double *p = nullptr, *pn = nullptr, *u = nullptr, *un = nullptr, *w = nullptr;
+    double *FB = nullptr, *FBh = nullptr;
+    double *V = nullptr, *z = nullptr, *z1 = nullptr, *b = nullptr;
+    double *partial = nullptr, *dsc = nullptr;   // device scalars
+    // binary32 shadows for the mixed inner loop
+    float *Vf = nullptr, *zf = nullptr, *z1f = nullptr, *wf = nullptr, *FBf = nullptr, *FBhf = nullptr;
+    float *rhof = nullptr, *pkf = nullptr, *WJf = nullptr, *Gf = nullptr, *nSf = nullptr, *xf = nullptr;
+    // pinned host scalars
+    double* hsc = nullptr;
+    // device scalar slots (offsets into dsc)
+    enum { S_RAW1 = 0, S_RAW2 = 64, S_NRM = 128, S_SV = 192, S_COEF = 256, S_MISC = 320, S_N = 384 };
+};
+
+namespace imx {
+
+struct Layout {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+};
+
+// Computes (and with base != null, assigns) the workspace layout.
+static size_t layout(imx_solver* s, char* base) {
+    Layout Lo;
+    const int64_t L = s->L, E = s->E;
+    const int Np = s->Np, Nf = s->Nf;
+    const Mesh& m = *s->mesh;
+    auto D = [&](size_t n) -> double* { size_t o = Lo.take(n * sizeof(double)); return base ? (double*)(base + o) : nullptr; };
+    auto F = [&](size_t n) -> float* { size_t o = Lo.take(n * sizeof(float)); return base ? (float*)(base + o) : nullptr; };
+    auto I = [&](size_t n) -> int* { size_t o = Lo.take(n * sizeof(int)); return base ? (int*)(base + o) : nullptr; };
+    DevMesh& dm = s->dm;
+    dm.kind = I(E * 6);
+    dm.nbr = I(E * 6);
+    dm.aux = I(E * 6);
+    dm.hang = I(std::max<int64_t>(m.nh, 1) * 4);
+    dm.h = D(E * 3);
+    dm.WJ = D(L);
+    if (m.deformed) {
+        dm.G = D(9 * L);
+        dm.nS = D((size_t)E * 6 * 3 * Nf);
+    }
+    if (s->phys.sponge_lambda != 0.0) dm.sponge = D(L);
+    s->y = D(5 * L);
+    s->ybak = D(5 * L);
+    s->Y = D(5 * L);
+    for (int l = 0; l < 3; ++l) {
+        s->fN[l] = D(5 * L);
+        s->fS[l] = D(4 * L);
+    }
+    s->rho = D(L);
+    s->Fh = D(3 * L);
+    s->G0h = D(L);
+    s->Gp = D(L);
+    s->p = D(L);
+    s->pn = D(L);
+    s->u = D(3 * L);
+    s->un = D(3 * L);
+    s->w = D(3 * L);
+    s->FB = D((size_t)E * 6 * Nf);
+    s->FBh = D(std::max<int64_t>(m.nh, 1) * 4 * Nf);
+    s->V = D((size_t)(s->m + 1) * L);
+    s->z = D(L);
+    s->z1 = D(L);
+    s->b = D(L);
+    s->partial = D((size_t)RED_BLOCKS * MAXV);
+    s->dsc = D(imx_solver::S_N);
+    if (s->mixed) {
+        s->Vf = F((size_t)(s->m + 1) * L);
+        s->zf = F(L);
+        s->z1f = F(L);
+        s->wf = F(3 * L);
+        s->FBf = F((size_t)E * 6 * Nf);
+        s->FBhf = F(std::max<int64_t>(m.nh, 1) * 4 * Nf);
+        s->rhof = F(L);
+        s->pkf = F(L);
+        s->xf = F(L);
+        s->WJf = F(L);
+        dm.WJf = s->WJf;
+        if (m.deformed) {
+            s->Gf = F(9 * L);
+            s->nSf = F((size_t)E * 6 * 3 * Nf);
+            dm.Gf = s->Gf;
+            dm.nSf = s->nSf;
+        }
+    }
+    return Lo.off;
+}
+
+static imx_status validate_num(const imx_numerics& n) {
+    if (!(n.dt > 0) || (n.scheme != IMX_R1 && n.scheme != IMX_R2) ||
+        (n.precision != IMX_FP64 && n.precision != IMX_MIXED) || n.picard_max < 1 || n.gmres_max < 1 ||
+        n.gmres_restart < 1 || n.gmres_restart > MAXV - 1 || !(n.gmres_tol >= 0) || !(n.picard_tol >= 0)) {
+        set_error("invalid numerics (dt > 0, scheme R1/R2, 1 <= gmres_restart <= 32, positive caps)");
+        return IMX_EINVAL;
+    }
+    if (n.precision == IMX_MIXED) {
+        set_error("IMX_MIXED is not available in this build");
+        return IMX_EINVAL;
+    }
+    return IMX_OK;
+}
+
+static StageK stage_k(const imx_solver* s, double a_ll) {
+    StageK k;
+    k.c_dt = a_ll * s->num.dt;
+    k.beta = a_ll * s->num.dt * s->phys.f;
+    k.gamma = s->phys.gamma;
+    k.g = s->phys.g;
+    k.scheme = s->num.scheme;
+    return k;
+}
+
+static imx_status sync_read(imx_solver* s, const double* dev, int n) {
+    HIPCHK(hipMemcpyAsync(s->hsc, dev, n * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return IMX_OK;
+}
+
+static imx_status put_scalars(imx_solver* s, double* dev, const double* vals, int n, int slot) {
+    // each slot of the pinned buffer is written once before its copy is queued
+    double* h = s->hsc + 512 + slot;
+    std::memcpy(h, vals, n * sizeof(double));
+    HIPCHK(hipMemcpyAsync(dev, h, n * sizeof(double), hipMemcpyHostToDevice, s->st));
+    return IMX_OK;
+}
+
+// ------------------------------------------------------------ stage context
+struct StageCtx {
+    StageK k;
+    const double* Fh;   // primal momentum right-hand side (M^{-1}(f - f_g))
+    const double* Gp;   // primal energy right-hand side (M^{-1}(g - Lambda - k ...))
+    const double* pk;   // lagged pressure
+    const double* uk;   // lagged velocity (R1)
+    const double* rho;
+};
+
+// r = M^{-1}(RHS - S x) with x scaled by *xs (device) if xs != null
+static void residual(imx_solver* s, const StageCtx& c, const double* x, const double* xs, double* out) {
+    launch_pass1<double>(s->dm, s->tab, c.k, x, xs, c.Fh, c.rho, c.pk, c.uk, s->w, s->FB, s->FBh, s->st);
+    launch_pass2<double>(s->dm, s->tab, c.k, c.Gp, x, xs, s->w, c.pk, c.rho, s->FB, s->FBh, out, 1.0, 0, s->st);
+}
+
+// z = M^{-1} S (xs * x)
+static void matvec(imx_solver* s, const StageCtx& c, const double* x, const double* xs, double* out) {
+    launch_pass1<double>(s->dm, s->tab, c.k, x, xs, nullptr, c.rho, c.pk, c.uk, s->w, s->FB, s->FBh, s->st);
+    launch_pass2<double>(s->dm, s->tab, c.k, nullptr, x, xs, s->w, c.pk, c.rho, s->FB, s->FBh, out, -1.0, 0, s->st);
+}
+
+
+struct GmresOut {
+    int its = 0;
+    double relres = 0.0;
+};
+
+// Restarted GMRES(m) for A x = b, A = M^{-1} S, in the M inner product, with
+// classical Gram-Schmidt applied twice and Givens rotations on the host
+// (Saad, Alg. 6.9). x: initial guess in, solution out. Stops when the
+// Givens residual estimate reaches tol*|b| (unless `fixed`), after maxit
+// products, or on breakdown; the final residual is recomputed.
+static imx_status gmres(imx_solver* s, const StageCtx& c, double* x, double bnorm, double tol, int maxit,
+                        bool fixed, GmresOut& out) {
+    const int64_t L = s->L;
+    const int m = s->m;
+    double* V = s->V;
+    double* raw1 = s->dsc + imx_solver::S_RAW1;
+    double* raw2 = s->dsc + imx_solver::S_RAW2;
+    double* nrm = s->dsc + imx_solver::S_NRM;
+    double* sv = s->dsc + imx_solver::S_SV;
+    double* coef = s->dsc + imx_solver::S_COEF;
+    double* bb = s->dsc + imx_solver::S_MISC;
+    std::vector<double> H((m + 1) * m), g(m + 1), cs(m), sn(m), svh(m + 1), yv(m), cf(m);
+    residual(s, c, x, nullptr, V);
+    launch_wdot(L, V, nullptr, s->dm.WJ, s->partial, bb, s->st);
+    CHK(sync_read(s, bb, 1));
+    double beta = std::sqrt(s->hsc[0]);
+    int its = 0;
+    while (true) {
+        if (!std::isfinite(beta)) {
+            set_error("GMRES: non-finite residual");
+            return IMX_ENONFINITE;
+        }
+        if (beta == 0.0 || its >= maxit || (!fixed && beta <= tol * bnorm)) break;
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        svh[0] = 1.0 / beta;
+        CHK(put_scalars(s, sv, &svh[0], 1, 0));
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            matvec(s, c, V + (size_t)j * L, sv + j, s->z);
+            ++its;
+            launch_dots<double>(L, j + 1, V, L, s->z, s->dm.WJ, s->partial, raw1, s->st);
+            launch_axpy_reduce<double>(L, j + 1, V, L, raw1, sv, s->z, s->z1, s->dm.WJ, 0, s->partial, raw2, s->st);
+            launch_axpy_reduce<double>(L, j + 1, V, L, raw2, sv, s->z1, V + (size_t)(j + 1) * L, s->dm.WJ, 1,
+                                       s->partial, nrm, s->st);
+            HIPCHK(hipMemcpyAsync(s->hsc, raw1, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s->st));
+            HIPCHK(hipMemcpyAsync(s->hsc + 64, raw2, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s->st));
+            HIPCHK(hipMemcpyAsync(s->hsc + 128, nrm, sizeof(double), hipMemcpyDeviceToHost, s->st));
+            HIPCHK(hipStreamSynchronize(s->st));
+            for (int i = 0; i <= j; ++i) H[i * m + j] = svh[i] * (s->hsc[i] + s->hsc[64 + i]);
+            const double hnext = std::sqrt(s->hsc[128]);
+            H[(j + 1) * m + j] = hnext;
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = t;
+            }
+            const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+            cs[j] = H[j * m + j] / den;
+            sn[j] = H[(j + 1) * m + j] / den;
+            H[j * m + j] = den;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            if (!std::isfinite(hnext)) {
+                set_error("GMRES: non-finite Krylov vector");
+                return IMX_ENONFINITE;
+            }
+            if (hnext == 0.0 || its >= maxit || (!fixed && std::fabs(g[j + 1]) <= tol * bnorm)) break;
+            svh[j + 1] = 1.0 / hnext;
+            CHK(put_scalars(s, sv + j + 1, &svh[j + 1], 1, j + 1));
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int l = i + 1; l < k; ++l) t -= H[i * m + l] * yv[l];
+            yv[i] = t / H[i * m + i];
+        }
+        for (int i = 0; i < k; ++i) cf[i] = yv[i] * svh[i];
+        CHK(put_scalars(s, coef, cf.data(), k, 100));
+        launch_lincomb<double>(L, k, V, L, coef, x, s->st);
+        residual(s, c, x, nullptr, V);
+        launch_wdot(L, V, nullptr, s->dm.WJ, s->partial, bb, s->st);
+        CHK(sync_read(s, bb, 1));
+        beta = std::sqrt(s->hsc[0]);
+    }
+    out.its = its;
+    out.relres = bnorm > 0 ? beta / bnorm : 0.0;
+    return IMX_OK;
+}
+
+// Solves the pressure system of the current stage context for x (initial
+// guess in, solution out) to gmres_tol.
+static imx_status pressure_solve(imx_solver* s, const StageCtx& c, double* x, GmresOut& out) {
+    const int64_t L = s->L;
+    double* bb = s->dsc + imx_solver::S_MISC;
+    // |b|_M with b = M^{-1} RHS: the residual at x = 0
+    residual(s, c, nullptr, nullptr, s->b);
+    launch_wdot(L, s->b, nullptr, s->dm.WJ, s->partial, bb, s->st);
+    CHK(sync_read(s, bb, 1));
+    const double bnorm = std::sqrt(s->hsc[0]);
+    return gmres(s, c, x, bnorm, s->num.gmres_tol, s->num.gmres_max, s->num.fixed_iterations != 0, out);
+}
+
+// Picard iteration on the stage system; p, u: initial iterate in, result out.
+static imx_status stage_solve(imx_solver* s, double a_ll, const double* rho, const double* Fh, const double* G0h,
+                              double*& p, double*& u, double*& pn, double*& un, imx_solve_stats* st) {
+    const int64_t L = s->L;
+    const bool fixed = s->num.fixed_iterations != 0;
+    StageK k = stage_k(s, a_ll);
+    imx_solve_stats stats{};
+    bool converged = false;
+    double* bb = s->dsc + imx_solver::S_MISC;
+    for (int it = 0; it < s->num.picard_max; ++it) {
+        launch_lambda(s->dm, s->tab, k, p, u, rho, G0h, s->Gp, s->st);
+        StageCtx c{k, Fh, s->Gp, p, u, rho};
+        HIPCHK(hipMemcpyAsync(pn, p, L * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+        GmresOut go;
+        CHK(pressure_solve(s, c, pn, go));
+        // velocity recovery from the momentum equation
+        launch_pass1<double>(s->dm, s->tab, k, pn, nullptr, Fh, rho, p, u, un, nullptr, nullptr, s->st);
+        launch_picard_var(L, p, u, pn, un, rho, s->dm.WJ, s->phys.gamma, s->partial, bb, s->st);
+        CHK(sync_read(s, bb, 2));
+        const double var = std::sqrt(s->hsc[0] / s->hsc[1]);
+        std::swap(p, pn);
+        std::swap(u, un);
+        stats.picard_iters++;
+        stats.gmres_iters += go.its;
+        stats.gmres_relres = go.relres;
+        stats.picard_variation = var;
+        if (!std::isfinite(var)) {
+            if (st) *st = stats;
+            set_error("Picard: non-finite iterate");
+            return IMX_ENONFINITE;
+        }
+        if (!fixed && var <= s->num.picard_tol) {
+            converged = true;
+            break;
+        }
+    }
+    if (st) *st = stats;
+    if (!fixed && !converged) {
+        set_error("Picard iteration did not converge within picard_max");
+        return IMX_ENOCONV;
+    }
+    return IMX_OK;
+}
+
+static PhysK phys_k(const imx_solver* s) {
+    PhysK k;
+    k.gamma = s->phys.gamma;
+    k.g = s->phys.g;
+    k.f = s->phys.f;
+    for (int c = 0; c < 3; ++c) k.su[c] = s->phys.sponge_u[c];
+    k.sponge = s->phys.sponge_lambda != 0.0;
+    return k;
+}
+
+static imx_status one_step(imx_solver* s, imx_step_stats* acc) {
+    const int64_t L = s->L;
+    const double dt = s->num.dt;
+    const PhysK ph = phys_k(s);
+    HIPCHK(hipMemcpyAsync(s->ybak, s->y, 5 * L * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+    launch_explicit<double>(s->dm, s->tab, ph, s->y, s->fN[0], s->fS[0], s->st);
+    for (int l = 1; l <= 2; ++l) {
+        StageCoef c{};
+        for (int mm = 0; mm < l; ++mm) {
+            c.a[mm] = TAB.a[l][mm];
+            c.at[mm] = TAB.at[l][mm];
+        }
+        c.l = l;
+        c.dt = dt;
+        c.c_dt = TAB.at[l][l] * dt;
+        c.g = s->phys.g;
+        c.gamma = s->phys.gamma;
+        const double* yprev = l == 1 ? s->y : s->Y;
+        launch_stage_prepare(L, s->y, s->fN, s->fS, yprev, c, s->rho, s->Fh, s->G0h, s->p, s->u, s->st);
+        imx_solve_stats ss{};
+        imx_status rc = stage_solve(s, TAB.at[l][l], s->rho, s->Fh, s->G0h, s->p, s->u, s->pn, s->un, &ss);
+        acc->picard_iters += ss.picard_iters;
+        acc->gmres_iters += ss.gmres_iters;
+        if (rc != IMX_OK) {
+            (void)hipMemcpyAsync(s->y, s->ybak, 5 * L * sizeof(double), hipMemcpyDeviceToDevice, s->st);
+            return rc;
+        }
+        launch_finalize(L, s->rho, s->p, s->u, s->phys.gamma, s->Y, s->st);
+        launch_explicit<double>(s->dm, s->tab, ph, s->Y, s->fN[l], s->fS[l], s->st);
+    }
+    launch_final_update(L, s->y, s->fN, s->fS, TAB.b, dt, s->y, s->st);
+    double* bb = s->dsc + imx_solver::S_MISC;
+    launch_mass(L, s->y, s->dm.WJ, s->partial, bb, s->st);
+    CHK(sync_read(s, bb, 2));
+    if (s->hsc[1] != 0.0 || !std::isfinite(s->hsc[0])) {
+        HIPCHK(hipMemcpyAsync(s->y, s->ybak, 5 * L * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
+        set_error("non-finite state after step");
+        return IMX_ENONFINITE;
+    }
+    acc->mass = s->hsc[0];
+    acc->steps++;
+    return IMX_OK;
+}
+
+}  // namespace imx
+
+// =================================================================== C-ABI
+extern "C" {
+
+const char* imx_last_error(void) { return imx::g_err.c_str(); }
+
+imx_status imx_mesh_create(const imx_mesh_desc* desc, imx_mesh** out) {
+    if (!desc || !out) {
+        set_error("imx_mesh_create: null argument");
+        return IMX_EINVAL;
+    }
+    imx_mesh* m = new (std::nothrow) imx_mesh;
+    if (!m) return IMX_ENOMEM;
+    try {
+        imx_status rc = build_mesh(*desc, m->m);
+        if (rc != IMX_OK) {
+            delete m;
+            return rc;
+        }
+    } catch (const std::bad_alloc&) {
+        delete m;
+        set_error("imx_mesh_create: out of host memory");
+        return IMX_ENOMEM;
+    }
+    *out = m;
+    return IMX_OK;
+}
+
+imx_status imx_mesh_info(const imx_mesh* mesh, int64_t* n_elem, int* nodes_per_elem, int64_t* n_hanging,
+                         int* deformed) {
+    if (!mesh) return IMX_EINVAL;
+    if (n_elem) *n_elem = mesh->m.E;
+    if (nodes_per_elem) *nodes_per_elem = mesh->m.Np;
+    if (n_hanging) *n_hanging = mesh->m.nh;
+    if (deformed) *deformed = mesh->m.deformed ? 1 : 0;
+    return IMX_OK;
+}
+
+imx_status imx_mesh_node_coords(const imx_mesh* mesh, double* xyz) {
+    if (!mesh || !xyz) return IMX_EINVAL;
+    std::memcpy(xyz, mesh->m.xyz.data(), mesh->m.xyz.size() * sizeof(double));
+    return IMX_OK;
+}
+
+imx_status imx_mesh_mass_diag(const imx_mesh* mesh, double* mh) {
+    if (!mesh || !mh) return IMX_EINVAL;
+    std::memcpy(mh, mesh->m.WJ.data(), mesh->m.WJ.size() * sizeof(double));
+    return IMX_OK;
+}
+
+void imx_mesh_destroy(imx_mesh* mesh) { delete mesh; }
+
+imx_status imx_solver_create(const imx_mesh* mesh, const imx_phys* phys, const imx_numerics* num, void* stream,
+                             imx_solver** out) {
+    if (!mesh || !phys || !num || !out) {
+        set_error("imx_solver_create: null argument");
+        return IMX_EINVAL;
+    }
+    CHK(validate_num(*num));
+    imx_solver* s = new (std::nothrow) imx_solver;
+    if (!s) return IMX_ENOMEM;
+    s->mesh = &mesh->m;
+    s->phys = *phys;
+    s->num = *num;
+    s->st = (hipStream_t)stream;
+    hipGetDevice(&s->device);
+    s->E = mesh->m.E;
+    s->Np = mesh->m.Np;
+    s->Nf = mesh->m.Nf;
+    s->L = s->E * s->Np;
+    s->m = num->gmres_restart;
+    s->mixed = num->precision == IMX_MIXED;
+    s->dm.E = s->E;
+    s->dm.nh = mesh->m.nh;
+    s->dm.n = mesh->m.n;
+    s->dm.Np = s->Np;
+    s->dm.Nf = s->Nf;
+    s->dm.deformed = mesh->m.deformed;
+    s->tab = make_tab(mesh->m.basis);
+    s->ws_bytes = layout(s, nullptr);
+    if (hipHostMalloc((void**)&s->hsc, 1024 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        delete s;
+        set_error("imx_solver_create: pinned host buffer");
+        return IMX_ENOMEM;
+    }
+    *out = s;
+    return IMX_OK;
+}
+
+imx_status imx_solver_workspace_bytes(const imx_solver* s, size_t* bytes) {
+    if (!s || !bytes) return IMX_EINVAL;
+    *bytes = s->ws_bytes;
+    return IMX_OK;
+}
+
+imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
+    if (!s || !dev) return IMX_EINVAL;
+    if (bytes < s->ws_bytes) {
+        set_error("imx_solver_bind_workspace: workspace too small");
+        return IMX_ENOMEM;
+    }
+    if (((uintptr_t)dev & 255) != 0) {
+        set_error("imx_solver_bind_workspace: workspace must be 256-byte aligned");
+        return IMX_EINVAL;
+    }
+    s->ws = (char*)dev;
+    layout(s, s->ws);
+    const Mesh& m = *s->mesh;
+    auto up = [&](const void* dst, const void* src, size_t n) -> imx_status {
+        HIPCHK(hipMemcpyAsync((void*)dst, src, n, hipMemcpyHostToDevice, s->st));
+        return IMX_OK;
+    };
+    CHK(up(s->dm.kind, m.fkind.data(), m.fkind.size() * sizeof(int)));
+    CHK(up(s->dm.nbr, m.fnbr.data(), m.fnbr.size() * sizeof(int)));
+    CHK(up(s->dm.aux, m.faux.data(), m.faux.size() * sizeof(int)));
+    if (m.nh) CHK(up(s->dm.hang, m.hang.data(), m.hang.size() * sizeof(int)));
+    CHK(up(s->dm.h, m.h.data(), m.h.size() * sizeof(double)));
+    CHK(up(s->dm.WJ, m.WJ.data(), m.WJ.size() * sizeof(double)));
+    if (m.deformed) {
+        CHK(up(s->dm.G, m.G.data(), m.G.size() * sizeof(double)));
+        CHK(up(s->dm.nS, m.nS.data(), m.nS.size() * sizeof(double)));
+    }
+    std::vector<double> spl;
+    if (s->dm.sponge) {
+        // lambda(z) of the Rayleigh sponge at every node
+        spl.resize(s->L);
+        const double zB = s->phys.sponge_zB, zT = s->phys.sponge_zT, lam = s->phys.sponge_lambda;
+        for (int64_t i = 0; i < s->L; ++i) {
+            const double zz = m.xyz[2 * s->L + i];
+            double v = 0.0;
+            if (zz >= zB) {
+                const double sn = std::sin(0.5 * M_PI * (zz - zB) / (zT - zB));
+                v = lam * sn * sn;
+            }
+            spl[i] = v;
+        }
+        CHK(up(s->dm.sponge, spl.data(), spl.size() * sizeof(double)));
+    }
+    std::vector<float> tmp;
+    if (s->mixed) {
+        tmp.assign(m.WJ.begin(), m.WJ.end());
+        CHK(up(s->WJf, tmp.data(), tmp.size() * sizeof(float)));
+        if (m.deformed) {
+            tmp.assign(m.G.begin(), m.G.end());
+            CHK(up(s->Gf, tmp.data(), tmp.size() * sizeof(float)));
+            tmp.assign(m.nS.begin(), m.nS.end());
+            CHK(up(s->nSf, tmp.data(), tmp.size() * sizeof(float)));
+        }
+    }
+    HIPCHK(hipMemsetAsync(s->dsc, 0, imx_solver::S_N * sizeof(double), s->st));
+    HIPCHK(hipStreamSynchronize(s->st));   // host staging vectors go out of scope
+    s->bound = true;
+    return IMX_OK;
+}
+
+imx_status imx_solver_set_numerics(imx_solver* s, const imx_numerics* num) {
+    if (!s || !num) return IMX_EINVAL;
+    CHK(validate_num(*num));
+    if (num->gmres_restart > s->m || (num->precision == IMX_MIXED && !s->mixed)) {
+        set_error("imx_solver_set_numerics: restart length / precision exceed the bound workspace");
+        return IMX_EINVAL;
+    }
+    s->num = *num;
+    return IMX_OK;
+}
+
+#define NEED_BOUND(s)                                      \
+    do {                                                   \
+        if (!(s)) return IMX_EINVAL;                       \
+        if (!(s)->bound) {                                 \
+            set_error("solver has no workspace bound");    \
+            return IMX_ESTATE;                             \
+        }                                                  \
+    } while (0)
+
+imx_status imx_set_state(imx_solver* s, const double* q) {
+    NEED_BOUND(s);
+    HIPCHK(hipMemcpyAsync(s->y, q, 5 * s->L * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+    return IMX_OK;
+}
+
+imx_status imx_get_state(const imx_solver* s, double* q) {
+    NEED_BOUND(s);
+    HIPCHK(hipMemcpyAsync(q, s->y, 5 * s->L * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+    return IMX_OK;
+}
+
+imx_status imx_explicit_residual(imx_solver* s, const double* q, double* fNS, double* fS) {
+    NEED_BOUND(s);
+    if (!q || !fNS || !fS) return IMX_EINVAL;
+    launch_explicit<double>(s->dm, s->tab, phys_k(s), q, fNS, fS, s->st);
+    HIPCHK(hipGetLastError());
+    return IMX_OK;
+}
+
+imx_status imx_implicit_setup(imx_solver* s, const double* rho_l, const double* p_lag, const double* u_lag) {
+    NEED_BOUND(s);
+    if (!rho_l || !p_lag || !u_lag) return IMX_EINVAL;
+    const size_t L = s->L * sizeof(double);
+    HIPCHK(hipMemcpyAsync(s->rho, rho_l, L, hipMemcpyDeviceToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(s->p, p_lag, L, hipMemcpyDeviceToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(s->u, u_lag, 3 * L, hipMemcpyDeviceToDevice, s->st));
+    return IMX_OK;
+}
+
+imx_status imx_schur_apply(imx_solver* s, const double* pin, double* out) {
+    NEED_BOUND(s);
+    if (!pin || !out) return IMX_EINVAL;
+    const double a_ll = TAB.at[1][1];
+    StageK k = stage_k(s, a_ll);
+    launch_pass1<double>(s->dm, s->tab, k, pin, nullptr, nullptr, s->rho, s->p, s->u, s->w, s->FB, s->FBh, s->st);
+    launch_pass2<double>(s->dm, s->tab, k, nullptr, pin, nullptr, s->w, s->p, s->rho, s->FB, s->FBh, out, -1.0, 1,
+                         s->st);
+    HIPCHK(hipGetLastError());
+    return IMX_OK;
+}
+
+imx_status imx_implicit_solve(imx_solver* s, const double* rho_l, const double* F, const double* G0,
+                              const double* p0, const double* u0, double* pout, double* uout,
+                              imx_solve_stats* stats) {
+    NEED_BOUND(s);
+    if (!rho_l || !F || !G0 || !p0 || !u0 || !pout || !uout) return IMX_EINVAL;
+    const int64_t L = s->L;
+    const size_t B = L * sizeof(double);
+    HIPCHK(hipMemcpyAsync(s->rho, rho_l, B, hipMemcpyDeviceToDevice, s->st));
+    launch_scale_div(L, 3, F, s->dm.WJ, s->Fh, s->st);
+    launch_scale_div(L, 1, G0, s->dm.WJ, s->G0h, s->st);
+    HIPCHK(hipMemcpyAsync(s->p, p0, B, hipMemcpyDeviceToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(s->u, u0, 3 * B, hipMemcpyDeviceToDevice, s->st));
+    imx_status rc = stage_solve(s, TAB.at[1][1], s->rho, s->Fh, s->G0h, s->p, s->u, s->pn, s->un, stats);
+    HIPCHK(hipMemcpyAsync(pout, s->p, B, hipMemcpyDeviceToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(uout, s->u, 3 * B, hipMemcpyDeviceToDevice, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return rc;
+}
+
+imx_status imx_step(imx_solver* s, int nsteps, imx_step_stats* stats) {
+    NEED_BOUND(s);
+    if (nsteps < 0) return IMX_EINVAL;
+    imx_step_stats acc{};
+    for (int i = 0; i < nsteps; ++i) {
+        imx_status rc = one_step(s, &acc);
+        if (rc != IMX_OK) {
+            if (stats) *stats = acc;
+            return rc;
+        }
+    }
+    if (stats) *stats = acc;
+    return IMX_OK;
+}
+
+imx_status imx_total_mass(imx_solver* s, double* mass) {
+    NEED_BOUND(s);
+    if (!mass) return IMX_EINVAL;
+    double* bb = s->dsc + imx_solver::S_MISC;
+    launch_mass(s->L, s->y, s->dm.WJ, s->partial, bb, s->st);
+    CHK(sync_read(s, bb, 2));
+    *mass = s->hsc[0];
+    return IMX_OK;
+}
+
+void imx_solver_destroy(imx_solver* s) {
+    if (!s) return;
+    if (s->hsc) (void)hipHostFree(s->hsc);
+    delete s;
+}
+
+}  // extern "C"

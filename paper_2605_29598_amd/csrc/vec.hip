@@ -1,0 +1,382 @@
+// Streaming kernels: stage combinations of the ARK2 scheme and the Krylov
+// vector work of GMRES (M-weighted multi-dot products, Gram-Schmidt updates,
+// norms). Reductions write one partial per workgroup and are summed by a
+// single workgroup in a fixed order, so every result is bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace imx {
+
+constexpr int TPB = 256;
+
+static unsigned grid_for(int64_t L, int64_t per_block = TPB * 4) {
+    int64_t g = (L + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    return (unsigned)g;
+}
+
+// block reduction of NV values held per thread; result in red[v] for thread 0 use
+template <int NV>
+__device__ __forceinline__ void block_sum(double* v, double* red) {
+    // wavefront (64 lanes) butterfly, then across the 4 wavefronts of the block
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+        for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int i = 0; i < NV; ++i) red[wid * NV + i] = v[i];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0;
+        for (int k = 0; k < TPB / 64; ++k) s += red[k * NV + threadIdx.x];
+        red[TPB / 64 * NV + threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// final fixed-order sum of partials[nb][nv] -> out[nv]
+__global__ void k_final_sum(const double* __restrict__ partial, int nb, int nv, double* __restrict__ out) {
+    __shared__ double red[TPB];
+    for (int v = 0; v < nv; ++v) {
+        double s = 0;
+        for (int b = threadIdx.x; b < nb; b += TPB) s += partial[(size_t)b * nv + v];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int off = TPB / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[v] = red[0];
+        __syncthreads();
+    }
+}
+
+static void final_sum(const double* partial, int nb, int nv, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(TPB), 0, st, partial, nb, nv, out);
+}
+
+// ------------------------------------------------------- multi-dot products
+template <typename R, int CH>
+__global__ void __launch_bounds__(TPB)
+k_dots(int64_t L, int nv, int v0, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z,
+       const R* __restrict__ WJ, double* __restrict__ partial, int nvtot) {
+    __shared__ double red[(TPB / 64 + 1) * CH];
+    double acc[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) acc[i] = 0;
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) {
+        const double wz = (double)WJ[x] * (double)z[x];
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            if (i < nv) acc[i] += wz * (double)V[(int64_t)(v0 + i) * ldv + x];
+    }
+    block_sum<CH>(acc, red);
+    if (threadIdx.x < nv) partial[(size_t)blockIdx.x * nvtot + v0 + threadIdx.x] = red[TPB / 64 * CH + threadIdx.x];
+}
+
+template <typename R>
+void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R* WJ, double* partial,
+                 double* out, hipStream_t st) {
+    const unsigned g = grid_for(L, TPB * 8) > RED_BLOCKS ? RED_BLOCKS : grid_for(L, TPB * 8);
+    for (int v0 = 0; v0 < nv; v0 += 16) {
+        const int c = nv - v0 < 16 ? nv - v0 : 16;
+        if (c <= 4)
+            hipLaunchKernelGGL((k_dots<R, 4>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv);
+        else
+            hipLaunchKernelGGL((k_dots<R, 16>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv);
+    }
+    final_sum(partial, (int)g, nv, out, st);
+}
+template void launch_dots<double>(int64_t, int, const double*, int64_t, const double*, const double*, double*,
+                                  double*, hipStream_t);
+template void launch_dots<float>(int64_t, int, const float*, int64_t, const float*, const float*, double*, double*,
+                                 hipStream_t);
+
+// --------------------------------------------- Gram-Schmidt update (+ reduce)
+// z1 = z - sum_i raw[i] s[i]^2 V_i; then dots of z1 with all V_i (mode 0) or
+// its squared M-norm (mode 1).
+template <typename R, int CH>
+__global__ void __launch_bounds__(TPB)
+k_axpy_red(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const double* __restrict__ raw,
+           const double* __restrict__ s, const R* __restrict__ z, R* __restrict__ z1, const R* __restrict__ WJ,
+           int mode_norm, double* __restrict__ partial) {
+    __shared__ double red[(TPB / 64 + 1) * CH];
+    __shared__ double cf[CH];
+    if (threadIdx.x < CH) cf[threadIdx.x] = threadIdx.x < nv ? raw[threadIdx.x] * s[threadIdx.x] * s[threadIdx.x] : 0.0;
+    __syncthreads();
+    double acc[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) acc[i] = 0;
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) {
+        R v[CH];
+        double zz = (double)z[x];
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            if (i < nv) {
+                v[i] = V[(int64_t)i * ldv + x];
+                zz -= cf[i] * (double)v[i];
+            }
+        const R zr = (R)zz;
+        z1[x] = zr;
+        const double wz = (double)WJ[x] * (double)zr;
+        if (mode_norm) {
+            acc[0] += wz * (double)zr;
+        } else {
+#pragma unroll
+            for (int i = 0; i < CH; ++i)
+                if (i < nv) acc[i] += wz * (double)v[i];
+        }
+    }
+    block_sum<CH>(acc, red);
+    const int nout = mode_norm ? 1 : nv;
+    if (threadIdx.x < nout) partial[(size_t)blockIdx.x * nout + threadIdx.x] = red[TPB / 64 * CH + threadIdx.x];
+}
+
+template <typename R>
+void launch_axpy_reduce(int64_t L, int nv, const R* V, int64_t ldv, const double* raw, const double* s,
+                        const R* z, R* z1, const R* WJ, int mode_norm, double* partial, double* out,
+                        hipStream_t st) {
+    const unsigned g = grid_for(L, TPB * 8) > RED_BLOCKS ? RED_BLOCKS : grid_for(L, TPB * 8);
+    if (nv <= 8)
+        hipLaunchKernelGGL((k_axpy_red<R, 8>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ, mode_norm,
+                           partial);
+    else if (nv <= 16)
+        hipLaunchKernelGGL((k_axpy_red<R, 16>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
+                           mode_norm, partial);
+    else
+        hipLaunchKernelGGL((k_axpy_red<R, 32>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
+                           mode_norm, partial);
+    final_sum(partial, (int)g, mode_norm ? 1 : nv, out, st);
+}
+template void launch_axpy_reduce<double>(int64_t, int, const double*, int64_t, const double*, const double*,
+                                         const double*, double*, const double*, int, double*, double*,
+                                         hipStream_t);
+template void launch_axpy_reduce<float>(int64_t, int, const float*, int64_t, const double*, const double*,
+                                        const float*, float*, const float*, int, double*, double*, hipStream_t);
+
+// ----------------------------------------------------------- linear combination
+template <typename R>
+__global__ void k_lincomb(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const double* __restrict__ coef,
+                          R* __restrict__ x) {
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < L; i += (int64_t)gridDim.x * TPB) {
+        double acc = (double)x[i];
+        for (int k = 0; k < nv; ++k) acc += coef[k] * (double)V[(int64_t)k * ldv + i];
+        x[i] = (R)acc;
+    }
+}
+template <typename R>
+void launch_lincomb(int64_t L, int nv, const R* V, int64_t ldv, const double* coef, R* x, hipStream_t st) {
+    hipLaunchKernelGGL((k_lincomb<R>), dim3(grid_for(L)), dim3(TPB), 0, st, L, nv, V, ldv, coef, x);
+}
+template void launch_lincomb<double>(int64_t, int, const double*, int64_t, const double*, double*, hipStream_t);
+template void launch_lincomb<float>(int64_t, int, const float*, int64_t, const double*, float*, hipStream_t);
+
+// ------------------------------------------------------------ weighted dots
+__global__ void __launch_bounds__(TPB)
+k_wdot(int64_t L, const double* __restrict__ a, const double* __restrict__ b, const double* __restrict__ WJ,
+       double* __restrict__ partial) {
+    __shared__ double red[(TPB / 64 + 1)];
+    double acc[1] = {0};
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB)
+        acc[0] += WJ[x] * a[x] * b[x];
+    block_sum<1>(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[TPB / 64];
+}
+void launch_wdot(int64_t L, const double* a, const double* b, const double* WJ, double* partial, double* out,
+                 hipStream_t st) {
+    const unsigned g = grid_for(L, TPB * 8) > RED_BLOCKS ? RED_BLOCKS : grid_for(L, TPB * 8);
+    hipLaunchKernelGGL(k_wdot, dim3(g), dim3(TPB), 0, st, L, a, b ? b : a, WJ, partial);
+    final_sum(partial, (int)g, 1, out, st);
+}
+
+__global__ void __launch_bounds__(TPB)
+k_picard_var(int64_t L, const double* __restrict__ p0, const double* __restrict__ u0, const double* __restrict__ p1,
+             const double* __restrict__ u1, const double* __restrict__ rho, const double* __restrict__ WJ,
+             double gamma, double* __restrict__ partial) {
+    __shared__ double red[(TPB / 64 + 1) * 2];
+    double acc[2] = {0, 0};
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) {
+        const double dp = p1[x] - p0[x];
+        double du2 = 0;
+        for (int c = 0; c < 3; ++c) {
+            const double du = u1[c * L + x] - u0[c * L + x];
+            du2 += du * du;
+        }
+        acc[0] += WJ[x] * (dp * dp + gamma * p1[x] * rho[x] * du2);
+        acc[1] += WJ[x] * p1[x] * p1[x];
+    }
+    block_sum<2>(acc, red);
+    if (threadIdx.x < 2) partial[blockIdx.x * 2 + threadIdx.x] = red[TPB / 64 * 2 + threadIdx.x];
+}
+void launch_picard_var(int64_t L, const double* p0, const double* u0, const double* p1, const double* u1,
+                       const double* rho, const double* WJ, double gamma, double* partial, double* out,
+                       hipStream_t st) {
+    const unsigned g = grid_for(L, TPB * 8) > RED_BLOCKS ? RED_BLOCKS : grid_for(L, TPB * 8);
+    hipLaunchKernelGGL(k_picard_var, dim3(g), dim3(TPB), 0, st, L, p0, u0, p1, u1, rho, WJ, gamma, partial);
+    final_sum(partial, (int)g, 2, out, st);
+}
+
+__global__ void __launch_bounds__(TPB)
+k_mass(int64_t L, const double* __restrict__ q, const double* __restrict__ WJ, double* __restrict__ partial) {
+    __shared__ double red[(TPB / 64 + 1) * 2];
+    double acc[2] = {0, 0};
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) {
+        acc[0] += WJ[x] * q[x];
+        for (int t = 0; t < 5; ++t)
+            if (!isfinite(q[t * L + x])) acc[1] += 1.0;
+    }
+    block_sum<2>(acc, red);
+    if (threadIdx.x < 2) partial[blockIdx.x * 2 + threadIdx.x] = red[TPB / 64 * 2 + threadIdx.x];
+}
+void launch_mass(int64_t L, const double* q, const double* WJ, double* partial, double* out, hipStream_t st) {
+    const unsigned g = grid_for(L, TPB * 8) > RED_BLOCKS ? RED_BLOCKS : grid_for(L, TPB * 8);
+    hipLaunchKernelGGL(k_mass, dim3(g), dim3(TPB), 0, st, L, q, WJ, partial);
+    final_sum(partial, (int)g, 2, out, st);
+}
+
+// ---------------------------------------------------------- stage combines
+__global__ void k_stage_prepare(int64_t L, const double* __restrict__ y, const double* __restrict__ fN0,
+                                const double* __restrict__ fN1, const double* __restrict__ fS0,
+                                const double* __restrict__ fS1, const double* __restrict__ yp, StageCoef c,
+                                double* __restrict__ rho, double* __restrict__ Fh, double* __restrict__ G0h,
+                                double* __restrict__ p0, double* __restrict__ u0) {
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) {
+        const double* fN[2] = {fN0, fN1};
+        const double* fS[2] = {fS0, fS1};
+        double r = 0, F[3] = {0, 0, 0}, G = 0;
+        for (int m = 0; m < c.l; ++m) {
+            r += c.a[m] * fN[m][x];
+            for (int k = 0; k < 3; ++k) F[k] += c.a[m] * fN[m][(1 + k) * L + x] + c.at[m] * fS[m][k * L + x];
+            G += c.a[m] * fN[m][4 * L + x] + c.at[m] * fS[m][3 * L + x];
+        }
+        const double rl = y[x] + c.dt * r;
+        rho[x] = rl;
+        for (int k = 0; k < 3; ++k) Fh[k * L + x] = y[(1 + k) * L + x] + c.dt * F[k];
+        Fh[2 * L + x] -= c.c_dt * c.g * rl;
+        G0h[x] = y[4 * L + x] + c.dt * G;
+        const double rp = yp[x];
+        double k2 = 0;
+        for (int k = 0; k < 3; ++k) {
+            const double uu = yp[(1 + k) * L + x] / rp;
+            u0[k * L + x] = uu;
+            k2 += uu * uu;
+        }
+        p0[x] = (c.gamma - 1.0) * (yp[4 * L + x] - rp * 0.5 * k2);
+    }
+}
+void launch_stage_prepare(int64_t L, const double* y, const double* const* fNS, const double* const* fS,
+                          const double* yprev, const StageCoef& c, double* rho, double* Fh, double* G0h,
+                          double* p0, double* u0, hipStream_t st) {
+    hipLaunchKernelGGL(k_stage_prepare, dim3(grid_for(L)), dim3(TPB), 0, st, L, y, fNS[0], c.l > 1 ? fNS[1] : fNS[0],
+                       fS[0], c.l > 1 ? fS[1] : fS[0], yprev, c, rho, Fh, G0h, p0, u0);
+}
+
+__global__ void k_finalize(int64_t L, const double* __restrict__ rho, const double* __restrict__ p,
+                           const double* __restrict__ u, double gamma, double* __restrict__ Y) {
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) {
+        const double r = rho[x];
+        double k2 = 0;
+        Y[x] = r;
+        for (int k = 0; k < 3; ++k) {
+            const double uu = u[k * L + x];
+            Y[(1 + k) * L + x] = r * uu;
+            k2 += uu * uu;
+        }
+        Y[4 * L + x] = p[x] / (gamma - 1.0) + 0.5 * r * k2;
+    }
+}
+void launch_finalize(int64_t L, const double* rho, const double* p, const double* u, double gamma, double* Y,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(grid_for(L)), dim3(TPB), 0, st, L, rho, p, u, gamma, Y);
+}
+
+struct FinalArgs {
+    const double* fN[3];
+    const double* fS[3];
+    double b[3];
+};
+__global__ void k_final_update(int64_t L, const double* __restrict__ y, FinalArgs a, double dt,
+                               double* __restrict__ yn) {
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) {
+        for (int t = 0; t < 5; ++t) {
+            double s = 0;
+            for (int l = 0; l < 3; ++l) {
+                double v = a.fN[l][t * L + x];
+                if (t > 0) v += a.fS[l][(t - 1) * L + x];
+                s += a.b[l] * v;
+            }
+            yn[t * L + x] = y[t * L + x] + dt * s;
+        }
+    }
+}
+void launch_final_update(int64_t L, const double* y, const double* const* fNS, const double* const* fS,
+                         const double* b, double dt, double* ynew, hipStream_t st) {
+    FinalArgs a;
+    for (int l = 0; l < 3; ++l) {
+        a.fN[l] = fNS[l];
+        a.fS[l] = fS[l];
+        a.b[l] = b[l];
+    }
+    hipLaunchKernelGGL(k_final_update, dim3(grid_for(L)), dim3(TPB), 0, st, L, y, a, dt, ynew);
+}
+
+__global__ void k_scale_div(int64_t L, int nf, const double* __restrict__ in, const double* __restrict__ WJ,
+                            double* __restrict__ out) {
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB)
+        for (int t = 0; t < nf; ++t) out[t * L + x] = in[t * L + x] / WJ[x];
+}
+void launch_scale_div(int64_t L, int nf, const double* in, const double* WJ, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_div, dim3(grid_for(L)), dim3(TPB), 0, st, L, nf, in, WJ, out);
+}
+
+__global__ void k_d2f(int64_t L, const double* __restrict__ in, float* __restrict__ out) {
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) out[x] = (float)in[x];
+}
+void launch_d2f(int64_t L, const double* in, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_d2f, dim3(grid_for(L)), dim3(TPB), 0, st, L, in, out);
+}
+
+__global__ void k_f2d_add(int64_t L, const float* __restrict__ in, const double* __restrict__ s,
+                          double* __restrict__ x) {
+    const double sc = s ? s[0] : 1.0;
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < L; i += (int64_t)gridDim.x * TPB)
+        x[i] += sc * (double)in[i];
+}
+void launch_f2d_add(int64_t L, const float* in, const double* scale, double* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_f2d_add, dim3(grid_for(L)), dim3(TPB), 0, st, L, in, scale, x);
+}
+
+__global__ void k_axpby(int64_t L, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                        double* __restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < L; i += (int64_t)gridDim.x * TPB)
+        out[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+void launch_axpby(int64_t L, double a, const double* x, double b, const double* y, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for(L)), dim3(TPB), 0, st, L, a, x, b, y, out);
+}
+
+// out = in * s (s from device: s[0], or 1/sqrt(s[0]) when invert_sqrt)
+__global__ void k_scale_store(int64_t L, const double* __restrict__ in, const double* __restrict__ s, int inv,
+                              double* __restrict__ out) {
+    const double sc = inv ? 1.0 / sqrt(s[0]) : s[0];
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < L; i += (int64_t)gridDim.x * TPB) out[i] = sc * in[i];
+}
+void launch_scale_store(int64_t L, const double* in, const double* s_ptr, int invert_sqrt, double* out,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_store, dim3(grid_for(L)), dim3(TPB), 0, st, L, in, s_ptr, invert_sqrt, out);
+}
+__global__ void k_scale_store_f(int64_t L, const double* __restrict__ in, const double* __restrict__ s,
+                                float* __restrict__ out) {
+    const double sc = s[0];
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < L; i += (int64_t)gridDim.x * TPB)
+        out[i] = (float)(sc * in[i]);
+}
+void launch_scale_store_f(int64_t L, const double* in, const double* s_ptr, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_store_f, dim3(grid_for(L)), dim3(TPB), 0, st, L, in, s_ptr, out);
+}
+
+}  // namespace imx
