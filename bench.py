@@ -1,0 +1,163 @@
+"""Benchmark: IMEX-ARK2 steps of the rotating inertia-gravity-wave channel on one MI355X.
+
+Workload: 3000x1000x10 km channel, 120x40x10 hexahedra of degree 3 (48,000
+elements, 15.36 M DoF over the 5 conserved fields), N = 0.01 1/s, theta0 =
+300 K, U = 20 m/s, f = 1e-4 1/s, dt = 20 s, R2 treatment, GMRES / Picard
+tolerance 1e-10, binary64. A step is one whole IMEX-ARK2 step (three explicit
+residuals, two implicit stages with their Picard and GMRES iterations, stage
+combinations, final update and mass check) on device-resident state.
+
+Prints one JSON line: DoF-updates/s (5 E Np per step), the roofline of the
+kernel class that takes the most device time in the timed region (algorithmic
+bytes / HIP-event time on the solver stream), and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "DoF-updates/s per IMEX step (FP64 vs FP32-inner); operator GB/s; p99 latency"
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "vec.hip"):
+        with open(os.path.join(ROOT, "paper_2605_29598_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if the
+    kernels have not changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kind)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(seconds_budget=30.0):
+    """Oracle (plain numpy, one thread) on a 12x4x10-element piece of the same
+    channel: identical element size, degree, dt, physics and tolerances."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import dg
+    from oracle.mesh import Mesh as OMesh, MeshDesc
+    from paper_2605_29598_amd import workloads as W
+
+    w = W.igw_channel()
+    nx, ny = 12, 4
+    w.mesh.Lx, w.mesh.Ly = 3000e3 * nx / 120, 1000e3 * ny / 40
+    w.mesh.nx, w.mesh.ny = nx, ny
+    w.pert_xc = w.mesh.Lx / 2
+    om = OMesh(MeshDesc(**vars(w.mesh)))
+    q = W.initial_state(w, om.node_coords())
+    ph, num = dg.Phys(**vars(w.phys)), dg.Numerics(**vars(w.num))
+    steps, t_total = 0, 0.0
+    with threadpool_limits(1):
+        while steps < 4 and t_total < seconds_budget:
+            t0 = time.perf_counter()
+            q, _ = dg.ark2_step(om, ph, num, q)
+            t_total += time.perf_counter() - t0
+            steps += 1
+    dofs = 5 * om.E * om.Np
+    return {"value": dofs * steps / t_total, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} ARK2 steps of a {nx}x{ny}x10-element piece of the channel "
+                      f"({om.E} elements, r=3, same dt/physics/tolerances), numpy on 1 thread, "
+                      f"{t_total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scheme", default="R2", choices=["R1", "R2"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", action="store_true", help="print progress per step")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2605_29598_amd import binding as B
+    from paper_2605_29598_amd import workloads as W
+
+    w = W.igw_channel(scheme=B.IMX_R1 if args.scheme == "R1" else B.IMX_R2)
+    mesh = B.Mesh(w.mesh)
+    sol = B.Solver(mesh, w.phys, w.num, device="cuda:0")
+    q0 = W.initial_state(w, mesh.node_coords())
+    sol.set_state(q0)
+    dofs = 5 * mesh.E * mesh.Np
+    for i in range(args.warmup):
+        sol.step(1)
+        if args.profile_steps:
+            print(f"warmup step {i} done", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    sol.timing(True)
+    picard = gmres = 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        st = sol.step(1)
+        picard += st.picard_iters
+        gmres += st.gmres_iters
+        if args.profile_steps:
+            print(f"step {i}: picard {st.picard_iters} gmres {st.gmres_iters}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    rep = sol.timing_report()
+    sol.timing(False)
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = dofs * args.steps / elapsed
+    dom = max(rep, key=lambda k: rep[k][0])
+    ms, by, n = rep[dom]
+    achieved = by / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom)
+    kernels = {k: {"ms_per_step": round(v[0] / args.steps, 3), "GB_per_s": round(v[1] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else 0,
+                   "launches_per_step": round(v[2] / args.steps, 1)} for k, v in rep.items() if v[2]}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DoF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "elements": mesh.E, "degree": w.mesh.degree, "dofs": dofs,
+                   "dt": w.num.dt, "scheme": args.scheme, "precision": "fp64",
+                   "gmres_restart": w.num.gmres_restart, "tolerances": [w.num.picard_tol, w.num.gmres_tol]},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "avg_launch_us": 1e3 * ms / max(n, 1), "algorithmic_bytes_per_launch": by / max(n, 1)},
+        "iterations_per_step": {"picard": picard / args.steps, "gmres": gmres / args.steps},
+        "kernels": kernels,
+        "mass": sol.total_mass(),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -188,6 +188,31 @@ imx_status imx_step(imx_solver* s, int nsteps, imx_step_stats* stats);
 imx_status imx_total_mass(imx_solver* s, double* mass);
 void imx_solver_destroy(imx_solver* s);
 
+/* ------------------------------------------------------------ timing */
+/* Kernel classes timed by imx_solver_timing. */
+enum {
+    IMX_K_EXPLICIT = 0,   /* explicit residual */
+    IMX_K_PASS1 = 1,      /* Schur pass 1: w = (I+beta J)^{-1} A^{-1} (F - B p), face fluxes */
+    IMX_K_PASS2 = 2,      /* Schur pass 2: D p - (C^k + M_g) w */
+    IMX_K_LAMBDA = 3,     /* Picard refresh of the lagged energy terms */
+    IMX_K_DOTS = 4,       /* GMRES M-weighted multi-dot products */
+    IMX_K_ORTHO = 5,      /* GMRES Gram-Schmidt update (+ dots or norm) */
+    IMX_K_LINCOMB = 6,    /* GMRES solution update */
+    IMX_K_STAGE = 7,      /* ARK2 stage combinations */
+    IMX_K_REDUCE = 8,     /* small reductions (norms, mass, Picard variation) */
+    IMX_K_COUNT = 9
+};
+/* enable != 0: clears the counters and brackets every subsequent kernel
+ * launch of the solver with a pair of HIP events on its stream; enable = 0
+ * stops recording. */
+imx_status imx_solver_timing(imx_solver* s, int enable);
+/* Accumulated device time (ms), algorithmic bytes (every field a kernel reads
+ * or writes counted once, geometry included, neighbour re-reads and internal
+ * face buffers excluded) and launch count of kernel class `kind` since timing
+ * was enabled. Synchronises the stream. */
+imx_status imx_solver_timing_report(imx_solver* s, int kind, double* total_ms, double* bytes,
+                                    int64_t* launches);
+
 /* Description of the last error raised on the calling thread. */
 const char* imx_last_error(void);
 

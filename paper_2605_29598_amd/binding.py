@@ -78,7 +78,12 @@ SIGNATURES = {
     "imx_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(imx_step_stats)]),
     "imx_total_mass": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
     "imx_solver_destroy": (None, [_vp]),
+    "imx_solver_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "imx_solver_timing_report": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                                ctypes.POINTER(ctypes.c_double), _c_i64p]),
 }
+
+KERNEL_KINDS = ["explicit", "pass1", "pass2", "lambda", "dots", "ortho", "lincomb", "stage", "reduce"]
 
 _lib = None
 
@@ -232,6 +237,19 @@ class Solver:
         st = imx_step_stats()
         check(lib().imx_step(self.h, int(nsteps), ctypes.byref(st)), "imx_step")
         return st
+
+    def timing(self, enable):
+        check(lib().imx_solver_timing(self.h, int(bool(enable))), "imx_solver_timing")
+
+    def timing_report(self):
+        """{kind: (total_ms, algorithmic_bytes, launches)} since timing was enabled."""
+        out = {}
+        for k, name in enumerate(KERNEL_KINDS):
+            ms, by, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+            check(lib().imx_solver_timing_report(self.h, k, ctypes.byref(ms), ctypes.byref(by), ctypes.byref(n)),
+                  "imx_solver_timing_report")
+            out[name] = (ms.value, by.value, n.value)
+        return out
 
     def total_mass(self):
         m = ctypes.c_double()

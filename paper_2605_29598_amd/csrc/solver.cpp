@@ -81,6 +81,13 @@ struct imx_solver {
     float *rhof = nullptr, *pkf = nullptr, *WJf = nullptr, *Gf = nullptr, *nSf = nullptr, *xf = nullptr;
     // pinned host scalars
     double* hsc = nullptr;
+    // kernel timing (imx_solver_timing)
+    bool timing = false;
+    struct TRec { int kind; hipEvent_t a, b; double bytes; };
+    std::vector<TRec> trec;
+    std::vector<hipEvent_t> tpool;
+    double t_ms[IMX_K_COUNT] = {}, t_bytes[IMX_K_COUNT] = {};
+    int64_t t_count[IMX_K_COUNT] = {};
     // device scalar slots (offsets into dsc)
     enum { S_RAW1 = 0, S_RAW2 = 64, S_NRM = 128, S_SV = 192, S_COEF = 256, S_MISC = 320, S_N = 384 };
 };
@@ -201,6 +208,58 @@ static imx_status put_scalars(imx_solver* s, double* dev, const double* vals, in
     return IMX_OK;
 }
 
+// ----------------------------------------------------------- kernel timing
+static void timing_flush(imx_solver* s) {
+    if (s->trec.empty()) return;
+    (void)hipStreamSynchronize(s->st);
+    for (auto& r : s->trec) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, r.a, r.b);
+        s->t_ms[r.kind] += ms;
+        s->t_bytes[r.kind] += r.bytes;
+        s->t_count[r.kind] += 1;
+        s->tpool.push_back(r.a);
+        s->tpool.push_back(r.b);
+    }
+    s->trec.clear();
+}
+
+static hipEvent_t timing_event(imx_solver* s) {
+    if (s->tpool.empty()) {
+        if (s->trec.size() > 4096) timing_flush(s);
+        if (s->tpool.empty()) {
+            hipEvent_t e;
+            (void)hipEventCreate(&e);
+            return e;
+        }
+    }
+    hipEvent_t e = s->tpool.back();
+    s->tpool.pop_back();
+    return e;
+}
+
+// Runs `launch` (a kernel launch on s->st), bracketed by events when timing.
+template <typename Fn>
+static void timed(imx_solver* s, int kind, double bytes, Fn&& launch) {
+    if (!s->timing) {
+        launch();
+        return;
+    }
+    imx_solver::TRec r{kind, timing_event(s), timing_event(s), bytes};
+    (void)hipEventRecord(r.a, s->st);
+    launch();
+    (void)hipEventRecord(r.b, s->st);
+    s->trec.push_back(r);
+}
+
+// algorithmic bytes of one launch: nfields nodal fields of the element kernels
+// plus the geometry (per element 10 Np + 9 Nf values when deformed)
+static double field_bytes(const imx_solver* s, double nfields, bool geometry) {
+    double b = nfields * (double)s->L * 8.0;
+    if (geometry && s->mesh->deformed) b += (double)s->E * (10.0 * s->Np + 9.0 * s->Nf) * 8.0;
+    return b;
+}
+
 // ------------------------------------------------------------ stage context
 struct StageCtx {
     StageK k;
@@ -213,14 +272,25 @@ struct StageCtx {
 
 // r = M^{-1}(RHS - S x) with x scaled by *xs (device) if xs != null
 static void residual(imx_solver* s, const StageCtx& c, const double* x, const double* xs, double* out) {
-    launch_pass1<double>(s->dm, s->tab, c.k, x, xs, c.Fh, c.rho, c.pk, c.uk, s->w, s->FB, s->FBh, s->st);
-    launch_pass2<double>(s->dm, s->tab, c.k, c.Gp, x, xs, s->w, c.pk, c.rho, s->FB, s->FBh, out, 1.0, 0, s->st);
+    const double n1 = (x ? 1 : 0) + 3 + 1 + 1 + 3 + (c.k.scheme == 1 ? 3 : 0);   // x, Fh, rho, pk, w (, uk)
+    timed(s, IMX_K_PASS1, field_bytes(s, n1, true), [&] {
+        launch_pass1<double>(s->dm, s->tab, c.k, x, xs, c.Fh, c.rho, c.pk, c.uk, s->w, s->FB, s->FBh, s->st);
+    });
+    const double n2 = 1 + (x ? 1 : 0) + 3 + 1 + (c.k.scheme == 2 ? 1 : 0) + 1;   // Gp, x, w, pk, rho, out
+    timed(s, IMX_K_PASS2, field_bytes(s, n2, true), [&] {
+        launch_pass2<double>(s->dm, s->tab, c.k, c.Gp, x, xs, s->w, c.pk, c.rho, s->FB, s->FBh, out, 1.0, 0, s->st);
+    });
 }
 
 // z = M^{-1} S (xs * x)
 static void matvec(imx_solver* s, const StageCtx& c, const double* x, const double* xs, double* out) {
-    launch_pass1<double>(s->dm, s->tab, c.k, x, xs, nullptr, c.rho, c.pk, c.uk, s->w, s->FB, s->FBh, s->st);
-    launch_pass2<double>(s->dm, s->tab, c.k, nullptr, x, xs, s->w, c.pk, c.rho, s->FB, s->FBh, out, -1.0, 0, s->st);
+    timed(s, IMX_K_PASS1, field_bytes(s, 6, true), [&] {   // x, rho, pk, w
+        launch_pass1<double>(s->dm, s->tab, c.k, x, xs, nullptr, c.rho, c.pk, c.uk, s->w, s->FB, s->FBh, s->st);
+    });
+    timed(s, IMX_K_PASS2, field_bytes(s, 6 + (c.k.scheme == 2 ? 1 : 0), true), [&] {   // x, w, pk, (rho), out
+        launch_pass2<double>(s->dm, s->tab, c.k, nullptr, x, xs, s->w, c.pk, c.rho, s->FB, s->FBh, out, -1.0, 0,
+                             s->st);
+    });
 }
 
 
@@ -247,7 +317,8 @@ static imx_status gmres(imx_solver* s, const StageCtx& c, double* x, double bnor
     double* bb = s->dsc + imx_solver::S_MISC;
     std::vector<double> H((m + 1) * m), g(m + 1), cs(m), sn(m), svh(m + 1), yv(m), cf(m);
     residual(s, c, x, nullptr, V);
-    launch_wdot(L, V, nullptr, s->dm.WJ, s->partial, bb, s->st);
+    timed(s, IMX_K_REDUCE, 2 * (double)L * 8.0,
+          [&] { launch_wdot(L, V, nullptr, s->dm.WJ, s->partial, bb, s->st); });
     CHK(sync_read(s, bb, 1));
     double beta = std::sqrt(s->hsc[0]);
     int its = 0;
@@ -266,10 +337,18 @@ static imx_status gmres(imx_solver* s, const StageCtx& c, double* x, double bnor
         for (int j = 0; j < m; ++j) {
             matvec(s, c, V + (size_t)j * L, sv + j, s->z);
             ++its;
-            launch_dots<double>(L, j + 1, V, L, s->z, s->dm.WJ, s->partial, raw1, s->st);
-            launch_axpy_reduce<double>(L, j + 1, V, L, raw1, sv, s->z, s->z1, s->dm.WJ, 0, s->partial, raw2, s->st);
-            launch_axpy_reduce<double>(L, j + 1, V, L, raw2, sv, s->z1, V + (size_t)(j + 1) * L, s->dm.WJ, 1,
-                                       s->partial, nrm, s->st);
+            const double vb = (double)L * 8.0;
+            timed(s, IMX_K_DOTS, (j + 3) * vb, [&] {
+                launch_dots<double>(L, j + 1, V, L, s->z, s->dm.WJ, s->partial, raw1, s->st);
+            });
+            timed(s, IMX_K_ORTHO, (j + 4) * vb, [&] {
+                launch_axpy_reduce<double>(L, j + 1, V, L, raw1, sv, s->z, s->z1, s->dm.WJ, 0, s->partial, raw2,
+                                           s->st);
+            });
+            timed(s, IMX_K_ORTHO, (j + 4) * vb, [&] {
+                launch_axpy_reduce<double>(L, j + 1, V, L, raw2, sv, s->z1, V + (size_t)(j + 1) * L, s->dm.WJ, 1,
+                                           s->partial, nrm, s->st);
+            });
             HIPCHK(hipMemcpyAsync(s->hsc, raw1, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s->st));
             HIPCHK(hipMemcpyAsync(s->hsc + 64, raw2, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s->st));
             HIPCHK(hipMemcpyAsync(s->hsc + 128, nrm, sizeof(double), hipMemcpyDeviceToHost, s->st));
@@ -305,9 +384,11 @@ static imx_status gmres(imx_solver* s, const StageCtx& c, double* x, double bnor
         }
         for (int i = 0; i < k; ++i) cf[i] = yv[i] * svh[i];
         CHK(put_scalars(s, coef, cf.data(), k, 100));
-        launch_lincomb<double>(L, k, V, L, coef, x, s->st);
+        timed(s, IMX_K_LINCOMB, (k + 2) * (double)L * 8.0,
+              [&] { launch_lincomb<double>(L, k, V, L, coef, x, s->st); });
         residual(s, c, x, nullptr, V);
-        launch_wdot(L, V, nullptr, s->dm.WJ, s->partial, bb, s->st);
+        timed(s, IMX_K_REDUCE, 2 * (double)L * 8.0,
+          [&] { launch_wdot(L, V, nullptr, s->dm.WJ, s->partial, bb, s->st); });
         CHK(sync_read(s, bb, 1));
         beta = std::sqrt(s->hsc[0]);
     }
@@ -323,7 +404,8 @@ static imx_status pressure_solve(imx_solver* s, const StageCtx& c, double* x, Gm
     double* bb = s->dsc + imx_solver::S_MISC;
     // |b|_M with b = M^{-1} RHS: the residual at x = 0
     residual(s, c, nullptr, nullptr, s->b);
-    launch_wdot(L, s->b, nullptr, s->dm.WJ, s->partial, bb, s->st);
+    timed(s, IMX_K_REDUCE, 2 * (double)L * 8.0,
+          [&] { launch_wdot(L, s->b, nullptr, s->dm.WJ, s->partial, bb, s->st); });
     CHK(sync_read(s, bb, 1));
     const double bnorm = std::sqrt(s->hsc[0]);
     return gmres(s, c, x, bnorm, s->num.gmres_tol, s->num.gmres_max, s->num.fixed_iterations != 0, out);
@@ -339,14 +421,19 @@ static imx_status stage_solve(imx_solver* s, double a_ll, const double* rho, con
     bool converged = false;
     double* bb = s->dsc + imx_solver::S_MISC;
     for (int it = 0; it < s->num.picard_max; ++it) {
-        launch_lambda(s->dm, s->tab, k, p, u, rho, G0h, s->Gp, s->st);
+        timed(s, IMX_K_LAMBDA, field_bytes(s, 8, true),
+              [&] { launch_lambda(s->dm, s->tab, k, p, u, rho, G0h, s->Gp, s->st); });
         StageCtx c{k, Fh, s->Gp, p, u, rho};
         HIPCHK(hipMemcpyAsync(pn, p, L * sizeof(double), hipMemcpyDeviceToDevice, s->st));
         GmresOut go;
         CHK(pressure_solve(s, c, pn, go));
         // velocity recovery from the momentum equation
-        launch_pass1<double>(s->dm, s->tab, k, pn, nullptr, Fh, rho, p, u, un, nullptr, nullptr, s->st);
-        launch_picard_var(L, p, u, pn, un, rho, s->dm.WJ, s->phys.gamma, s->partial, bb, s->st);
+        timed(s, IMX_K_PASS1, field_bytes(s, 1 + 3 + 1 + 3 + (k.scheme == 1 ? 3 : 0), true), [&] {
+            launch_pass1<double>(s->dm, s->tab, k, pn, nullptr, Fh, rho, p, u, un, nullptr, nullptr, s->st);
+        });
+        timed(s, IMX_K_REDUCE, 10 * (double)L * 8.0, [&] {
+            launch_picard_var(L, p, u, pn, un, rho, s->dm.WJ, s->phys.gamma, s->partial, bb, s->st);
+        });
         CHK(sync_read(s, bb, 2));
         const double var = std::sqrt(s->hsc[0] / s->hsc[1]);
         std::swap(p, pn);
@@ -388,7 +475,8 @@ static imx_status one_step(imx_solver* s, imx_step_stats* acc) {
     const double dt = s->num.dt;
     const PhysK ph = phys_k(s);
     HIPCHK(hipMemcpyAsync(s->ybak, s->y, 5 * L * sizeof(double), hipMemcpyDeviceToDevice, s->st));
-    launch_explicit<double>(s->dm, s->tab, ph, s->y, s->fN[0], s->fS[0], s->st);
+    timed(s, IMX_K_EXPLICIT, field_bytes(s, 14 + (ph.sponge ? 1 : 0), true),
+          [&] { launch_explicit<double>(s->dm, s->tab, ph, s->y, s->fN[0], s->fS[0], s->st); });
     for (int l = 1; l <= 2; ++l) {
         StageCoef c{};
         for (int mm = 0; mm < l; ++mm) {
@@ -401,7 +489,9 @@ static imx_status one_step(imx_solver* s, imx_step_stats* acc) {
         c.g = s->phys.g;
         c.gamma = s->phys.gamma;
         const double* yprev = l == 1 ? s->y : s->Y;
-        launch_stage_prepare(L, s->y, s->fN, s->fS, yprev, c, s->rho, s->Fh, s->G0h, s->p, s->u, s->st);
+        timed(s, IMX_K_STAGE, (5 + 9 * l + 5 + 1 + 3 + 1 + 1 + 3) * (double)L * 8.0, [&] {
+            launch_stage_prepare(L, s->y, s->fN, s->fS, yprev, c, s->rho, s->Fh, s->G0h, s->p, s->u, s->st);
+        });
         imx_solve_stats ss{};
         imx_status rc = stage_solve(s, TAB.at[l][l], s->rho, s->Fh, s->G0h, s->p, s->u, s->pn, s->un, &ss);
         acc->picard_iters += ss.picard_iters;
@@ -410,12 +500,15 @@ static imx_status one_step(imx_solver* s, imx_step_stats* acc) {
             (void)hipMemcpyAsync(s->y, s->ybak, 5 * L * sizeof(double), hipMemcpyDeviceToDevice, s->st);
             return rc;
         }
-        launch_finalize(L, s->rho, s->p, s->u, s->phys.gamma, s->Y, s->st);
-        launch_explicit<double>(s->dm, s->tab, ph, s->Y, s->fN[l], s->fS[l], s->st);
+        timed(s, IMX_K_STAGE, 10 * (double)L * 8.0,
+              [&] { launch_finalize(L, s->rho, s->p, s->u, s->phys.gamma, s->Y, s->st); });
+        timed(s, IMX_K_EXPLICIT, field_bytes(s, 14 + (ph.sponge ? 1 : 0), true),
+              [&] { launch_explicit<double>(s->dm, s->tab, ph, s->Y, s->fN[l], s->fS[l], s->st); });
     }
-    launch_final_update(L, s->y, s->fN, s->fS, TAB.b, dt, s->y, s->st);
+    timed(s, IMX_K_STAGE, (5 + 27 + 5) * (double)L * 8.0,
+          [&] { launch_final_update(L, s->y, s->fN, s->fS, TAB.b, dt, s->y, s->st); });
     double* bb = s->dsc + imx_solver::S_MISC;
-    launch_mass(L, s->y, s->dm.WJ, s->partial, bb, s->st);
+    timed(s, IMX_K_REDUCE, 6 * (double)L * 8.0, [&] { launch_mass(L, s->y, s->dm.WJ, s->partial, bb, s->st); });
     CHK(sync_read(s, bb, 2));
     if (s->hsc[1] != 0.0 || !std::isfinite(s->hsc[0])) {
         HIPCHK(hipMemcpyAsync(s->y, s->ybak, 5 * L * sizeof(double), hipMemcpyDeviceToDevice, s->st));
@@ -619,7 +712,9 @@ imx_status imx_get_state(const imx_solver* s, double* q) {
 imx_status imx_explicit_residual(imx_solver* s, const double* q, double* fNS, double* fS) {
     NEED_BOUND(s);
     if (!q || !fNS || !fS) return IMX_EINVAL;
-    launch_explicit<double>(s->dm, s->tab, phys_k(s), q, fNS, fS, s->st);
+    const PhysK ph = phys_k(s);
+    timed(s, IMX_K_EXPLICIT, field_bytes(s, 14 + (ph.sponge ? 1 : 0), true),
+          [&] { launch_explicit<double>(s->dm, s->tab, ph, q, fNS, fS, s->st); });
     HIPCHK(hipGetLastError());
     return IMX_OK;
 }
@@ -639,9 +734,14 @@ imx_status imx_schur_apply(imx_solver* s, const double* pin, double* out) {
     if (!pin || !out) return IMX_EINVAL;
     const double a_ll = TAB.at[1][1];
     StageK k = stage_k(s, a_ll);
-    launch_pass1<double>(s->dm, s->tab, k, pin, nullptr, nullptr, s->rho, s->p, s->u, s->w, s->FB, s->FBh, s->st);
-    launch_pass2<double>(s->dm, s->tab, k, nullptr, pin, nullptr, s->w, s->p, s->rho, s->FB, s->FBh, out, -1.0, 1,
-                         s->st);
+    timed(s, IMX_K_PASS1, field_bytes(s, 6, true), [&] {
+        launch_pass1<double>(s->dm, s->tab, k, pin, nullptr, nullptr, s->rho, s->p, s->u, s->w, s->FB, s->FBh,
+                             s->st);
+    });
+    timed(s, IMX_K_PASS2, field_bytes(s, 6 + (k.scheme == 2 ? 1 : 0), true), [&] {
+        launch_pass2<double>(s->dm, s->tab, k, nullptr, pin, nullptr, s->w, s->p, s->rho, s->FB, s->FBh, out, -1.0,
+                             1, s->st);
+    });
     HIPCHK(hipGetLastError());
     return IMX_OK;
 }
@@ -690,8 +790,34 @@ imx_status imx_total_mass(imx_solver* s, double* mass) {
     return IMX_OK;
 }
 
+imx_status imx_solver_timing(imx_solver* s, int enable) {
+    NEED_BOUND(s);
+    timing_flush(s);
+    if (enable) {
+        for (int k = 0; k < IMX_K_COUNT; ++k) {
+            s->t_ms[k] = 0.0;
+            s->t_bytes[k] = 0.0;
+            s->t_count[k] = 0;
+        }
+    }
+    s->timing = enable != 0;
+    return IMX_OK;
+}
+
+imx_status imx_solver_timing_report(imx_solver* s, int kind, double* ms, double* bytes, int64_t* launches) {
+    NEED_BOUND(s);
+    if (kind < 0 || kind >= IMX_K_COUNT) return IMX_EINVAL;
+    timing_flush(s);
+    if (ms) *ms = s->t_ms[kind];
+    if (bytes) *bytes = s->t_bytes[kind];
+    if (launches) *launches = s->t_count[kind];
+    return IMX_OK;
+}
+
 void imx_solver_destroy(imx_solver* s) {
     if (!s) return;
+    timing_flush(s);
+    for (auto e : s->tpool) (void)hipEventDestroy(e);
     if (s->hsc) (void)hipHostFree(s->hsc);
     delete s;
 }
