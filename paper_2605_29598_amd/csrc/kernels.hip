@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 
 #include "kernels.hpp"
 
@@ -49,6 +50,40 @@ static Tab<N, R> to_tab(const HostTab& h) {
             for (int i = 0; i < N; ++i) t.H[hh][a][i] = (R)h.H[(hh * N + a) * N + i];
     for (int i = 0; i < N; ++i) t.w[i] = (R)h.w[i];
     return t;
+}
+
+// the basis tables are indexed per lane, so every block keeps a copy in LDS
+// (visible after the block's first barrier)
+template <int N, typename R>
+__device__ __forceinline__ void load_tab(const Tab<N, R>* __restrict__ src, Tab<N, R>* dst) {
+    constexpr int NW = (int)(sizeof(Tab<N, R>) / sizeof(R));
+    const R* a = (const R*)src;
+    R* b = (R*)dst;
+    for (int i = threadIdx.x; i < NW; i += blockDim.x) b[i] = a[i];
+}
+
+size_t tab_bytes(int n, int f32) {
+    switch (n) {
+        case 2: return f32 ? sizeof(Tab<2, float>) : sizeof(Tab<2, double>);
+        case 3: return f32 ? sizeof(Tab<3, float>) : sizeof(Tab<3, double>);
+        case 4: return f32 ? sizeof(Tab<4, float>) : sizeof(Tab<4, double>);
+        default: return f32 ? sizeof(Tab<5, float>) : sizeof(Tab<5, double>);
+    }
+}
+
+template <int N, typename R>
+static void fill_n(const HostTab& h, void* out) {
+    Tab<N, R> t = to_tab<N, R>(h);
+    std::memcpy(out, &t, sizeof(t));
+}
+
+void fill_tab(const HostTab& h, int f32, void* out) {
+    switch (h.n) {
+        case 2: f32 ? fill_n<2, float>(h, out) : fill_n<2, double>(h, out); break;
+        case 3: f32 ? fill_n<3, float>(h, out) : fill_n<3, double>(h, out); break;
+        case 4: f32 ? fill_n<4, float>(h, out) : fill_n<4, double>(h, out); break;
+        default: f32 ? fill_n<5, float>(h, out) : fill_n<5, double>(h, out); break;
+    }
 }
 
 template <typename R>
@@ -223,91 +258,145 @@ __device__ __forceinline__ void euler_flux(const R* qa, const R* qbin, const R* 
     fl[8] = (R)0.5 * (hA * unSA + hB * unSB) + hl * (pA - pB) / gm1;
 }
 
+// value of the coarse neighbour's face polynomial (face (d, side) of the
+// element at f) at point pt of quarter sub; the same arithmetic as taking
+// the coarse face values first and then sub_interp
+template <int N, typename R, typename P>
+__device__ __forceinline__ R coarse_point(const P* f, const R* fv, const Tab<N, R>& T, int d, int sub, int pt) {
+    const int a = pt % N, b = pt / N, h1 = sub & 1, h2 = sub >> 1;
+    R acc = 0;
+#pragma unroll 1
+    for (int bb = 0; bb < N; ++bb) {
+        R s = 0;
+#pragma unroll 1
+        for (int aa = 0; aa < N; ++aa) s += T.H[h1][a][aa] * face_value<N>(f, fv, d, aa + N * bb);
+        acc += T.H[h2][b][bb] * s;
+    }
+    return acc;
+}
+
 // =====================================================================
 // Explicit residual: fNS = M^{-1} T_NS, fS = M^{-1} T_S (momentum, energy)
 // =====================================================================
-template <int N, typename R>
+template <int N, typename R, bool SLOW>
 __global__ void __launch_bounds__(threads_of(N))
-k_explicit(const R* __restrict__ q, R* __restrict__ fNS, R* __restrict__ fS, Geom<R> g, Tab<N, R> T,
+k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, R* __restrict__ fNS, R* __restrict__ fS, Geom<R> g, const Tab<N, R>* __restrict__ Tg,
            PhysK ph, const double* __restrict__ sponge) {
     constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
+    constexpr int L_FAST = 6 * 9 * NF, L_SLOW = 5 * NF + 5 * NF + 9 * NF + 4 * 9 * NF, L_VOL = 9 * NP;
+    constexpr int UN = (L_FAST > L_SLOW ? L_FAST : L_SLOW) > L_VOL ? (L_FAST > L_SLOW ? L_FAST : L_SLOW) : L_VOL;
     __shared__ R s_q[EPB][5][NP];
-    __shared__ R s_own[EPB][5][NF];
-    __shared__ R s_nb[EPB][5][NF];
-    __shared__ R s_fl[EPB][9][NF];
-    __shared__ R s_sub[EPB][4][9][NF];
-    __shared__ R s_G[EPB][3][NP];
+    __shared__ R s_u[EPB][UN];
     const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
-    const int64_t e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
-    const bool act = le < EPB && e < g.E;
+    __shared__ Tab<N, R> T;
+    load_tab<N, R>(Tg, &T);
+    const int64_t slot = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+    const bool act = le < EPB && slot < nel;
+    const int64_t e = act ? (elist ? (int64_t)elist[slot] : slot) : 0;
     const size_t fs = (size_t)g.E * NP;
     const R gam = (R)ph.gamma;
     if (act)
         for (int t = 0; t < 5; ++t) s_q[le][t][node] = q[t * fs + e * NP + node];
+    constexpr bool slow = SLOW;
     __syncthreads();
     R acc[9];
     for (int o = 0; o < 9; ++o) acc[o] = 0;
+    R* U = &s_u[le][0];
 
-    for (int f = 0; f < 6; ++f) {
-        const int d = f >> 1, s = f & 1;
-        const int kind = act ? g.kind[e * 6 + f] : -1;
-        const int nbr = act ? g.nbr[e * 6 + f] : 0;
-        const int aux = act ? g.aux[e * 6 + f] : 0;
-        if (act && node < NF) {
-            for (int t = 0; t < 5; ++t) s_own[le][t][node] = face_value<N>(&s_q[le][t][0], T.f[s], d, node);
-            if (kind == CONF || kind == FINE)
-                for (int t = 0; t < 5; ++t)
-                    s_nb[le][t][node] = face_value<N>(q + t * fs + (size_t)nbr * NP, T.f[1 - s], d, node);
-        }
-        __syncthreads();
-        if (act) {
-            const int nit = kind == COARSE ? 4 * NF : NF;
-            for (int it = node; it < nit; it += NP) {
-                const int hs = it / NF, pt = it - hs * NF;
+    if (!slow) {
+        // all faces at once: U[(f*9 + o)*NF + pt]
+        if (act)
+            for (int it = node; it < 6 * NF; it += NP) {
+                const int f = it / NF, pt = it - f * NF, d = f >> 1, s = f & 1;
+                const int kind = g.kind[e * 6 + f], nbr = g.nbr[e * 6 + f];
                 R qa[5], qb[5], nS[3], fl[9];
-                bool wall = false;
-                if (kind == COARSE) {
-                    const int fn = g.hang[nbr * 4 + hs];
-                    for (int t = 0; t < 5; ++t) {
-                        qa[t] = sub_interp<N>(&s_own[le][t][0], T, hs, pt);
-                        qb[t] = face_value<N>(q + t * fs + (size_t)fn * NP, T.f[1 - s], d, pt);
+                for (int t = 0; t < 5; ++t) qa[t] = face_value<N>(&s_q[le][t][0], T.f[s], d, pt);
+                if (kind == CONF)
+                    for (int t = 0; t < 5; ++t) qb[t] = face_value<N>(q + t * fs + (size_t)nbr * NP, T.f[1 - s], d, pt);
+                else if (kind == FINE)
+                    for (int t = 0; t < 5; ++t)
+                        qb[t] = coarse_point<N>(q + t * fs + (size_t)nbr * NP, T.f[1 - s], T, d,
+                                                g.aux[e * 6 + f] & 3, pt);
+                area<N>(g, T, e, f, pt, nS);
+                euler_flux<R>(qa, qb, nS, kind == WALL, gam, fl);
+                for (int o = 0; o < 9; ++o) U[(f * 9 + o) * NF + pt] = fl[o];
+            }
+        __syncthreads();
+        if (act)
+            for (int f = 0; f < 6; ++f) {
+                int m, pt;
+                split_node<N>(f >> 1, node, m, pt);
+                const R lf = T.f[f & 1][m];
+                for (int o = 0; o < 9; ++o) acc[o] -= lf * U[(f * 9 + o) * NF + pt];
+            }
+    } else {
+        R* s_own = U;                 // [5][NF]
+        R* s_nb = U + 5 * NF;         // [5][NF]
+        R* s_fl = U + 10 * NF;        // [9][NF]
+        R* s_sub = U + 19 * NF;       // [4][9][NF]
+        for (int f = 0; f < 6; ++f) {
+            const int d = f >> 1, s = f & 1;
+            const int kind = act ? g.kind[e * 6 + f] : -1;
+            const int nbr = act ? g.nbr[e * 6 + f] : 0;
+            const int aux = act ? g.aux[e * 6 + f] : 0;
+            if (act && node < NF) {
+                for (int t = 0; t < 5; ++t) s_own[t * NF + node] = face_value<N>(&s_q[le][t][0], T.f[s], d, node);
+                if (kind == CONF || kind == FINE)
+                    for (int t = 0; t < 5; ++t)
+                        s_nb[t * NF + node] = face_value<N>(q + t * fs + (size_t)nbr * NP, T.f[1 - s], d, node);
+            }
+            __syncthreads();
+            if (act) {
+                const int nit = kind == COARSE ? 4 * NF : NF;
+                for (int it = node; it < nit; it += NP) {
+                    const int hs = it / NF, pt = it - hs * NF;
+                    R qa[5], qb[5], nS[3], fl[9];
+                    bool wall = false;
+                    if (kind == COARSE) {
+                        const int fn = g.hang[nbr * 4 + hs];
+                        for (int t = 0; t < 5; ++t) {
+                            qa[t] = sub_interp<N>(s_own + t * NF, T, hs, pt);
+                            qb[t] = face_value<N>(q + t * fs + (size_t)fn * NP, T.f[1 - s], d, pt);
+                        }
+                        area<N>(g, T, fn, f ^ 1, pt, nS);
+                        for (int c = 0; c < 3; ++c) nS[c] = -nS[c];
+                    } else {
+                        for (int t = 0; t < 5; ++t) qa[t] = s_own[t * NF + pt];
+                        if (kind == CONF)
+                            for (int t = 0; t < 5; ++t) qb[t] = s_nb[t * NF + pt];
+                        else if (kind == FINE)
+                            for (int t = 0; t < 5; ++t) qb[t] = sub_interp<N>(s_nb + t * NF, T, aux & 3, pt);
+                        else
+                            wall = true;
+                        area<N>(g, T, e, f, pt, nS);
                     }
-                    area<N>(g, T, fn, f ^ 1, pt, nS);
-                    for (int c = 0; c < 3; ++c) nS[c] = -nS[c];
-                } else {
-                    for (int t = 0; t < 5; ++t) qa[t] = s_own[le][t][pt];
-                    if (kind == CONF)
-                        for (int t = 0; t < 5; ++t) qb[t] = s_nb[le][t][pt];
-                    else if (kind == FINE)
-                        for (int t = 0; t < 5; ++t) qb[t] = sub_interp<N>(&s_nb[le][t][0], T, aux & 3, pt);
+                    euler_flux<R>(qa, qb, nS, wall, gam, fl);
+                    if (kind == COARSE)
+                        for (int o = 0; o < 9; ++o) s_sub[(hs * 9 + o) * NF + pt] = fl[o];
                     else
-                        wall = true;
-                    area<N>(g, T, e, f, pt, nS);
+                        for (int o = 0; o < 9; ++o) s_fl[o * NF + pt] = fl[o];
                 }
-                euler_flux<R>(qa, qb, nS, wall, gam, fl);
-                if (kind == COARSE)
-                    for (int o = 0; o < 9; ++o) s_sub[le][hs][o][pt] = fl[o];
-                else
-                    for (int o = 0; o < 9; ++o) s_fl[le][o][pt] = fl[o];
             }
-        }
-        __syncthreads();
-        if (act && kind == COARSE && node < NF)
-            for (int o = 0; o < 9; ++o) {
-                R v = 0;
-                for (int h = 0; h < 4; ++h) v += sub_interp_T<N>(&s_sub[le][h][o][0], T, h, node);
-                s_fl[le][o][node] = v;
+            __syncthreads();
+            if (act && kind == COARSE && node < NF)
+                for (int o = 0; o < 9; ++o) {
+                    R v = 0;
+                    for (int h = 0; h < 4; ++h) v += sub_interp_T<N>(s_sub + (h * 9 + o) * NF, T, h, node);
+                    s_fl[o * NF + node] = v;
+                }
+            __syncthreads();
+            if (act) {
+                int m, pt;
+                split_node<N>(d, node, m, pt);
+                const R lf = T.f[s][m];
+                for (int o = 0; o < 9; ++o) acc[o] -= lf * s_fl[o * NF + pt];
             }
-        __syncthreads();
-        if (act) {
-            int m, pt;
-            split_node<N>(d, node, m, pt);
-            const R lf = T.f[s][m];
-            for (int o = 0; o < 9; ++o) acc[o] -= lf * s_fl[le][o][pt];
+            __syncthreads();
         }
     }
+    __syncthreads();   // the volume staging reuses the face buffers
 
-    // volume terms
+    // volume terms, three outputs per round: U[(o3*3 + d)*NP + node]
     R rho = 1, u[3] = {0, 0, 0}, kin = 0, p = 0, wj = 1;
     if (act) {
         rho = s_q[le][0][node];
@@ -316,30 +405,33 @@ k_explicit(const R* __restrict__ q, R* __restrict__ fNS, R* __restrict__ fS, Geo
         p = (gam - (R)1) * (s_q[le][4][node] - rho * kin);
         wj = g.WJ[e * NP + node];
     }
-    for (int o = 0; o < 9; ++o) {
-        if (act) {
-            R F[3];
-            if (o == 0) {
-                for (int c = 0; c < 3; ++c) F[c] = s_q[le][1 + c][node];
-            } else if (o < 4) {
-                const R mo = s_q[le][o][node];
-                for (int c = 0; c < 3; ++c) F[c] = mo * u[c];
-            } else if (o == 4) {
-                for (int c = 0; c < 3; ++c) F[c] = kin * s_q[le][1 + c][node];
-            } else if (o < 8) {
-                for (int c = 0; c < 3; ++c) F[c] = (c == o - 5) ? p : (R)0;
-            } else {
-                const R rh = gam / (gam - (R)1) * p;
-                for (int c = 0; c < 3; ++c) F[c] = rh * u[c];
+    for (int r3 = 0; r3 < 3; ++r3) {
+        if (act)
+            for (int o3 = 0; o3 < 3; ++o3) {
+                const int o = 3 * r3 + o3;
+                R F[3];
+                if (o == 0) {
+                    for (int c = 0; c < 3; ++c) F[c] = s_q[le][1 + c][node];
+                } else if (o < 4) {
+                    const R mo = s_q[le][o][node];
+                    for (int c = 0; c < 3; ++c) F[c] = mo * u[c];
+                } else if (o == 4) {
+                    for (int c = 0; c < 3; ++c) F[c] = kin * s_q[le][1 + c][node];
+                } else if (o < 8) {
+                    for (int c = 0; c < 3; ++c) F[c] = (c == o - 5) ? p : (R)0;
+                } else {
+                    const R rh = gam / (gam - (R)1) * p;
+                    for (int c = 0; c < 3; ++c) F[c] = rh * u[c];
+                }
+                for (int dd = 0; dd < 3; ++dd) {
+                    R v = 0;
+                    for (int c = 0; c < 3; ++c) v += metric<N>(g, e, node, dd, c, wj) * F[c];
+                    U[(o3 * 3 + dd) * NP + node] = v;
+                }
             }
-            for (int dd = 0; dd < 3; ++dd) {
-                R v = 0;
-                for (int c = 0; c < 3; ++c) v += metric<N>(g, e, node, dd, c, wj) * F[c];
-                s_G[le][dd][node] = v;
-            }
-        }
         __syncthreads();
-        if (act) acc[o] += div_T<N>(&s_G[le][0][0], T, node);
+        if (act)
+            for (int o3 = 0; o3 < 3; ++o3) acc[3 * r3 + o3] += div_T<N>(U + o3 * 3 * NP, T, node);
         __syncthreads();
     }
     if (!act) return;
@@ -358,91 +450,144 @@ k_explicit(const R* __restrict__ q, R* __restrict__ fNS, R* __restrict__ fS, Geo
 // =====================================================================
 // Schur pass 1: w = P (Fh/rho - M^{-1} B p / rho) (+ R1 lag), face buffers
 // =====================================================================
-template <int N, typename R>
+template <int N, typename R, bool SLOW>
 __global__ void __launch_bounds__(threads_of(N))
-k_pass1(const R* __restrict__ p, const R* __restrict__ pscale, const R* __restrict__ Fh,
+k_pass1(const int* __restrict__ elist, int64_t nel, const R* __restrict__ p, const R* __restrict__ pscale, const R* __restrict__ Fh,
         const R* __restrict__ rho, const R* __restrict__ pk, const R* __restrict__ uk, R* __restrict__ w,
-        R* __restrict__ FB, R* __restrict__ FBh, Geom<R> g, Tab<N, R> T, StageK sk) {
+        R* __restrict__ FB, R* __restrict__ FBh, Geom<R> g, const Tab<N, R>* __restrict__ Tg, StageK sk) {
     constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
+    constexpr int L_FAST = 6 * 3 * NF, L_SLOW = 4 * NF + NF + 3 * NF + 4 * 3 * NF, L_VOL = 3 * NP;
+    constexpr int UN = (L_FAST > L_SLOW ? L_FAST : L_SLOW) > L_VOL ? (L_FAST > L_SLOW ? L_FAST : L_SLOW) : L_VOL;
     __shared__ R s_p[EPB][NP];
     __shared__ R s_pk[EPB][NP];
     __shared__ R s_w[EPB][3][NP];
-    __shared__ R s_own[EPB][4][NF];
-    __shared__ R s_nb[EPB][NF];
-    __shared__ R s_fl[EPB][3][NF];
-    __shared__ R s_sub[EPB][4][3][NF];
-    __shared__ R s_G[EPB][3][NP];
+    __shared__ R s_u[EPB][UN];
     const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
-    const int64_t e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
-    const bool act = le < EPB && e < g.E;
+    __shared__ Tab<N, R> T;
+    load_tab<N, R>(Tg, &T);
+    const int64_t slot = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+    const bool act = le < EPB && slot < nel;
+    const int64_t e = act ? (elist ? (int64_t)elist[slot] : slot) : 0;
     const size_t fs = (size_t)g.E * NP;
     const R gam = (R)sk.gamma;
     const R sc = pscale ? pscale[0] : (R)1;
+    R* U = &s_u[le][0];
     if (act) {
         s_p[le][node] = p ? p[e * NP + node] : (R)0;
         s_pk[le][node] = pk[e * NP + node];
     }
+    constexpr bool slow = SLOW;
     __syncthreads();
     R acc[3] = {0, 0, 0};
     const R wj = act ? g.WJ[e * NP + node] : (R)1;
     if (p) {
-        for (int f = 0; f < 6; ++f) {
-            const int d = f >> 1, s = f & 1;
-            const int kind = act ? g.kind[e * 6 + f] : -1;
-            const int nbr = act ? g.nbr[e * 6 + f] : 0;
-            const int aux = act ? g.aux[e * 6 + f] : 0;
-            if (act && node < NF) {
-                s_own[le][0][node] = sc * face_value<N>(&s_p[le][0], T.f[s], d, node);
-                if (kind == CONF || kind == FINE)
-                    s_nb[le][node] = sc * face_value<N>(p + (size_t)nbr * NP, T.f[1 - s], d, node);
-            }
-            __syncthreads();
-            if (act) {
-                const int nit = kind == COARSE ? 4 * NF : NF;
-                for (int it = node; it < nit; it += NP) {
-                    const int hs = it / NF, pt = it - hs * NF;
-                    R pa, pb, nS[3];
-                    if (kind == COARSE) {
-                        const int fn = g.hang[nbr * 4 + hs];
-                        pa = sub_interp<N>(&s_own[le][0][0], T, hs, pt);
-                        pb = sc * face_value<N>(p + (size_t)fn * NP, T.f[1 - s], d, pt);
-                        area<N>(g, T, fn, f ^ 1, pt, nS);
-                        for (int c = 0; c < 3; ++c) nS[c] = -nS[c];
-                    } else {
-                        pa = s_own[le][0][pt];
-                        pb = kind == CONF ? s_nb[le][pt]
-                                          : (kind == FINE ? sub_interp<N>(&s_nb[le][0], T, aux & 3, pt) : pa);
-                        area<N>(g, T, e, f, pt, nS);
-                    }
+        if (!slow) {
+            // {p} nS for all face points: U[(f*3 + c)*NF + pt]
+            if (act)
+                for (int it = node; it < 6 * NF; it += NP) {
+                    const int f = it / NF, pt = it - f * NF, d = f >> 1, s = f & 1;
+                    const int kind = g.kind[e * 6 + f], nbr = g.nbr[e * 6 + f];
+                    const R pa = sc * face_value<N>(&s_p[le][0], T.f[s], d, pt);
+                    R pb = pa;
+                    if (kind == CONF) pb = sc * face_value<N>(p + (size_t)nbr * NP, T.f[1 - s], d, pt);
+                    else if (kind == FINE)
+                        pb = sc * coarse_point<N>(p + (size_t)nbr * NP, T.f[1 - s], T, d, g.aux[e * 6 + f] & 3, pt);
+                    R nS[3];
+                    area<N>(g, T, e, f, pt, nS);
                     const R avg = (R)0.5 * (pa + pb);
-                    for (int c = 0; c < 3; ++c) {
-                        if (kind == COARSE) s_sub[le][hs][c][pt] = avg * nS[c];
-                        else s_fl[le][c][pt] = avg * nS[c];
+                    for (int c = 0; c < 3; ++c) U[(f * 3 + c) * NF + pt] = avg * nS[c];
+                }
+            __syncthreads();
+            if (act)
+                for (int f = 0; f < 6; ++f) {
+                    int m, pt;
+                    split_node<N>(f >> 1, node, m, pt);
+                    const R lf = T.f[f & 1][m];
+                    for (int c = 0; c < 3; ++c) acc[c] += lf * U[(f * 3 + c) * NF + pt];
+                }
+        } else {
+            R* s_own = U;               // [NF]
+            R* s_nb = U + NF;           // [NF]
+            R* s_fl = U + 2 * NF;       // [3][NF]
+            R* s_sub = U + 5 * NF;      // [4][3][NF]
+            for (int f = 0; f < 6; ++f) {
+                const int d = f >> 1, s = f & 1;
+                const int kind = act ? g.kind[e * 6 + f] : -1;
+                const int nbr = act ? g.nbr[e * 6 + f] : 0;
+                const int aux = act ? g.aux[e * 6 + f] : 0;
+                if (act && node < NF) {
+                    s_own[node] = sc * face_value<N>(&s_p[le][0], T.f[s], d, node);
+                    if (kind == CONF || kind == FINE)
+                        s_nb[node] = sc * face_value<N>(p + (size_t)nbr * NP, T.f[1 - s], d, node);
+                }
+                __syncthreads();
+                if (act) {
+                    const int nit = kind == COARSE ? 4 * NF : NF;
+                    for (int it = node; it < nit; it += NP) {
+                        const int hs = it / NF, pt = it - hs * NF;
+                        R pa, pb, nS[3];
+                        if (kind == COARSE) {
+                            const int fn = g.hang[nbr * 4 + hs];
+                            pa = sub_interp<N>(s_own, T, hs, pt);
+                            pb = sc * face_value<N>(p + (size_t)fn * NP, T.f[1 - s], d, pt);
+                            area<N>(g, T, fn, f ^ 1, pt, nS);
+                            for (int c = 0; c < 3; ++c) nS[c] = -nS[c];
+                        } else {
+                            pa = s_own[pt];
+                            pb = kind == CONF ? s_nb[pt] : (kind == FINE ? sub_interp<N>(s_nb, T, aux & 3, pt) : pa);
+                            area<N>(g, T, e, f, pt, nS);
+                        }
+                        const R avg = (R)0.5 * (pa + pb);
+                        for (int c = 0; c < 3; ++c) {
+                            if (kind == COARSE) s_sub[(hs * 3 + c) * NF + pt] = avg * nS[c];
+                            else s_fl[c * NF + pt] = avg * nS[c];
+                        }
                     }
                 }
-            }
-            __syncthreads();
-            if (act && kind == COARSE && node < NF)
-                for (int c = 0; c < 3; ++c) {
-                    R v = 0;
-                    for (int h = 0; h < 4; ++h) v += sub_interp_T<N>(&s_sub[le][h][c][0], T, h, node);
-                    s_fl[le][c][node] = v;
+                __syncthreads();
+                if (act && kind == COARSE && node < NF)
+                    for (int c = 0; c < 3; ++c) {
+                        R v = 0;
+                        for (int h = 0; h < 4; ++h) v += sub_interp_T<N>(s_sub + (h * 3 + c) * NF, T, h, node);
+                        s_fl[c * NF + node] = v;
+                    }
+                __syncthreads();
+                if (act) {
+                    int m, pt;
+                    split_node<N>(d, node, m, pt);
+                    const R lf = T.f[s][m];
+                    for (int c = 0; c < 3; ++c) acc[c] += lf * s_fl[c * NF + pt];
                 }
-            __syncthreads();
-            if (act) {
-                int m, pt;
-                split_node<N>(d, node, m, pt);
-                const R lf = T.f[s][m];
-                for (int c = 0; c < 3; ++c) acc[c] += lf * s_fl[le][c][pt];
+                __syncthreads();
             }
         }
+        __syncthreads();
+        // volume: -int p div(phi_c)
         const R pv = act ? sc * s_p[le][node] : (R)0;
-        for (int c = 0; c < 3; ++c) {
-            if (act)
-                for (int dd = 0; dd < 3; ++dd) s_G[le][dd][node] = metric<N>(g, e, node, dd, c, wj) * pv;
+        if (!g.deformed) {
+            if (act) U[node] = wj * pv;
             __syncthreads();
-            if (act) acc[c] -= div_T<N>(&s_G[le][0][0], T, node);
-            __syncthreads();
+            if (act) {
+                const int i = node % N, j = (node / N) % N, k = node / (N * N);
+                R d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+                for (int qq = 0; qq < N; ++qq) {
+                    d0 += T.D[qq][i] * U[qq + N * (j + N * k)];
+                    d1 += T.D[qq][j] * U[i + N * (qq + N * k)];
+                    d2 += T.D[qq][k] * U[i + N * (j + N * qq)];
+                }
+                acc[0] -= d0 / (R)g.h[3 * e + 0];
+                acc[1] -= d1 / (R)g.h[3 * e + 1];
+                acc[2] -= d2 / (R)g.h[3 * e + 2];
+            }
+        } else {
+            for (int c = 0; c < 3; ++c) {
+                if (act)
+                    for (int dd = 0; dd < 3; ++dd) U[dd * NP + node] = metric<N>(g, e, node, dd, c, wj) * pv;
+                __syncthreads();
+                if (act) acc[c] -= div_T<N>(U, T, node);
+                __syncthreads();
+            }
         }
     }
     R wv[3] = {0, 0, 0};
@@ -475,17 +620,33 @@ k_pass1(const R* __restrict__ p, const R* __restrict__ pscale, const R* __restri
             s_w[le][c][node] = wv[c];
         }
     }
-    __syncthreads();
     if (!FB) return;
+    __syncthreads();
     // face buffers: (rho h)^k (w . nS) on this element's side of every face
     const R hfac = gam / (gam - (R)1);
+    if (!slow) {
+        if (act)
+            for (int it = node; it < 6 * NF; it += NP) {
+                const int f = it / NF, pt = it - f * NF, d = f >> 1, s = f & 1;
+                if (g.kind[e * 6 + f] == WALL) continue;
+                R nS[3];
+                area<N>(g, T, e, f, pt, nS);
+                const R hk = face_value<N>(&s_pk[le][0], T.f[s], d, pt);
+                const R w0 = face_value<N>(&s_w[le][0][0], T.f[s], d, pt);
+                const R w1 = face_value<N>(&s_w[le][1][0], T.f[s], d, pt);
+                const R w2 = face_value<N>(&s_w[le][2][0], T.f[s], d, pt);
+                FB[((size_t)e * 6 + f) * NF + pt] = hfac * hk * (w0 * nS[0] + w1 * nS[1] + w2 * nS[2]);
+            }
+        return;
+    }
+    R* s_own = U;   // [4][NF]
     for (int f = 0; f < 6; ++f) {
         const int d = f >> 1, s = f & 1;
         const int kind = act ? g.kind[e * 6 + f] : -1;
         const int nbr = act ? g.nbr[e * 6 + f] : 0;
         if (act && node < NF) {
-            s_own[le][0][node] = face_value<N>(&s_pk[le][0], T.f[s], d, node);
-            for (int c = 0; c < 3; ++c) s_own[le][1 + c][node] = face_value<N>(&s_w[le][c][0], T.f[s], d, node);
+            s_own[node] = face_value<N>(&s_pk[le][0], T.f[s], d, node);
+            for (int c = 0; c < 3; ++c) s_own[(1 + c) * NF + node] = face_value<N>(&s_w[le][c][0], T.f[s], d, node);
         }
         __syncthreads();
         if (act && kind != WALL) {
@@ -495,13 +656,13 @@ k_pass1(const R* __restrict__ p, const R* __restrict__ pscale, const R* __restri
                 R nS[3], vals[4];
                 if (kind == COARSE) {
                     const int fn = g.hang[nbr * 4 + hs];
-                    for (int t = 0; t < 4; ++t) vals[t] = sub_interp<N>(&s_own[le][t][0], T, hs, pt);
+                    for (int t = 0; t < 4; ++t) vals[t] = sub_interp<N>(s_own + t * NF, T, hs, pt);
                     area<N>(g, T, fn, f ^ 1, pt, nS);
                     for (int c = 0; c < 3; ++c) nS[c] = -nS[c];
                     FBh[((size_t)nbr * 4 + hs) * NF + pt] =
                         hfac * vals[0] * (vals[1] * nS[0] + vals[2] * nS[1] + vals[3] * nS[2]);
                 } else {
-                    for (int t = 0; t < 4; ++t) vals[t] = s_own[le][t][pt];
+                    for (int t = 0; t < 4; ++t) vals[t] = s_own[t * NF + pt];
                     area<N>(g, T, e, f, pt, nS);
                     FB[((size_t)e * 6 + f) * NF + pt] =
                         hfac * vals[0] * (vals[1] * nS[0] + vals[2] * nS[1] + vals[3] * nS[2]);
@@ -515,58 +676,92 @@ k_pass1(const R* __restrict__ p, const R* __restrict__ pscale, const R* __restri
 // =====================================================================
 // Schur pass 2: out = alpha (Gp - p/(gamma-1) - M^{-1} C^k w - [R2] M^{-1} M_g w)
 // =====================================================================
-template <int N, typename R>
+template <int N, typename R, bool SLOW>
 __global__ void __launch_bounds__(threads_of(N))
-k_pass2(const R* __restrict__ Gp, const R* __restrict__ p, const R* __restrict__ pscale,
+k_pass2(const int* __restrict__ elist, int64_t nel, const R* __restrict__ Gp, const R* __restrict__ p, const R* __restrict__ pscale,
         const R* __restrict__ w, const R* __restrict__ pk, const R* __restrict__ rho, const R* __restrict__ FB,
-        const R* __restrict__ FBh, R* __restrict__ out, R alpha, int dual, Geom<R> g, Tab<N, R> T, StageK sk) {
+        const R* __restrict__ FBh, R* __restrict__ out, R alpha, int dual, Geom<R> g,
+        const Tab<N, R>* __restrict__ Tg, StageK sk, const R* __restrict__ V, int nv, int64_t ldv,
+        double* __restrict__ partial) {
     constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
-    __shared__ R s_fl[EPB][NF];
-    __shared__ R s_sub[EPB][4][NF];
-    __shared__ R s_G[EPB][3][NP];
+    constexpr int L_FAST = 6 * NF, L_SLOW = NF + 4 * NF, L_VOL = 3 * NP;
+    constexpr int UN = (L_FAST > L_SLOW ? L_FAST : L_SLOW) > L_VOL ? (L_FAST > L_SLOW ? L_FAST : L_SLOW) : L_VOL;
+    __shared__ R s_u[EPB][UN];
     const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
-    const int64_t e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
-    const bool act = le < EPB && e < g.E;
+    __shared__ Tab<N, R> T;
+    load_tab<N, R>(Tg, &T);
+    const int64_t slot = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+    const bool act = le < EPB && slot < nel;
+    const int64_t e = act ? (elist ? (int64_t)elist[slot] : slot) : 0;
     const size_t fs = (size_t)g.E * NP;
     const R gam = (R)sk.gamma;
+    R* U = &s_u[le][0];
+    constexpr bool slow = SLOW;
+    __syncthreads();
     R acc = 0;
-    for (int f = 0; f < 6; ++f) {
-        const int d = f >> 1, s = f & 1;
-        const int kind = act ? g.kind[e * 6 + f] : -1;
-        const int nbr = act ? g.nbr[e * 6 + f] : 0;
-        const int aux = act ? g.aux[e * 6 + f] : 0;
-        if (act) {
-            const int nit = kind == COARSE ? 4 * NF : NF;
-            for (int it = node; it < nit; it += NP) {
-                const int hs = it / NF, pt = it - hs * NF;
-                if (kind == COARSE) {
-                    const int fn = g.hang[nbr * 4 + hs];
-                    s_sub[le][hs][pt] = (R)0.5 * (FBh[((size_t)nbr * 4 + hs) * NF + pt] -
-                                                  FB[((size_t)fn * 6 + (f ^ 1)) * NF + pt]);
-                } else if (kind == CONF) {
-                    s_fl[le][pt] = (R)0.5 * (FB[((size_t)e * 6 + f) * NF + pt] - FB[((size_t)nbr * 6 + (f ^ 1)) * NF + pt]);
-                } else if (kind == FINE) {
-                    s_fl[le][pt] = (R)0.5 * (FB[((size_t)e * 6 + f) * NF + pt] -
+    if (!slow) {
+        if (act)
+            for (int it = node; it < 6 * NF; it += NP) {
+                const int f = it / NF, pt = it - f * NF;
+                const int kind = g.kind[e * 6 + f], nbr = g.nbr[e * 6 + f];
+                R v = 0;
+                if (kind == CONF)
+                    v = (R)0.5 * (FB[((size_t)e * 6 + f) * NF + pt] - FB[((size_t)nbr * 6 + (f ^ 1)) * NF + pt]);
+                else if (kind == FINE) {
+                    const int aux = g.aux[e * 6 + f];
+                    v = (R)0.5 * (FB[((size_t)e * 6 + f) * NF + pt] - FBh[((size_t)(aux >> 2) * 4 + (aux & 3)) * NF + pt]);
+                }
+                U[f * NF + pt] = v;
+            }
+        __syncthreads();
+        if (act)
+            for (int f = 0; f < 6; ++f) {
+                int m, pt;
+                split_node<N>(f >> 1, node, m, pt);
+                acc += T.f[f & 1][m] * U[f * NF + pt];
+            }
+    } else {
+        R* s_fl = U;          // [NF]
+        R* s_sub = U + NF;    // [4][NF]
+        for (int f = 0; f < 6; ++f) {
+            const int d = f >> 1, s = f & 1;
+            const int kind = act ? g.kind[e * 6 + f] : -1;
+            const int nbr = act ? g.nbr[e * 6 + f] : 0;
+            const int aux = act ? g.aux[e * 6 + f] : 0;
+            if (act) {
+                const int nit = kind == COARSE ? 4 * NF : NF;
+                for (int it = node; it < nit; it += NP) {
+                    const int hs = it / NF, pt = it - hs * NF;
+                    if (kind == COARSE) {
+                        const int fn = g.hang[nbr * 4 + hs];
+                        s_sub[hs * NF + pt] = (R)0.5 * (FBh[((size_t)nbr * 4 + hs) * NF + pt] -
+                                                        FB[((size_t)fn * 6 + (f ^ 1)) * NF + pt]);
+                    } else if (kind == CONF) {
+                        s_fl[pt] = (R)0.5 * (FB[((size_t)e * 6 + f) * NF + pt] - FB[((size_t)nbr * 6 + (f ^ 1)) * NF + pt]);
+                    } else if (kind == FINE) {
+                        s_fl[pt] = (R)0.5 * (FB[((size_t)e * 6 + f) * NF + pt] -
                                              FBh[((size_t)(aux >> 2) * 4 + (aux & 3)) * NF + pt]);
-                } else {
-                    s_fl[le][pt] = 0;
+                    } else {
+                        s_fl[pt] = 0;
+                    }
                 }
             }
+            __syncthreads();
+            if (act && kind == COARSE && node < NF) {
+                R v = 0;
+                for (int h = 0; h < 4; ++h) v += sub_interp_T<N>(s_sub + h * NF, T, h, node);
+                s_fl[node] = v;
+            }
+            __syncthreads();
+            if (act) {
+                int m, pt;
+                split_node<N>(d, node, m, pt);
+                acc += T.f[s][m] * s_fl[pt];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if (act && kind == COARSE && node < NF) {
-            R v = 0;
-            for (int h = 0; h < 4; ++h) v += sub_interp_T<N>(&s_sub[le][h][0], T, h, node);
-            s_fl[le][node] = v;
-        }
-        __syncthreads();
-        if (act) {
-            int m, pt;
-            split_node<N>(d, node, m, pt);
-            acc += T.f[s][m] * s_fl[le][pt];
-        }
-        __syncthreads();
     }
+    __syncthreads();
     R wv[3] = {0, 0, 0}, wj = 1, rh = 0;
     if (act) {
         wj = g.WJ[e * NP + node];
@@ -575,105 +770,175 @@ k_pass2(const R* __restrict__ Gp, const R* __restrict__ p, const R* __restrict__
         for (int dd = 0; dd < 3; ++dd) {
             R v = 0;
             for (int c = 0; c < 3; ++c) v += metric<N>(g, e, node, dd, c, wj) * wv[c];
-            s_G[le][dd][node] = rh * v;
+            U[dd * NP + node] = rh * v;
         }
     }
     __syncthreads();
-    if (!act) return;
-    acc -= div_T<N>(&s_G[le][0][0], T, node);
-    const R cdt = (R)sk.c_dt;
-    R res = Gp ? Gp[e * NP + node] : (R)0;
-    if (p) res -= (pscale ? pscale[0] : (R)1) * p[e * NP + node] / (gam - (R)1);
-    res -= cdt * acc / wj;
-    if (sk.scheme == 2) res -= cdt * (R)sk.g * rho[e * NP + node] * wv[2];
-    res *= alpha;
-    if (dual) res *= wj;
-    out[e * NP + node] = res;
+    R res = 0;
+    if (act) {
+        acc -= div_T<N>(U, T, node);
+        const R cdt = (R)sk.c_dt;
+        res = Gp ? Gp[e * NP + node] : (R)0;
+        if (p) res -= (pscale ? pscale[0] : (R)1) * p[e * NP + node] / (gam - (R)1);
+        res -= cdt * acc / wj;
+        if (sk.scheme == 2) res -= cdt * (R)sk.g * rho[e * NP + node] * wv[2];
+        res *= alpha;
+        out[e * NP + node] = dual ? res * wj : res;
+    }
+    if (!V) return;
+    // fused Gram-Schmidt projections: partial sums of <V_i, out>_M (i < nv)
+    // and <out, out>_M for this workgroup, in a fixed order
+    __shared__ double s_red[threads_of(N) / 64][33];
+    const double wz = act ? (double)wj * (double)res : 0.0;
+    const int lane = tid & 63, wid = tid >> 6;
+    for (int i0 = 0; i0 <= nv; i0 += 8) {
+        double v[8];   // eight projections per batch so that their loads overlap
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = i0 + k;
+            v[k] = i < nv ? (act ? wz * (double)V[(int64_t)i * ldv + e * NP + node] : 0.0)
+                          : (i == nv ? wz * (double)res : 0.0);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+        if (lane == 0)
+            for (int k = 0; k < 8; ++k)
+                if (i0 + k <= nv) s_red[wid][i0 + k] = v[k];
+    }
+    __syncthreads();
+    if (tid <= nv) {
+        double t = 0;
+        for (int k = 0; k < threads_of(N) / 64; ++k) t += s_red[k][tid];
+        partial[(size_t)blockIdx.x * (nv + 1) + tid] = t;
+    }
 }
 
 // =====================================================================
 // Picard refresh: Gp = G0h - M^{-1} Lambda^k - rho kappa^k [- R1 gravity lag]
 // =====================================================================
 template <int N>
+__device__ __forceinline__ double lambda_flux(const double* a, const double* b, const double* nS, double gm1) {
+    const double dS = sqrt(nS[0] * nS[0] + nS[1] * nS[1] + nS[2] * nS[2]);
+    const double unA = (a[0] * nS[0] + a[1] * nS[1] + a[2] * nS[2]) / dS;
+    const double unB = (b[0] * nS[0] + b[1] * nS[1] + b[2] * nS[2]) / dS;
+    const double lam = fmax(fabs(unA), fabs(unB));
+    return 0.5 * lam * (a[3] - b[3]) / gm1 * dS;
+}
+
+template <int N, bool SLOW>
 __global__ void __launch_bounds__(threads_of(N))
-k_lambda(const double* __restrict__ pk, const double* __restrict__ uk, const double* __restrict__ rho,
-         const double* __restrict__ G0h, double* __restrict__ Gp, Geom<double> g, Tab<N, double> T, StageK sk) {
+k_lambda(const int* __restrict__ elist, int64_t nel, const double* __restrict__ pk, const double* __restrict__ uk, const double* __restrict__ rho,
+         const double* __restrict__ G0h, double* __restrict__ Gp, Geom<double> g,
+         const Tab<N, double>* __restrict__ Tg, StageK sk) {
     using R = double;
     constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
+    constexpr int L_FAST = 6 * NF, L_SLOW = 4 * NF + 4 * NF + NF + 4 * NF;
+    constexpr int UN = L_FAST > L_SLOW ? L_FAST : L_SLOW;
     __shared__ R s_q[EPB][4][NP];
-    __shared__ R s_own[EPB][4][NF];
-    __shared__ R s_nb[EPB][4][NF];
-    __shared__ R s_fl[EPB][NF];
-    __shared__ R s_sub[EPB][4][NF];
+    __shared__ R s_u[EPB][UN];
     const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
-    const int64_t e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
-    const bool act = le < EPB && e < g.E;
+    __shared__ Tab<N, R> T;
+    load_tab<N, R>(Tg, &T);
+    const int64_t slot = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+    const bool act = le < EPB && slot < nel;
+    const int64_t e = act ? (elist ? (int64_t)elist[slot] : slot) : 0;
     const size_t fs = (size_t)g.E * NP;
     const R gm1 = sk.gamma - 1.0;
+    R* U = &s_u[le][0];
     // fields 0..2: u^k, 3: p^k
     auto src = [&](int t) -> const R* { return t < 3 ? uk + t * fs : pk; };
     if (act)
         for (int t = 0; t < 4; ++t) s_q[le][t][node] = src(t)[e * NP + node];
+    constexpr bool slow = SLOW;
     __syncthreads();
     R acc = 0;
-    for (int f = 0; f < 6; ++f) {
-        const int d = f >> 1, s = f & 1;
-        const int kind = act ? g.kind[e * 6 + f] : -1;
-        const int nbr = act ? g.nbr[e * 6 + f] : 0;
-        const int aux = act ? g.aux[e * 6 + f] : 0;
-        if (act && node < NF) {
-            for (int t = 0; t < 4; ++t) s_own[le][t][node] = face_value<N>(&s_q[le][t][0], T.f[s], d, node);
-            if (kind == CONF || kind == FINE)
-                for (int t = 0; t < 4; ++t)
-                    s_nb[le][t][node] = face_value<N>(src(t) + (size_t)nbr * NP, T.f[1 - s], d, node);
-        }
-        __syncthreads();
-        if (act) {
-            const int nit = kind == COARSE ? 4 * NF : NF;
-            for (int it = node; it < nit; it += NP) {
-                const int hs = it / NF, pt = it - hs * NF;
-                R a[4], b[4], nS[3];
-                if (kind == WALL) {
-                    s_fl[le][pt] = 0;
-                    continue;
-                }
-                if (kind == COARSE) {
-                    const int fn = g.hang[nbr * 4 + hs];
+    if (!slow) {
+        if (act)
+            for (int it = node; it < 6 * NF; it += NP) {
+                const int f = it / NF, pt = it - f * NF, d = f >> 1, s = f & 1;
+                const int kind = g.kind[e * 6 + f], nbr = g.nbr[e * 6 + f];
+                R v = 0;
+                if (kind != WALL) {
+                    R a[4], b[4], nS[3];
                     for (int t = 0; t < 4; ++t) {
-                        a[t] = sub_interp<N>(&s_own[le][t][0], T, hs, pt);
-                        b[t] = face_value<N>(src(t) + (size_t)fn * NP, T.f[1 - s], d, pt);
-                    }
-                    area<N>(g, T, fn, f ^ 1, pt, nS);
-                    for (int c = 0; c < 3; ++c) nS[c] = -nS[c];
-                } else {
-                    for (int t = 0; t < 4; ++t) {
-                        a[t] = s_own[le][t][pt];
-                        b[t] = kind == CONF ? s_nb[le][t][pt] : sub_interp<N>(&s_nb[le][t][0], T, aux & 3, pt);
+                        a[t] = face_value<N>(&s_q[le][t][0], T.f[s], d, pt);
+                        b[t] = kind == CONF ? face_value<N>(src(t) + (size_t)nbr * NP, T.f[1 - s], d, pt)
+                                            : coarse_point<N>(src(t) + (size_t)nbr * NP, T.f[1 - s], T, d,
+                                                              g.aux[e * 6 + f] & 3, pt);
                     }
                     area<N>(g, T, e, f, pt, nS);
+                    v = lambda_flux<N>(a, b, nS, gm1);
                 }
-                const R dS = sqrt(nS[0] * nS[0] + nS[1] * nS[1] + nS[2] * nS[2]);
-                const R unA = (a[0] * nS[0] + a[1] * nS[1] + a[2] * nS[2]) / dS;
-                const R unB = (b[0] * nS[0] + b[1] * nS[1] + b[2] * nS[2]) / dS;
-                const R lam = fmax(fabs(unA), fabs(unB));
-                const R v = 0.5 * lam * (a[3] - b[3]) / gm1 * dS;
-                if (kind == COARSE) s_sub[le][hs][pt] = v;
-                else s_fl[le][pt] = v;
+                U[f * NF + pt] = v;
             }
-        }
         __syncthreads();
-        if (act && kind == COARSE && node < NF) {
-            R v = 0;
-            for (int h = 0; h < 4; ++h) v += sub_interp_T<N>(&s_sub[le][h][0], T, h, node);
-            s_fl[le][node] = v;
+        if (act)
+            for (int f = 0; f < 6; ++f) {
+                int m, pt;
+                split_node<N>(f >> 1, node, m, pt);
+                acc += T.f[f & 1][m] * U[f * NF + pt];
+            }
+    } else {
+        R* s_own = U;              // [4][NF]
+        R* s_nb = U + 4 * NF;      // [4][NF]
+        R* s_fl = U + 8 * NF;      // [NF]
+        R* s_sub = U + 9 * NF;     // [4][NF]
+        for (int f = 0; f < 6; ++f) {
+            const int d = f >> 1, s = f & 1;
+            const int kind = act ? g.kind[e * 6 + f] : -1;
+            const int nbr = act ? g.nbr[e * 6 + f] : 0;
+            const int aux = act ? g.aux[e * 6 + f] : 0;
+            if (act && node < NF) {
+                for (int t = 0; t < 4; ++t) s_own[t * NF + node] = face_value<N>(&s_q[le][t][0], T.f[s], d, node);
+                if (kind == CONF || kind == FINE)
+                    for (int t = 0; t < 4; ++t)
+                        s_nb[t * NF + node] = face_value<N>(src(t) + (size_t)nbr * NP, T.f[1 - s], d, node);
+            }
+            __syncthreads();
+            if (act) {
+                const int nit = kind == COARSE ? 4 * NF : NF;
+                for (int it = node; it < nit; it += NP) {
+                    const int hs = it / NF, pt = it - hs * NF;
+                    R a[4], b[4], nS[3];
+                    if (kind == WALL) {
+                        s_fl[pt] = 0;
+                        continue;
+                    }
+                    if (kind == COARSE) {
+                        const int fn = g.hang[nbr * 4 + hs];
+                        for (int t = 0; t < 4; ++t) {
+                            a[t] = sub_interp<N>(s_own + t * NF, T, hs, pt);
+                            b[t] = face_value<N>(src(t) + (size_t)fn * NP, T.f[1 - s], d, pt);
+                        }
+                        area<N>(g, T, fn, f ^ 1, pt, nS);
+                        for (int c = 0; c < 3; ++c) nS[c] = -nS[c];
+                    } else {
+                        for (int t = 0; t < 4; ++t) {
+                            a[t] = s_own[t * NF + pt];
+                            b[t] = kind == CONF ? s_nb[t * NF + pt] : sub_interp<N>(s_nb + t * NF, T, aux & 3, pt);
+                        }
+                        area<N>(g, T, e, f, pt, nS);
+                    }
+                    const R v = lambda_flux<N>(a, b, nS, gm1);
+                    if (kind == COARSE) s_sub[hs * NF + pt] = v;
+                    else s_fl[pt] = v;
+                }
+            }
+            __syncthreads();
+            if (act && kind == COARSE && node < NF) {
+                R v = 0;
+                for (int h = 0; h < 4; ++h) v += sub_interp_T<N>(s_sub + h * NF, T, h, node);
+                s_fl[node] = v;
+            }
+            __syncthreads();
+            if (act) {
+                int m, pt;
+                split_node<N>(d, node, m, pt);
+                acc += T.f[s][m] * s_fl[pt];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if (act) {
-            int m, pt;
-            split_node<N>(d, node, m, pt);
-            acc += T.f[s][m] * s_fl[le][pt];
-        }
-        __syncthreads();
     }
     if (!act) return;
     const R wj = g.WJ[e * NP + node];
@@ -685,43 +950,60 @@ k_lambda(const double* __restrict__ pk, const double* __restrict__ uk, const dou
 }
 
 // ------------------------------------------------------------ launchers
-template <typename R, int N>
-static void explicit_n(const DevMesh& m, const HostTab& t, const PhysK& ph, const R* q, R* fNS, R* fS,
-                       hipStream_t st) {
-    const int64_t nb = (m.E + epb_of(N) - 1) / epb_of(N);
-    hipLaunchKernelGGL((k_explicit<N, R>), dim3((unsigned)nb), dim3(threads_of(N)), 0, st, q, fNS, fS, geom<R>(m),
-                       to_tab<N, R>(t), ph, m.sponge);
+template <typename R>
+static const void* tab_ptr(const DevMesh& m);
+template <>
+const void* tab_ptr<double>(const DevMesh& m) { return m.tab; }
+template <>
+const void* tab_ptr<float>(const DevMesh& m) { return m.tabf; }
+
+// Launches kern over all elements, or (meshes with hanging faces) the
+// face-by-face instance over the elements owning a coarse hanging face and
+// the all-faces instance over the others.
+template <int N, typename KF, typename KS, typename... Args>
+static void launch_split(const DevMesh& m, KF fast, KS slow, hipStream_t st, Args... args) {
+    constexpr int EPB = epb_of(N);
+    auto go = [&](auto kern, const int* list, int64_t n) {
+        if (n <= 0) return;
+        const int64_t nb = (n + EPB - 1) / EPB;
+        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(threads_of(N)), 0, st, list, n, args...);
+    };
+    if (m.ncoarse == 0) {
+        go(fast, nullptr, m.E);
+    } else {
+        go(fast, m.reg_list, m.E - m.ncoarse);
+        go(slow, m.crs_list, m.ncoarse);
+    }
 }
 
-template <typename R>
-void launch_explicit(const DevMesh& m, const HostTab& t, const PhysK& ph, const R* q, R* fNS, R* fS,
-                     hipStream_t st) {
-    switch (m.n) {
-        case 2: explicit_n<R, 2>(m, t, ph, q, fNS, fS, st); break;
-        case 3: explicit_n<R, 3>(m, t, ph, q, fNS, fS, st); break;
-        case 4: explicit_n<R, 4>(m, t, ph, q, fNS, fS, st); break;
-        case 5: explicit_n<R, 5>(m, t, ph, q, fNS, fS, st); break;
+#define IMX_DISPATCH_N(n, CALL) \
+    switch (n) {                 \
+        case 2: CALL(2); break;  \
+        case 3: CALL(3); break;  \
+        case 4: CALL(4); break;  \
+        case 5: CALL(5); break;  \
     }
+
+template <typename R>
+void launch_explicit(const DevMesh& m, const HostTab&, const PhysK& ph, const R* q, R* fNS, R* fS,
+                     hipStream_t st) {
+#define CALL(NN)                                                                                      \
+    launch_split<NN>(m, k_explicit<NN, R, false>, k_explicit<NN, R, true>, st, q, fNS, fS, geom<R>(m), \
+                     (const Tab<NN, R>*)tab_ptr<R>(m), ph, m.sponge)
+    IMX_DISPATCH_N(m.n, CALL)
+#undef CALL
 }
 template void launch_explicit<double>(const DevMesh&, const HostTab&, const PhysK&, const double*, double*,
                                       double*, hipStream_t);
 
-template <typename R, int N>
-static void pass1_n(const DevMesh& m, const HostTab& t, const StageK& sk, const R* p, const R* pscale,
-                    const R* Fh, const R* rho, const R* pk, const R* uk, R* w, R* FB, R* FBh, hipStream_t st) {
-    const int64_t nb = (m.E + epb_of(N) - 1) / epb_of(N);
-    hipLaunchKernelGGL((k_pass1<N, R>), dim3((unsigned)nb), dim3(threads_of(N)), 0, st, p, pscale, Fh, rho, pk, uk,
-                       w, FB, FBh, geom<R>(m), to_tab<N, R>(t), sk);
-}
 template <typename R>
-void launch_pass1(const DevMesh& m, const HostTab& t, const StageK& sk, const R* p, const R* pscale,
+void launch_pass1(const DevMesh& m, const HostTab&, const StageK& sk, const R* p, const R* pscale,
                   const R* Fh, const R* rho, const R* pk, const R* uk, R* w, R* FB, R* FBh, hipStream_t st) {
-    switch (m.n) {
-        case 2: pass1_n<R, 2>(m, t, sk, p, pscale, Fh, rho, pk, uk, w, FB, FBh, st); break;
-        case 3: pass1_n<R, 3>(m, t, sk, p, pscale, Fh, rho, pk, uk, w, FB, FBh, st); break;
-        case 4: pass1_n<R, 4>(m, t, sk, p, pscale, Fh, rho, pk, uk, w, FB, FBh, st); break;
-        case 5: pass1_n<R, 5>(m, t, sk, p, pscale, Fh, rho, pk, uk, w, FB, FBh, st); break;
-    }
+#define CALL(NN)                                                                                         \
+    launch_split<NN>(m, k_pass1<NN, R, false>, k_pass1<NN, R, true>, st, p, pscale, Fh, rho, pk, uk, w, FB, \
+                     FBh, geom<R>(m), (const Tab<NN, R>*)tab_ptr<R>(m), sk)
+    IMX_DISPATCH_N(m.n, CALL)
+#undef CALL
 }
 template void launch_pass1<double>(const DevMesh&, const HostTab&, const StageK&, const double*, const double*,
                                    const double*, const double*, const double*, const double*, double*, double*,
@@ -731,46 +1013,55 @@ template void launch_pass1<float>(const DevMesh&, const HostTab&, const StageK&,
                                   hipStream_t);
 
 template <typename R, int N>
-static void pass2_n(const DevMesh& m, const HostTab& t, const StageK& sk, const R* Gp, const R* p,
-                    const R* pscale, const R* w, const R* pk, const R* rho, const R* FB, const R* FBh, R* out,
-                    double alpha, int dual, hipStream_t st) {
-    const int64_t nb = (m.E + epb_of(N) - 1) / epb_of(N);
-    hipLaunchKernelGGL((k_pass2<N, R>), dim3((unsigned)nb), dim3(threads_of(N)), 0, st, Gp, p, pscale, w, pk, rho,
-                       FB, FBh, out, (R)alpha, dual, geom<R>(m), to_tab<N, R>(t), sk);
+static void pass2_n(const DevMesh& m, const StageK& sk, const R* Gp, const R* p, const R* pscale, const R* w,
+                    const R* pk, const R* rho, const R* FB, const R* FBh, R* out, double alpha, int dual,
+                    const R* V, int nv, double* partial, double* dots, hipStream_t st) {
+    constexpr int EPB = epb_of(N);
+    const Tab<N, R>* T = (const Tab<N, R>*)tab_ptr<R>(m);
+    const int64_t L = m.Lp;
+    const int64_t nf = m.ncoarse ? m.E - m.ncoarse : m.E, ns = m.ncoarse;
+    const int64_t bf = (nf + EPB - 1) / EPB, bs = (ns + EPB - 1) / EPB;
+    if (bf > 0)
+        hipLaunchKernelGGL((k_pass2<N, R, false>), dim3((unsigned)bf), dim3(threads_of(N)), 0, st,
+                           m.ncoarse ? m.reg_list : nullptr, nf, Gp, p, pscale, w, pk, rho, FB, FBh, out, (R)alpha,
+                           dual, geom<R>(m), T, sk, V, nv, L, partial);
+    if (bs > 0)
+        hipLaunchKernelGGL((k_pass2<N, R, true>), dim3((unsigned)bs), dim3(threads_of(N)), 0, st, m.crs_list, ns, Gp,
+                           p, pscale, w, pk, rho, FB, FBh, out, (R)alpha, dual, geom<R>(m), T, sk, V, nv, L,
+                           partial ? partial + (size_t)bf * (nv + 1) : nullptr);
+    if (V) launch_final_sum(partial, (int)(bf + bs), nv + 1, dots, st);
 }
+
 template <typename R>
-void launch_pass2(const DevMesh& m, const HostTab& t, const StageK& sk, const R* Gp, const R* p,
+void launch_pass2(const DevMesh& m, const HostTab&, const StageK& sk, const R* Gp, const R* p,
                   const R* pscale, const R* w, const R* pk, const R* rho, const R* FB, const R* FBh, R* out,
-                  double alpha, int dual, hipStream_t st) {
-    switch (m.n) {
-        case 2: pass2_n<R, 2>(m, t, sk, Gp, p, pscale, w, pk, rho, FB, FBh, out, alpha, dual, st); break;
-        case 3: pass2_n<R, 3>(m, t, sk, Gp, p, pscale, w, pk, rho, FB, FBh, out, alpha, dual, st); break;
-        case 4: pass2_n<R, 4>(m, t, sk, Gp, p, pscale, w, pk, rho, FB, FBh, out, alpha, dual, st); break;
-        case 5: pass2_n<R, 5>(m, t, sk, Gp, p, pscale, w, pk, rho, FB, FBh, out, alpha, dual, st); break;
-    }
+                  double alpha, int dual, hipStream_t st, const R* V, int nv, double* partial, double* dots) {
+#define CALL(NN) pass2_n<R, NN>(m, sk, Gp, p, pscale, w, pk, rho, FB, FBh, out, alpha, dual, V, nv, partial, dots, st)
+    IMX_DISPATCH_N(m.n, CALL)
+#undef CALL
 }
 template void launch_pass2<double>(const DevMesh&, const HostTab&, const StageK&, const double*, const double*,
                                    const double*, const double*, const double*, const double*, const double*,
-                                   const double*, double*, double, int, hipStream_t);
+                                   const double*, double*, double, int, hipStream_t, const double*, int, double*,
+                                   double*);
 template void launch_pass2<float>(const DevMesh&, const HostTab&, const StageK&, const float*, const float*,
                                   const float*, const float*, const float*, const float*, const float*,
-                                  const float*, float*, double, int, hipStream_t);
+                                  const float*, float*, double, int, hipStream_t, const float*, int, double*,
+                                  double*);
 
-template <int N>
-static void lambda_n(const DevMesh& m, const HostTab& t, const StageK& sk, const double* pk, const double* uk,
-                     const double* rho, const double* G0h, double* Gp, hipStream_t st) {
-    const int64_t nb = (m.E + epb_of(N) - 1) / epb_of(N);
-    hipLaunchKernelGGL((k_lambda<N>), dim3((unsigned)nb), dim3(threads_of(N)), 0, st, pk, uk, rho, G0h, Gp,
-                       geom<double>(m), to_tab<N, double>(t), sk);
+size_t pass2_partial_count(const DevMesh& m) {
+    const int e = m.n == 2 ? 16 : (m.n == 3 ? 9 : (m.n == 4 ? 4 : 2));
+    const int64_t nf = m.ncoarse ? m.E - m.ncoarse : m.E;
+    return (size_t)((nf + e - 1) / e + (m.ncoarse + e - 1) / e) * 33;
 }
-void launch_lambda(const DevMesh& m, const HostTab& t, const StageK& sk, const double* pk, const double* uk,
+
+void launch_lambda(const DevMesh& m, const HostTab&, const StageK& sk, const double* pk, const double* uk,
                    const double* rho, const double* G0h, double* Gp, hipStream_t st) {
-    switch (m.n) {
-        case 2: lambda_n<2>(m, t, sk, pk, uk, rho, G0h, Gp, st); break;
-        case 3: lambda_n<3>(m, t, sk, pk, uk, rho, G0h, Gp, st); break;
-        case 4: lambda_n<4>(m, t, sk, pk, uk, rho, G0h, Gp, st); break;
-        case 5: lambda_n<5>(m, t, sk, pk, uk, rho, G0h, Gp, st); break;
-    }
+#define CALL(NN)                                                                                    \
+    launch_split<NN>(m, k_lambda<NN, false>, k_lambda<NN, true>, st, pk, uk, rho, G0h, Gp, geom<double>(m), \
+                     (const Tab<NN, double>*)m.tab, sk)
+    IMX_DISPATCH_N(m.n, CALL)
+#undef CALL
 }
 
 }  // namespace imx

@@ -11,6 +11,7 @@ namespace imx {
 // precision inner loop) binary32 shadows.
 struct DevMesh {
     int64_t E = 0, nh = 0;
+    int64_t Lp = 0;                 // E*Np rounded up to a multiple of 4 (Krylov vector stride)
     int n = 0, Np = 0, Nf = 0;
     int deformed = 0;
     const int* kind = nullptr;      // [E*6]
@@ -25,6 +26,11 @@ struct DevMesh {
     const float* WJf = nullptr;
     const float* Gf = nullptr;
     const float* nSf = nullptr;
+    int64_t ncoarse = 0;            // elements owning a coarse hanging face
+    const int* reg_list = nullptr;  // [E - ncoarse] the other elements
+    const int* crs_list = nullptr;  // [ncoarse]
+    const void* tab = nullptr;      // basis tables (binary64), device
+    const void* tabf = nullptr;     // basis tables (binary32), device
 };
 
 struct PhysK {
@@ -46,6 +52,9 @@ struct HostTab {
     double D[64], f[16], H[2 * 64], w[8];
 };
 HostTab make_tab(const Basis1D& b);
+// device layout of the basis tables of degree n-1: size and host-side image
+size_t tab_bytes(int n, int f32);
+void fill_tab(const HostTab& h, int f32, void* out);
 
 // --- element kernels (templated on the floating type R = double / float)
 template <typename R>
@@ -60,10 +69,15 @@ void launch_pass1(const DevMesh& m, const HostTab& t, const StageK& sk, const R*
                   hipStream_t st);
 
 // out = alpha * (Gp - sc*p/(gamma-1) - M^{-1}C^k w - [R2] c g rho w_z) [* WJ if dual]
+// With V != null also dots[i] = <V_i, out>_M (i < nv) and dots[nv] = <out, out>_M
+// (partial: pass2_partial_count(m) doubles of scratch).
 template <typename R>
 void launch_pass2(const DevMesh& m, const HostTab& t, const StageK& sk, const R* Gp, const R* p,
                   const R* pscale, const R* w, const R* pk, const R* rho, const R* FB, const R* FBh,
-                  R* out, double alpha, int dual, hipStream_t st);
+                  R* out, double alpha, int dual, hipStream_t st, const R* V = nullptr, int nv = 0,
+                  double* partial = nullptr, double* dots = nullptr);
+size_t pass2_partial_count(const DevMesh& m);
+void launch_final_sum(const double* partial, int nb, int nv, double* out, hipStream_t st);
 
 // Gp = G0h - M^{-1}Lambda^k - rho kappa^k [R1: - c g rho uk_z]
 void launch_lambda(const DevMesh& m, const HostTab& t, const StageK& sk, const double* pk, const double* uk,
@@ -85,8 +99,10 @@ void launch_final_update(int64_t L, const double* y, const double* const* fNS, c
 void launch_scale_div(int64_t L, int nf, const double* in, const double* WJ, double* out, hipStream_t st);
 
 // --- reductions: partial sums per block then a fixed-order final sum
-constexpr int RED_BLOCKS = 1024;
+constexpr int RED_BLOCKS = 4096;
 constexpr int MAXV = 33;   // restart length <= 32
+// Krylov vectors are stored with L rounded up to a multiple of 4 (padding is
+// zero and carries zero weight), so the streaming kernels use 16-byte lanes.
 // out[i] = sum WJ * V_i * z  (i < nv), V_i = V + i*ldv, all length L (R = double or float)
 template <typename R>
 void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R* WJ, double* partial,

@@ -61,7 +61,7 @@ struct imx_solver {
     imx_numerics num{};
     hipStream_t st = nullptr;
     int device = 0;
-    int64_t E = 0, L = 0;
+    int64_t E = 0, L = 0, Lp = 0;
     int Np = 0, Nf = 0, m = 30;
     bool bound = false, mixed = false;
     size_t ws_bytes = 0;
@@ -75,7 +75,7 @@ struct imx_solver {
     double *p = nullptr, *pn = nullptr, *u = nullptr, *un = nullptr, *w = nullptr;
     double *FB = nullptr, *FBh = nullptr;
     double *V = nullptr, *z = nullptr, *z1 = nullptr, *b = nullptr;
-    double *partial = nullptr, *dsc = nullptr;   // device scalars
+    double *partial = nullptr, *partial2 = nullptr, *dsc = nullptr;   // reduction scratch, device scalars
     // binary32 shadows for the mixed inner loop
     float *Vf = nullptr, *zf = nullptr, *z1f = nullptr, *wf = nullptr, *FBf = nullptr, *FBhf = nullptr;
     float *rhof = nullptr, *pkf = nullptr, *WJf = nullptr, *Gf = nullptr, *nSf = nullptr, *xf = nullptr;
@@ -117,8 +117,23 @@ static size_t layout(imx_solver* s, char* base) {
     dm.nbr = I(E * 6);
     dm.aux = I(E * 6);
     dm.hang = I(std::max<int64_t>(m.nh, 1) * 4);
+    {
+        int64_t nc = 0;
+        for (int64_t e = 0; e < E; ++e) {
+            bool c = false;
+            for (int f = 0; f < 6; ++f) c |= m.fkind[6 * e + f] == COARSE;
+            nc += c;
+        }
+        dm.ncoarse = nc;
+        if (nc) {
+            dm.reg_list = I(E - nc + 1);
+            dm.crs_list = I(nc);
+        }
+    }
     dm.h = D(E * 3);
-    dm.WJ = D(L);
+    dm.tab = D(tab_bytes(m.n, 0) / 8 + 1);
+    dm.tabf = D(tab_bytes(m.n, 1) / 8 + 1);
+    dm.WJ = D(s->Lp);
     if (m.deformed) {
         dm.G = D(9 * L);
         dm.nS = D((size_t)E * 6 * 3 * Nf);
@@ -135,18 +150,19 @@ static size_t layout(imx_solver* s, char* base) {
     s->Fh = D(3 * L);
     s->G0h = D(L);
     s->Gp = D(L);
-    s->p = D(L);
-    s->pn = D(L);
+    s->p = D(s->Lp);
+    s->pn = D(s->Lp);
     s->u = D(3 * L);
     s->un = D(3 * L);
     s->w = D(3 * L);
     s->FB = D((size_t)E * 6 * Nf);
     s->FBh = D(std::max<int64_t>(m.nh, 1) * 4 * Nf);
-    s->V = D((size_t)(s->m + 1) * L);
-    s->z = D(L);
-    s->z1 = D(L);
+    s->V = D((size_t)(s->m + 1) * s->Lp);
+    s->z = D(s->Lp);
+    s->z1 = D(s->Lp);
     s->b = D(L);
-    s->partial = D((size_t)RED_BLOCKS * MAXV);
+    s->partial = D((size_t)RED_BLOCKS * MAXV + (size_t)RED_BLOCKS * 34);
+    s->partial2 = D(pass2_partial_count(s->dm));
     s->dsc = D(imx_solver::S_N);
     if (s->mixed) {
         s->Vf = F((size_t)(s->m + 1) * L);
@@ -282,17 +298,17 @@ static void residual(imx_solver* s, const StageCtx& c, const double* x, const do
     });
 }
 
-// z = M^{-1} S (xs * x)
-static void matvec(imx_solver* s, const StageCtx& c, const double* x, const double* xs, double* out) {
+// z = M^{-1} S (xs * x); with V != null also dots[i] = <V_i, z>_M (i < nv), dots[nv] = <z, z>_M
+static void matvec(imx_solver* s, const StageCtx& c, const double* x, const double* xs, double* out,
+                   const double* V = nullptr, int nv = 0, double* dots = nullptr) {
     timed(s, IMX_K_PASS1, field_bytes(s, 6, true), [&] {   // x, rho, pk, w
         launch_pass1<double>(s->dm, s->tab, c.k, x, xs, nullptr, c.rho, c.pk, c.uk, s->w, s->FB, s->FBh, s->st);
     });
-    timed(s, IMX_K_PASS2, field_bytes(s, 6 + (c.k.scheme == 2 ? 1 : 0), true), [&] {   // x, w, pk, (rho), out
+    timed(s, IMX_K_PASS2, field_bytes(s, 6 + (c.k.scheme == 2 ? 1 : 0) + nv, true), [&] {   // x, w, pk, (rho), out, V
         launch_pass2<double>(s->dm, s->tab, c.k, nullptr, x, xs, s->w, c.pk, c.rho, s->FB, s->FBh, out, -1.0, 0,
-                             s->st);
+                             s->st, V, nv, s->partial2, dots);
     });
 }
-
 
 struct GmresOut {
     int its = 0;
@@ -300,13 +316,13 @@ struct GmresOut {
 };
 
 // Restarted GMRES(m) for A x = b, A = M^{-1} S, in the M inner product, with
-// classical Gram-Schmidt applied twice and Givens rotations on the host
-// (Saad, Alg. 6.9). x: initial guess in, solution out. Stops when the
+// classical Gram-Schmidt (a second pass on severe cancellation) and Givens
+// rotations on the host (Saad, Alg. 6.9). x: initial guess in, solution out. Stops when the
 // Givens residual estimate reaches tol*|b| (unless `fixed`), after maxit
 // products, or on breakdown; the final residual is recomputed.
 static imx_status gmres(imx_solver* s, const StageCtx& c, double* x, double bnorm, double tol, int maxit,
                         bool fixed, GmresOut& out) {
-    const int64_t L = s->L;
+    const int64_t L = s->Lp;   // Krylov vector stride (element kernels touch the first E*Np)
     const int m = s->m;
     double* V = s->V;
     double* raw1 = s->dsc + imx_solver::S_RAW1;
@@ -335,25 +351,36 @@ static imx_status gmres(imx_solver* s, const StageCtx& c, double* x, double bnor
         CHK(put_scalars(s, sv, &svh[0], 1, 0));
         int k = 0;
         for (int j = 0; j < m; ++j) {
-            matvec(s, c, V + (size_t)j * L, sv + j, s->z);
+            // z = A (sv_j V_j), its projections <V_i, z> and norm, then one
+            // classical Gram-Schmidt update that also yields the new norm.
+            // A second pass runs only on severe cancellation (|z1| < 1e-3 |z|).
+            double* Vn = V + (size_t)(j + 1) * L;
+            // z is built in the slot of the next basis vector: its projections on
+            // V_0..V_j and its own norm come out of one multi-dot pass
+            matvec(s, c, V + (size_t)j * L, sv + j, Vn);
             ++its;
             const double vb = (double)L * 8.0;
-            timed(s, IMX_K_DOTS, (j + 3) * vb, [&] {
-                launch_dots<double>(L, j + 1, V, L, s->z, s->dm.WJ, s->partial, raw1, s->st);
-            });
+            timed(s, IMX_K_DOTS, (j + 3) * vb,
+                  [&] { launch_dots<double>(L, j + 2, V, L, Vn, s->dm.WJ, s->partial, raw1, s->st); });
             timed(s, IMX_K_ORTHO, (j + 4) * vb, [&] {
-                launch_axpy_reduce<double>(L, j + 1, V, L, raw1, sv, s->z, s->z1, s->dm.WJ, 0, s->partial, raw2,
-                                           s->st);
+                launch_axpy_reduce<double>(L, j + 1, V, L, raw1, sv, Vn, Vn, s->dm.WJ, 1, s->partial, nrm, s->st);
             });
-            timed(s, IMX_K_ORTHO, (j + 4) * vb, [&] {
-                launch_axpy_reduce<double>(L, j + 1, V, L, raw2, sv, s->z1, V + (size_t)(j + 1) * L, s->dm.WJ, 1,
-                                           s->partial, nrm, s->st);
-            });
-            HIPCHK(hipMemcpyAsync(s->hsc, raw1, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s->st));
-            HIPCHK(hipMemcpyAsync(s->hsc + 64, raw2, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s->st));
+            HIPCHK(hipMemcpyAsync(s->hsc, raw1, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s->st));
             HIPCHK(hipMemcpyAsync(s->hsc + 128, nrm, sizeof(double), hipMemcpyDeviceToHost, s->st));
             HIPCHK(hipStreamSynchronize(s->st));
-            for (int i = 0; i <= j; ++i) H[i * m + j] = svh[i] * (s->hsc[i] + s->hsc[64 + i]);
+            for (int i = 0; i <= j; ++i) H[i * m + j] = svh[i] * s->hsc[i];
+            if (s->hsc[128] < 1e-6 * s->hsc[j + 1]) {
+                timed(s, IMX_K_DOTS, (j + 3) * vb, [&] {
+                    launch_dots<double>(L, j + 1, V, L, Vn, s->dm.WJ, s->partial, raw2, s->st);
+                });
+                timed(s, IMX_K_ORTHO, (j + 4) * vb, [&] {
+                    launch_axpy_reduce<double>(L, j + 1, V, L, raw2, sv, Vn, Vn, s->dm.WJ, 1, s->partial, nrm, s->st);
+                });
+                HIPCHK(hipMemcpyAsync(s->hsc + 64, raw2, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s->st));
+                HIPCHK(hipMemcpyAsync(s->hsc + 128, nrm, sizeof(double), hipMemcpyDeviceToHost, s->st));
+                HIPCHK(hipStreamSynchronize(s->st));
+                for (int i = 0; i <= j; ++i) H[i * m + j] += svh[i] * s->hsc[64 + i];
+            }
             const double hnext = std::sqrt(s->hsc[128]);
             H[(j + 1) * m + j] = hnext;
             for (int i = 0; i < j; ++i) {
@@ -592,9 +619,11 @@ imx_status imx_solver_create(const imx_mesh* mesh, const imx_phys* phys, const i
     s->Np = mesh->m.Np;
     s->Nf = mesh->m.Nf;
     s->L = s->E * s->Np;
+    s->Lp = (s->L + 3) & ~int64_t(3);
     s->m = num->gmres_restart;
     s->mixed = num->precision == IMX_MIXED;
     s->dm.E = s->E;
+    s->dm.Lp = s->Lp;
     s->dm.nh = mesh->m.nh;
     s->dm.n = mesh->m.n;
     s->dm.Np = s->Np;
@@ -629,6 +658,8 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
     }
     s->ws = (char*)dev;
     layout(s, s->ws);
+    // zero first: the padding of the Krylov-stride vectors (and WJ) stays zero
+    HIPCHK(hipMemsetAsync(s->ws, 0, s->ws_bytes, s->st));
     const Mesh& m = *s->mesh;
     auto up = [&](const void* dst, const void* src, size_t n) -> imx_status {
         HIPCHK(hipMemcpyAsync((void*)dst, src, n, hipMemcpyHostToDevice, s->st));
@@ -638,7 +669,22 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
     CHK(up(s->dm.nbr, m.fnbr.data(), m.fnbr.size() * sizeof(int)));
     CHK(up(s->dm.aux, m.faux.data(), m.faux.size() * sizeof(int)));
     if (m.nh) CHK(up(s->dm.hang, m.hang.data(), m.hang.size() * sizeof(int)));
+    std::vector<int> reg, crs;
+    if (s->dm.ncoarse) {
+        for (int64_t e = 0; e < s->E; ++e) {
+            bool c = false;
+            for (int f = 0; f < 6; ++f) c |= m.fkind[6 * e + f] == COARSE;
+            (c ? crs : reg).push_back((int)e);
+        }
+        CHK(up(s->dm.reg_list, reg.data(), reg.size() * sizeof(int)));
+        CHK(up(s->dm.crs_list, crs.data(), crs.size() * sizeof(int)));
+    }
     CHK(up(s->dm.h, m.h.data(), m.h.size() * sizeof(double)));
+    std::vector<char> tabimg(tab_bytes(m.n, 0)), tabimgf(tab_bytes(m.n, 1));
+    fill_tab(s->tab, 0, tabimg.data());
+    fill_tab(s->tab, 1, tabimgf.data());
+    CHK(up(s->dm.tab, tabimg.data(), tabimg.size()));
+    CHK(up(s->dm.tabf, tabimgf.data(), tabimgf.size()));
     CHK(up(s->dm.WJ, m.WJ.data(), m.WJ.size() * sizeof(double)));
     if (m.deformed) {
         CHK(up(s->dm.G, m.G.data(), m.G.size() * sizeof(double)));

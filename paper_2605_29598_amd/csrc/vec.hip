@@ -38,41 +38,82 @@ __device__ __forceinline__ void block_sum(double* v, double* red) {
     __syncthreads();
 }
 
-// final fixed-order sum of partials[nb][nv] -> out[nv]
+// final fixed-order sum of partials[nb][nv] -> out[nv], one workgroup per value
 __global__ void k_final_sum(const double* __restrict__ partial, int nb, int nv, double* __restrict__ out) {
     __shared__ double red[TPB];
-    for (int v = 0; v < nv; ++v) {
-        double s = 0;
-        for (int b = threadIdx.x; b < nb; b += TPB) s += partial[(size_t)b * nv + v];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int off = TPB / 2; off > 0; off >>= 1) {
-            if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[v] = red[0];
+    const int v = blockIdx.x;
+    double s = 0;
+    for (int b = threadIdx.x; b < nb; b += TPB) s += partial[(size_t)b * nv + v];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = TPB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
+    if (threadIdx.x == 0) out[v] = red[0];
 }
 
 static void final_sum(const double* partial, int nb, int nv, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(TPB), 0, st, partial, nb, nv, out);
+    hipLaunchKernelGGL(k_final_sum, dim3(nv), dim3(TPB), 0, st, partial, nb, nv, out);
+}
+void launch_final_sum(const double* partial, int nb, int nv, double* out, hipStream_t st) {
+    final_sum(partial, nb, nv, out, st);
+}
+
+// 16-byte lanes: two binary64 or four binary32 values per load
+template <typename R>
+struct Vec16;
+template <>
+struct Vec16<double> {
+    using T = double2;
+    static constexpr int W = 2;
+};
+template <>
+struct Vec16<float> {
+    using T = float4;
+    static constexpr int W = 4;
+};
+template <typename T, typename R>
+__device__ __forceinline__ R lane(const T& v, int k) {
+    return ((const R*)&v)[k];
+}
+template <typename T, typename R>
+__device__ __forceinline__ void set_lane(T& v, int k, R x) {
+    ((R*)&v)[k] = x;
+}
+
+static unsigned stream_grid(int64_t L) {
+    int64_t g = (L + TPB * 2 - 1) / (TPB * 2);
+    if (g > RED_BLOCKS) g = RED_BLOCKS;
+    if (g < 1) g = 1;
+    return (unsigned)g;
 }
 
 // ------------------------------------------------------- multi-dot products
+// partial[b][v0 + i] = sum over the block's entries of WJ * V_i * z
 template <typename R, int CH>
 __global__ void __launch_bounds__(TPB)
 k_dots(int64_t L, int nv, int v0, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z,
        const R* __restrict__ WJ, double* __restrict__ partial, int nvtot) {
+    using VT = typename Vec16<R>::T;
+    constexpr int W = Vec16<R>::W;
     __shared__ double red[(TPB / 64 + 1) * CH];
     double acc[CH];
 #pragma unroll
     for (int i = 0; i < CH; ++i) acc[i] = 0;
-    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) {
-        const double wz = (double)WJ[x] * (double)z[x];
+    const int64_t nvec = L / W;   // ldv and L are multiples of W (checked by the launcher)
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < nvec; x += (int64_t)gridDim.x * TPB) {
+        const VT zz = ((const VT*)z)[x], ww = ((const VT*)WJ)[x];
+        double wz[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) wz[k] = (double)lane<VT, R>(ww, k) * (double)lane<VT, R>(zz, k);
 #pragma unroll
         for (int i = 0; i < CH; ++i)
-            if (i < nv) acc[i] += wz * (double)V[(int64_t)(v0 + i) * ldv + x];
+            if (i < nv) {
+                const VT v = ((const VT*)(V + (int64_t)(v0 + i) * ldv))[x];
+#pragma unroll
+                for (int k = 0; k < W; ++k) acc[i] += wz[k] * (double)lane<VT, R>(v, k);
+            }
     }
     block_sum<CH>(acc, red);
     if (threadIdx.x < nv) partial[(size_t)blockIdx.x * nvtot + v0 + threadIdx.x] = red[TPB / 64 * CH + threadIdx.x];
@@ -81,13 +122,15 @@ k_dots(int64_t L, int nv, int v0, const R* __restrict__ V, int64_t ldv, const R*
 template <typename R>
 void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R* WJ, double* partial,
                  double* out, hipStream_t st) {
-    const unsigned g = grid_for(L, TPB * 8) > RED_BLOCKS ? RED_BLOCKS : grid_for(L, TPB * 8);
-    for (int v0 = 0; v0 < nv; v0 += 16) {
-        const int c = nv - v0 < 16 ? nv - v0 : 16;
-        if (c <= 4)
-            hipLaunchKernelGGL((k_dots<R, 4>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv);
-        else
+    const unsigned g = stream_grid(L);
+    for (int v0 = 0; v0 < nv; v0 += 32) {
+        const int c = nv - v0 < 32 ? nv - v0 : 32;
+        if (c <= 8)
+            hipLaunchKernelGGL((k_dots<R, 8>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv);
+        else if (c <= 16)
             hipLaunchKernelGGL((k_dots<R, 16>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv);
+        else
+            hipLaunchKernelGGL((k_dots<R, 32>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv);
     }
     final_sum(partial, (int)g, nv, out, st);
 }
@@ -98,12 +141,14 @@ template void launch_dots<float>(int64_t, int, const float*, int64_t, const floa
 
 // --------------------------------------------- Gram-Schmidt update (+ reduce)
 // z1 = z - sum_i raw[i] s[i]^2 V_i; then dots of z1 with all V_i (mode 0) or
-// its squared M-norm (mode 1).
+// its squared M-norm (mode 1). z and z1 may be the same array.
 template <typename R, int CH>
 __global__ void __launch_bounds__(TPB)
 k_axpy_red(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const double* __restrict__ raw,
-           const double* __restrict__ s, const R* __restrict__ z, R* __restrict__ z1, const R* __restrict__ WJ,
-           int mode_norm, double* __restrict__ partial) {
+           const double* __restrict__ s, const R* z, R* z1, const R* __restrict__ WJ, int mode_norm,
+           double* __restrict__ partial) {
+    using VT = typename Vec16<R>::T;
+    constexpr int W = Vec16<R>::W;
     __shared__ double red[(TPB / 64 + 1) * CH];
     __shared__ double cf[CH];
     if (threadIdx.x < CH) cf[threadIdx.x] = threadIdx.x < nv ? raw[threadIdx.x] * s[threadIdx.x] * s[threadIdx.x] : 0.0;
@@ -111,24 +156,38 @@ k_axpy_red(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const double
     double acc[CH];
 #pragma unroll
     for (int i = 0; i < CH; ++i) acc[i] = 0;
-    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) {
-        R v[CH];
-        double zz = (double)z[x];
+    const int64_t nvec = L / W;
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < nvec; x += (int64_t)gridDim.x * TPB) {
+        VT v[CH];
+        const VT zin = ((const VT*)z)[x];
+        double zz[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) zz[k] = (double)lane<VT, R>(zin, k);
 #pragma unroll
         for (int i = 0; i < CH; ++i)
             if (i < nv) {
-                v[i] = V[(int64_t)i * ldv + x];
-                zz -= cf[i] * (double)v[i];
+                v[i] = ((const VT*)(V + (int64_t)i * ldv))[x];
+#pragma unroll
+                for (int k = 0; k < W; ++k) zz[k] -= cf[i] * (double)lane<VT, R>(v[i], k);
             }
-        const R zr = (R)zz;
-        z1[x] = zr;
-        const double wz = (double)WJ[x] * (double)zr;
+        VT zo;
+#pragma unroll
+        for (int k = 0; k < W; ++k) set_lane<VT, R>(zo, k, (R)zz[k]);
+        ((VT*)z1)[x] = zo;
+        const VT ww = ((const VT*)WJ)[x];
         if (mode_norm) {
-            acc[0] += wz * (double)zr;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const double zr = (double)lane<VT, R>(zo, k);
+                acc[0] += (double)lane<VT, R>(ww, k) * zr * zr;
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < CH; ++i)
-                if (i < nv) acc[i] += wz * (double)v[i];
+                if (i < nv)
+#pragma unroll
+                    for (int k = 0; k < W; ++k)
+                        acc[i] += (double)lane<VT, R>(ww, k) * (double)lane<VT, R>(zo, k) * (double)lane<VT, R>(v[i], k);
         }
     }
     block_sum<CH>(acc, red);
@@ -136,11 +195,66 @@ k_axpy_red(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const double
     if (threadIdx.x < nout) partial[(size_t)blockIdx.x * nout + threadIdx.x] = red[TPB / 64 * CH + threadIdx.x];
 }
 
+// z1 = z - sum_i raw[i] s[i]^2 V_i and its squared M-norm (no basis vector
+// kept live: one running value per lane)
+template <typename R, int CH>
+__global__ void __launch_bounds__(TPB)
+k_axpy_norm(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const double* __restrict__ raw,
+            const double* __restrict__ s, const R* z, R* z1, const R* __restrict__ WJ, double* __restrict__ partial) {
+    using VT = typename Vec16<R>::T;
+    constexpr int W = Vec16<R>::W;
+    __shared__ double red[(TPB / 64 + 1)];
+    __shared__ double cf[CH];
+    if (threadIdx.x < CH) cf[threadIdx.x] = threadIdx.x < nv ? raw[threadIdx.x] * s[threadIdx.x] * s[threadIdx.x] : 0.0;
+    __syncthreads();
+    double acc[1] = {0.0};
+    const int64_t nvec = L / W;
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < nvec; x += (int64_t)gridDim.x * TPB) {
+        const VT zin = ((const VT*)z)[x];
+        double zz[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) zz[k] = (double)lane<VT, R>(zin, k);
+#pragma unroll
+        for (int i = 0; i < CH; ++i)
+            if (i < nv) {
+                const VT v = ((const VT*)(V + (int64_t)i * ldv))[x];
+                const double c = cf[i];
+#pragma unroll
+                for (int k = 0; k < W; ++k) zz[k] -= c * (double)lane<VT, R>(v, k);
+            }
+        VT zo;
+#pragma unroll
+        for (int k = 0; k < W; ++k) set_lane<VT, R>(zo, k, (R)zz[k]);
+        ((VT*)z1)[x] = zo;
+        const VT ww = ((const VT*)WJ)[x];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const double zr = (double)lane<VT, R>(zo, k);
+            acc[0] += (double)lane<VT, R>(ww, k) * zr * zr;
+        }
+    }
+    block_sum<1>(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[TPB / 64];
+}
+
 template <typename R>
 void launch_axpy_reduce(int64_t L, int nv, const R* V, int64_t ldv, const double* raw, const double* s,
                         const R* z, R* z1, const R* WJ, int mode_norm, double* partial, double* out,
                         hipStream_t st) {
-    const unsigned g = grid_for(L, TPB * 8) > RED_BLOCKS ? RED_BLOCKS : grid_for(L, TPB * 8);
+    const unsigned g = stream_grid(L);
+    if (mode_norm) {
+        if (nv <= 8)
+            hipLaunchKernelGGL((k_axpy_norm<R, 8>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
+                               partial);
+        else if (nv <= 16)
+            hipLaunchKernelGGL((k_axpy_norm<R, 16>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
+                               partial);
+        else
+            hipLaunchKernelGGL((k_axpy_norm<R, 32>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
+                               partial);
+        final_sum(partial, (int)g, 1, out, st);
+        return;
+    }
     if (nv <= 8)
         hipLaunchKernelGGL((k_axpy_red<R, 8>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ, mode_norm,
                            partial);
@@ -162,15 +276,28 @@ template void launch_axpy_reduce<float>(int64_t, int, const float*, int64_t, con
 template <typename R>
 __global__ void k_lincomb(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const double* __restrict__ coef,
                           R* __restrict__ x) {
-    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < L; i += (int64_t)gridDim.x * TPB) {
-        double acc = (double)x[i];
-        for (int k = 0; k < nv; ++k) acc += coef[k] * (double)V[(int64_t)k * ldv + i];
-        x[i] = (R)acc;
+    using VT = typename Vec16<R>::T;
+    constexpr int W = Vec16<R>::W;
+    const int64_t nvec = L / W;
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < nvec; i += (int64_t)gridDim.x * TPB) {
+        const VT xin = ((const VT*)x)[i];
+        double acc[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) acc[k] = (double)lane<VT, R>(xin, k);
+        for (int j = 0; j < nv; ++j) {
+            const VT v = ((const VT*)(V + (int64_t)j * ldv))[i];
+#pragma unroll
+            for (int k = 0; k < W; ++k) acc[k] += coef[j] * (double)lane<VT, R>(v, k);
+        }
+        VT o;
+#pragma unroll
+        for (int k = 0; k < W; ++k) set_lane<VT, R>(o, k, (R)acc[k]);
+        ((VT*)x)[i] = o;
     }
 }
 template <typename R>
 void launch_lincomb(int64_t L, int nv, const R* V, int64_t ldv, const double* coef, R* x, hipStream_t st) {
-    hipLaunchKernelGGL((k_lincomb<R>), dim3(grid_for(L)), dim3(TPB), 0, st, L, nv, V, ldv, coef, x);
+    hipLaunchKernelGGL((k_lincomb<R>), dim3(stream_grid(L)), dim3(TPB), 0, st, L, nv, V, ldv, coef, x);
 }
 template void launch_lincomb<double>(int64_t, int, const double*, int64_t, const double*, double*, hipStream_t);
 template void launch_lincomb<float>(int64_t, int, const float*, int64_t, const double*, float*, hipStream_t);
