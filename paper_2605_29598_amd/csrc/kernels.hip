@@ -95,6 +95,7 @@ struct Geom {
     const int* aux;
     const int* hang;
     const double* h;
+    const double* hinv;   // 1 / h, per element and direction
     const R* WJ;
     const R* G;
     const R* nS;
@@ -104,11 +105,11 @@ template <typename R>
 static Geom<R> geom(const DevMesh& m);
 template <>
 Geom<double> geom<double>(const DevMesh& m) {
-    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.WJ, m.G, m.nS};
+    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJ, m.G, m.nS};
 }
 template <>
 Geom<float> geom<float>(const DevMesh& m) {
-    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.WJf, m.Gf, m.nSf};
+    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJf, m.Gf, m.nSf};
 }
 
 constexpr int epb_of(int N) { return N == 2 ? 16 : (N == 3 ? 9 : (N == 4 ? 4 : 2)); }
@@ -135,13 +136,21 @@ __device__ __forceinline__ void split_node(int d, int node, int& m, int& pt) {
     else { m = k; pt = i + N * j; }
 }
 
-// value of a Q_r field (nodal array f of one element) at face point pt
+// products and sums with one rounding each (no contraction into fma), so that
+// a trace formed from products staged in LDS rounds exactly like face_value
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
+__device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
+
+// value of a Q_r field (nodal array f of one element) at face point pt:
+// sum over m (in order) of l_m(s) f(m along the normal)
 template <int N, typename R, typename P>
 __device__ __forceinline__ R face_value(const P* f, const R* fv, int d, int pt) {
     const int a = pt % N, b = pt / N;
-    R acc = 0;
+    R acc = mul_rn(fv[0], (R)f[node_of<N>(d, 0, a, b)]);
 #pragma unroll
-    for (int m = 0; m < N; ++m) acc += fv[m] * (R)f[node_of<N>(d, m, a, b)];
+    for (int m = 1; m < N; ++m) acc = add_rn(acc, mul_rn(fv[m], (R)f[node_of<N>(d, m, a, b)]));
     return acc;
 }
 
@@ -196,7 +205,7 @@ template <int N, typename R>
 __device__ __forceinline__ R metric(const Geom<R>& g, int64_t e, int node, int d, int c, R wj) {
     constexpr int NP = N * N * N;
     if (g.deformed) return g.G[((size_t)(d * 3 + c) * g.E + e) * NP + node];
-    return d == c ? wj / (R)g.h[3 * e + d] : (R)0;
+    return d == c ? wj * (R)g.hinv[3 * e + d] : (R)0;
 }
 
 // sum_d (D_d^T G_d) at node, G in LDS [3][NP]
@@ -256,6 +265,13 @@ __device__ __forceinline__ void euler_flux(const R* qa, const R* qbin, const R* 
     for (int c = 0; c < 3; ++c) fl[5 + c] = pavg * nS[c];
     const R hA = gam / gm1 * pA, hB = gam / gm1 * pB;
     fl[8] = (R)0.5 * (hA * unSA + hB * unSB) + hl * (pA - pB) / gm1;
+}
+
+// (rho h)^k (w . nS) at a face point, rounded the same way wherever formed
+template <typename R>
+__device__ __forceinline__ R fb_value(R hfac, R hk, R w0, R w1, R w2, const R* nS) {
+    const R wn = add_rn(add_rn(mul_rn(w0, nS[0]), mul_rn(w1, nS[1])), mul_rn(w2, nS[2]));
+    return mul_rn(mul_rn(hfac, hk), wn);
 }
 
 // value of the coarse neighbour's face polynomial (face (d, side) of the
@@ -400,7 +416,8 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
     R rho = 1, u[3] = {0, 0, 0}, kin = 0, p = 0, wj = 1;
     if (act) {
         rho = s_q[le][0][node];
-        for (int c = 0; c < 3; ++c) u[c] = s_q[le][1 + c][node] / rho;
+        const R irho = (R)1 / rho;
+        for (int c = 0; c < 3; ++c) u[c] = s_q[le][1 + c][node] * irho;
         kin = (R)0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
         p = (gam - (R)1) * (s_q[le][4][node] - rho * kin);
         wj = g.WJ[e * NP + node];
@@ -443,8 +460,9 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
         const R lam = (R)sponge[e * NP + node];
         for (int c = 0; c < 3; ++c) acc[1 + c] -= wj * lam * (s_q[le][1 + c][node] - rho * (R)ph.su[c]);
     }
-    for (int t = 0; t < 5; ++t) fNS[t * fs + e * NP + node] = acc[t] / wj;
-    for (int t = 0; t < 4; ++t) fS[t * fs + e * NP + node] = acc[5 + t] / wj;
+    const R iwj = (R)1 / wj;
+    for (int t = 0; t < 5; ++t) fNS[t * fs + e * NP + node] = acc[t] * iwj;
+    for (int t = 0; t < 4; ++t) fS[t * fs + e * NP + node] = acc[5 + t] * iwj;
 }
 
 // =====================================================================
@@ -457,11 +475,13 @@ k_pass1(const int* __restrict__ elist, int64_t nel, const R* __restrict__ p, con
         R* __restrict__ FB, R* __restrict__ FBh, Geom<R> g, const Tab<N, R>* __restrict__ Tg, StageK sk) {
     constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
     constexpr int L_FAST = 6 * 3 * NF, L_SLOW = 4 * NF + NF + 3 * NF + 4 * 3 * NF, L_VOL = 3 * NP;
+    constexpr int NR = (6 * NF + NP - 1) / NP;   // face points per lane
     constexpr int UN = (L_FAST > L_SLOW ? L_FAST : L_SLOW) > L_VOL ? (L_FAST > L_SLOW ? L_FAST : L_SLOW) : L_VOL;
     __shared__ R s_p[EPB][NP];
     __shared__ R s_pk[EPB][NP];
     __shared__ R s_w[EPB][3][NP];
     __shared__ R s_u[EPB][UN];
+    __shared__ int s_kind[EPB][6], s_nbr[EPB][6];
     const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
     __shared__ Tab<N, R> T;
     load_tab<N, R>(Tg, &T);
@@ -472,30 +492,73 @@ k_pass1(const int* __restrict__ elist, int64_t nel, const R* __restrict__ p, con
     const R gam = (R)sk.gamma;
     const R sc = pscale ? pscale[0] : (R)1;
     R* U = &s_u[le][0];
+    // every global load of the kernel is issued here, before the first barrier:
+    // own fields, the face table and (fast path) the neighbour gathers
+    R* FL = U;                 // fast path: {p} nS at FL[(f*3 + c)*NF + pt]
+    R nbv[NR][N];              // fast path: the neighbour's values along the normal at this lane's points
+    R wj = (R)1, rl = (R)1, fh[3] = {0, 0, 0}, ukv[2] = {0, 0};
     if (act) {
         s_p[le][node] = p ? p[e * NP + node] : (R)0;
         s_pk[le][node] = pk[e * NP + node];
+        wj = g.WJ[e * NP + node];
+        rl = rho[e * NP + node];
+        if (Fh)
+            for (int c = 0; c < 3; ++c) fh[c] = Fh[c * fs + e * NP + node];
+        if (uk && Fh && sk.scheme == 1) {
+            ukv[0] = uk[0 * fs + e * NP + node];
+            ukv[1] = uk[1 * fs + e * NP + node];
+        }
+        int kf[6], nf[6];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            kf[f] = g.kind[e * 6 + f];
+            nf[f] = g.nbr[e * 6 + f];
+        }
+        if (node < 6) {
+            s_kind[le][node] = kf[node];
+            s_nbr[le][node] = nf[node];
+        }
+        if (!SLOW && p) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int it = node + r * NP;
+                int f = it / NF;
+                f = f < 6 ? f : 5;
+                const int pt = it - f * NF, d = f >> 1, a = pt % N, b = pt / N;
+                const bool ld = it < 6 * NF && kf[f] == CONF;
+                const R* src = p + (size_t)(ld ? nf[f] : 0) * NP;
+#pragma unroll
+                for (int m = 0; m < N; ++m) nbv[r][m] = ld ? src[node_of<N>(d, m, a, b)] : (R)0;
+            }
+        }
     }
     constexpr bool slow = SLOW;
     __syncthreads();
     R acc[3] = {0, 0, 0};
-    const R wj = act ? g.WJ[e * NP + node] : (R)1;
     if (p) {
         if (!slow) {
-            // {p} nS for all face points: U[(f*3 + c)*NF + pt]
             if (act)
-                for (int it = node; it < 6 * NF; it += NP) {
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const int it = node + r * NP;
+                    if (it >= 6 * NF) break;
                     const int f = it / NF, pt = it - f * NF, d = f >> 1, s = f & 1;
-                    const int kind = g.kind[e * 6 + f], nbr = g.nbr[e * 6 + f];
+                    const int kind = s_kind[le][f];
                     const R pa = sc * face_value<N>(&s_p[le][0], T.f[s], d, pt);
                     R pb = pa;
-                    if (kind == CONF) pb = sc * face_value<N>(p + (size_t)nbr * NP, T.f[1 - s], d, pt);
-                    else if (kind == FINE)
-                        pb = sc * coarse_point<N>(p + (size_t)nbr * NP, T.f[1 - s], T, d, g.aux[e * 6 + f] & 3, pt);
+                    if (kind == CONF) {
+                        R t = mul_rn(T.f[1 - s][0], nbv[r][0]);
+#pragma unroll
+                        for (int m = 1; m < N; ++m) t = add_rn(t, mul_rn(T.f[1 - s][m], nbv[r][m]));
+                        pb = sc * t;
+                    } else if (kind == FINE) {
+                        pb = sc * coarse_point<N>(p + (size_t)s_nbr[le][f] * NP, T.f[1 - s], T, d,
+                                                  g.aux[e * 6 + f] & 3, pt);
+                    }
                     R nS[3];
                     area<N>(g, T, e, f, pt, nS);
                     const R avg = (R)0.5 * (pa + pb);
-                    for (int c = 0; c < 3; ++c) U[(f * 3 + c) * NF + pt] = avg * nS[c];
+                    for (int c = 0; c < 3; ++c) FL[(f * 3 + c) * NF + pt] = avg * nS[c];
                 }
             __syncthreads();
             if (act)
@@ -503,7 +566,7 @@ k_pass1(const int* __restrict__ elist, int64_t nel, const R* __restrict__ p, con
                     int m, pt;
                     split_node<N>(f >> 1, node, m, pt);
                     const R lf = T.f[f & 1][m];
-                    for (int c = 0; c < 3; ++c) acc[c] += lf * U[(f * 3 + c) * NF + pt];
+                    for (int c = 0; c < 3; ++c) acc[c] += lf * FL[(f * 3 + c) * NF + pt];
                 }
         } else {
             R* s_own = U;               // [NF]
@@ -576,9 +639,9 @@ k_pass1(const int* __restrict__ elist, int64_t nel, const R* __restrict__ p, con
                     d1 += T.D[qq][j] * U[i + N * (qq + N * k)];
                     d2 += T.D[qq][k] * U[i + N * (j + N * qq)];
                 }
-                acc[0] -= d0 / (R)g.h[3 * e + 0];
-                acc[1] -= d1 / (R)g.h[3 * e + 1];
-                acc[2] -= d2 / (R)g.h[3 * e + 2];
+                acc[0] -= d0 * (R)g.hinv[3 * e + 0];
+                acc[1] -= d1 * (R)g.hinv[3 * e + 1];
+                acc[2] -= d2 * (R)g.hinv[3 * e + 2];
             }
         } else {
             for (int c = 0; c < 3; ++c) {
@@ -592,19 +655,17 @@ k_pass1(const int* __restrict__ elist, int64_t nel, const R* __restrict__ p, con
     }
     R wv[3] = {0, 0, 0};
     if (act) {
-        const R r = rho[e * NP + node];
+        const R r = rl;
         const R cdt = (R)sk.c_dt, beta = (R)sk.beta;
         R v[3];
-        for (int c = 0; c < 3; ++c) {
-            const R mBp = cdt * acc[c] / wj;
-            v[c] = (Fh ? Fh[c * fs + e * NP + node] : (R)0) / r - mBp / r;
-        }
+        const R iwj = (R)1 / wj, ir = (R)1 / r;
+        for (int c = 0; c < 3; ++c) v[c] = (fh[c] - cdt * acc[c] * iwj) * ir;
         if (sk.scheme == 1) {
             // the lagged rotation -A^{-1} R u^k = -beta J u^k belongs to the
             // right-hand side F - R u^k, so it comes with Fh only
             if (uk && Fh) {
-                v[0] += beta * uk[1 * fs + e * NP + node];
-                v[1] -= beta * uk[0 * fs + e * NP + node];
+                v[0] += beta * ukv[1];
+                v[1] -= beta * ukv[0];
             }
             wv[0] = v[0];
             wv[1] = v[1];
@@ -635,7 +696,7 @@ k_pass1(const int* __restrict__ elist, int64_t nel, const R* __restrict__ p, con
                 const R w0 = face_value<N>(&s_w[le][0][0], T.f[s], d, pt);
                 const R w1 = face_value<N>(&s_w[le][1][0], T.f[s], d, pt);
                 const R w2 = face_value<N>(&s_w[le][2][0], T.f[s], d, pt);
-                FB[((size_t)e * 6 + f) * NF + pt] = hfac * hk * (w0 * nS[0] + w1 * nS[1] + w2 * nS[2]);
+                FB[((size_t)e * 6 + f) * NF + pt] = fb_value<R>(hfac, hk, w0, w1, w2, nS);
             }
         return;
     }
@@ -659,13 +720,11 @@ k_pass1(const int* __restrict__ elist, int64_t nel, const R* __restrict__ p, con
                     for (int t = 0; t < 4; ++t) vals[t] = sub_interp<N>(s_own + t * NF, T, hs, pt);
                     area<N>(g, T, fn, f ^ 1, pt, nS);
                     for (int c = 0; c < 3; ++c) nS[c] = -nS[c];
-                    FBh[((size_t)nbr * 4 + hs) * NF + pt] =
-                        hfac * vals[0] * (vals[1] * nS[0] + vals[2] * nS[1] + vals[3] * nS[2]);
+                    FBh[((size_t)nbr * 4 + hs) * NF + pt] = fb_value<R>(hfac, vals[0], vals[1], vals[2], vals[3], nS);
                 } else {
                     for (int t = 0; t < 4; ++t) vals[t] = s_own[t * NF + pt];
                     area<N>(g, T, e, f, pt, nS);
-                    FB[((size_t)e * 6 + f) * NF + pt] =
-                        hfac * vals[0] * (vals[1] * nS[0] + vals[2] * nS[1] + vals[3] * nS[2]);
+                    FB[((size_t)e * 6 + f) * NF + pt] = fb_value<R>(hfac, vals[0], vals[1], vals[2], vals[3], nS);
                 }
             }
         }
@@ -678,15 +737,15 @@ k_pass1(const int* __restrict__ elist, int64_t nel, const R* __restrict__ p, con
 // =====================================================================
 template <int N, typename R, bool SLOW>
 __global__ void __launch_bounds__(threads_of(N))
-k_pass2(const int* __restrict__ elist, int64_t nel, const R* __restrict__ Gp, const R* __restrict__ p, const R* __restrict__ pscale,
-        const R* __restrict__ w, const R* __restrict__ pk, const R* __restrict__ rho, const R* __restrict__ FB,
-        const R* __restrict__ FBh, R* __restrict__ out, R alpha, int dual, Geom<R> g,
+k_pass2(const int* __restrict__ elist, int64_t nel, const R* __restrict__ Gp, const R* __restrict__ p,
+        const R* __restrict__ pscale, const R* __restrict__ w, const R* __restrict__ pk, const R* __restrict__ rho,
+        const R* __restrict__ FB, const R* __restrict__ FBh, R* __restrict__ out, R alpha, int dual, Geom<R> g,
         const Tab<N, R>* __restrict__ Tg, StageK sk, const R* __restrict__ V, int nv, int64_t ldv,
         double* __restrict__ partial) {
     constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
-    constexpr int L_FAST = 6 * NF, L_SLOW = NF + 4 * NF, L_VOL = 3 * NP;
-    constexpr int UN = (L_FAST > L_SLOW ? L_FAST : L_SLOW) > L_VOL ? (L_FAST > L_SLOW ? L_FAST : L_SLOW) : L_VOL;
-    __shared__ R s_u[EPB][UN];
+    constexpr int L_FACE = SLOW ? 5 * NF : 6 * NF;
+    __shared__ R s_face[EPB][L_FACE];
+    __shared__ R s_vol[EPB][3][NP];
     const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
     __shared__ Tab<N, R> T;
     load_tab<N, R>(Tg, &T);
@@ -695,25 +754,41 @@ k_pass2(const int* __restrict__ elist, int64_t nel, const R* __restrict__ Gp, co
     const int64_t e = act ? (elist ? (int64_t)elist[slot] : slot) : 0;
     const size_t fs = (size_t)g.E * NP;
     const R gam = (R)sk.gamma;
-    R* U = &s_u[le][0];
-    constexpr bool slow = SLOW;
-    __syncthreads();
-    R acc = 0;
-    if (!slow) {
-        if (act)
+    R* U = &s_face[le][0];
+    // all global loads first: own fields, and (fast path) both sides' face fluxes
+    R wv[3] = {0, 0, 0}, wj = 1, rh = 0, rl = 0, gp = 0, pv = 0;
+    if (act) {
+        wj = g.WJ[e * NP + node];
+        for (int c = 0; c < 3; ++c) wv[c] = w[c * fs + e * NP + node];
+        rh = gam / (gam - (R)1) * pk[e * NP + node];
+        if (sk.scheme == 2) rl = rho[e * NP + node];
+        if (Gp) gp = Gp[e * NP + node];
+        if (p) pv = (pscale ? pscale[0] : (R)1) * p[e * NP + node];
+        if (!SLOW)
             for (int it = node; it < 6 * NF; it += NP) {
                 const int f = it / NF, pt = it - f * NF;
-                const int kind = g.kind[e * 6 + f], nbr = g.nbr[e * 6 + f];
+                const int kind = g.kind[e * 6 + f];
                 R v = 0;
-                if (kind == CONF)
+                if (kind == CONF) {
+                    const int nbr = g.nbr[e * 6 + f];
                     v = (R)0.5 * (FB[((size_t)e * 6 + f) * NF + pt] - FB[((size_t)nbr * 6 + (f ^ 1)) * NF + pt]);
-                else if (kind == FINE) {
+                } else if (kind == FINE) {
                     const int aux = g.aux[e * 6 + f];
-                    v = (R)0.5 * (FB[((size_t)e * 6 + f) * NF + pt] - FBh[((size_t)(aux >> 2) * 4 + (aux & 3)) * NF + pt]);
+                    v = (R)0.5 * (FB[((size_t)e * 6 + f) * NF + pt] -
+                                  FBh[((size_t)(aux >> 2) * 4 + (aux & 3)) * NF + pt]);
                 }
                 U[f * NF + pt] = v;
             }
-        __syncthreads();
+        // contravariant (rho h)^k w for the volume term
+        for (int dd = 0; dd < 3; ++dd) {
+            R v = 0;
+            for (int c = 0; c < 3; ++c) v += metric<N>(g, e, node, dd, c, wj) * wv[c];
+            s_vol[le][dd][node] = rh * v;
+        }
+    }
+    __syncthreads();
+    R acc = 0;
+    if (!SLOW) {
         if (act)
             for (int f = 0; f < 6; ++f) {
                 int m, pt;
@@ -761,27 +836,14 @@ k_pass2(const int* __restrict__ elist, int64_t nel, const R* __restrict__ Gp, co
             __syncthreads();
         }
     }
-    __syncthreads();
-    R wv[3] = {0, 0, 0}, wj = 1, rh = 0;
-    if (act) {
-        wj = g.WJ[e * NP + node];
-        for (int c = 0; c < 3; ++c) wv[c] = w[c * fs + e * NP + node];
-        rh = gam / (gam - (R)1) * pk[e * NP + node];
-        for (int dd = 0; dd < 3; ++dd) {
-            R v = 0;
-            for (int c = 0; c < 3; ++c) v += metric<N>(g, e, node, dd, c, wj) * wv[c];
-            U[dd * NP + node] = rh * v;
-        }
-    }
-    __syncthreads();
     R res = 0;
     if (act) {
-        acc -= div_T<N>(U, T, node);
+        acc -= div_T<N>(&s_vol[le][0][0], T, node);
         const R cdt = (R)sk.c_dt;
-        res = Gp ? Gp[e * NP + node] : (R)0;
-        if (p) res -= (pscale ? pscale[0] : (R)1) * p[e * NP + node] / (gam - (R)1);
+        res = gp;
+        if (p) res -= pv / (gam - (R)1);
         res -= cdt * acc / wj;
-        if (sk.scheme == 2) res -= cdt * (R)sk.g * rho[e * NP + node] * wv[2];
+        if (sk.scheme == 2) res -= cdt * (R)sk.g * rl * wv[2];
         res *= alpha;
         out[e * NP + node] = dual ? res * wj : res;
     }

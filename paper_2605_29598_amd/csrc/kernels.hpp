@@ -19,6 +19,7 @@ struct DevMesh {
     const int* aux = nullptr;       // [E*6]
     const int* hang = nullptr;      // [nh*4]
     const double* h = nullptr;      // [E*3]
+    const double* hinv = nullptr;   // [E*3] 1 / h
     const double* WJ = nullptr;     // [E*Np]
     const double* G = nullptr;      // [9][E][Np]
     const double* nS = nullptr;     // [E][6][3][Nf]

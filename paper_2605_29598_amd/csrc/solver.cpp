@@ -131,6 +131,7 @@ static size_t layout(imx_solver* s, char* base) {
         }
     }
     dm.h = D(E * 3);
+    dm.hinv = D(E * 3);
     dm.tab = D(tab_bytes(m.n, 0) / 8 + 1);
     dm.tabf = D(tab_bytes(m.n, 1) / 8 + 1);
     dm.WJ = D(s->Lp);
@@ -680,6 +681,9 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
         CHK(up(s->dm.crs_list, crs.data(), crs.size() * sizeof(int)));
     }
     CHK(up(s->dm.h, m.h.data(), m.h.size() * sizeof(double)));
+    std::vector<double> hinv(m.h.size());
+    for (size_t i = 0; i < hinv.size(); ++i) hinv[i] = 1.0 / m.h[i];
+    CHK(up(s->dm.hinv, hinv.data(), hinv.size() * sizeof(double)));
     std::vector<char> tabimg(tab_bytes(m.n, 0)), tabimgf(tab_bytes(m.n, 1));
     fill_tab(s->tab, 0, tabimg.data());
     fill_tab(s->tab, 1, tabimgf.data());

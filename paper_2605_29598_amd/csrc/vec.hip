@@ -122,7 +122,9 @@ k_dots(int64_t L, int nv, int v0, const R* __restrict__ V, int64_t ldv, const R*
 template <typename R>
 void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R* WJ, double* partial,
                  double* out, hipStream_t st) {
-    const unsigned g = stream_grid(L);
+    // fewer, longer-running workgroups: the block reduction of up to 32 sums
+    // is amortised over more entries per lane
+    const unsigned g = stream_grid(L) > 1024 ? 1024 : stream_grid(L);
     for (int v0 = 0; v0 < nv; v0 += 32) {
         const int c = nv - v0 < 32 ? nv - v0 : 32;
         if (c <= 8)
