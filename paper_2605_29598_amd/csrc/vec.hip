@@ -124,15 +124,16 @@ void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R
                  double* out, hipStream_t st) {
     // fewer, longer-running workgroups: the block reduction of up to 32 sums
     // is amortised over more entries per lane
-    const unsigned g = stream_grid(L) > 1024 ? 1024 : stream_grid(L);
-    for (int v0 = 0; v0 < nv; v0 += 32) {
-        const int c = nv - v0 < 32 ? nv - v0 : 32;
+    const unsigned g = stream_grid(L) > 2048 ? 2048 : stream_grid(L);
+    // at most 16 running sums per lane (keeps 7 waves per SIMD); longer bases
+    // take several passes that re-read z and the weights
+    const int nch = (nv + 15) / 16, per = (nv + nch - 1) / nch;
+    for (int v0 = 0; v0 < nv; v0 += per) {
+        const int c = nv - v0 < per ? nv - v0 : per;
         if (c <= 8)
             hipLaunchKernelGGL((k_dots<R, 8>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv);
-        else if (c <= 16)
-            hipLaunchKernelGGL((k_dots<R, 16>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv);
         else
-            hipLaunchKernelGGL((k_dots<R, 32>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv);
+            hipLaunchKernelGGL((k_dots<R, 16>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv);
     }
     final_sum(partial, (int)g, nv, out, st);
 }
