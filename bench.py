@@ -80,6 +80,44 @@ def cpu_baseline(seconds_budget=30.0):
                       f"{t_total:.1f} s"}
 
 
+def field_errors(a, b, gamma=1.4):
+    """Max error per conserved field, relative to rho, p/c (momentum) and rho E scales."""
+    import numpy as np
+    rho = np.abs(b[0]).max()
+    kin = 0.5 * (b[1] ** 2 + b[2] ** 2 + b[3] ** 2) / b[0]
+    p = np.abs((gamma - 1.0) * (b[4] - kin)).max()
+    c = math.sqrt(gamma * p / rho)
+    scale = [rho, p / c, p / c, p / c, np.abs(b[4]).max()]
+    names = ["rho", "rho_u", "rho_v", "rho_w", "rho_E"]
+    return {names[t]: float(np.abs(a[t] - b[t]).max() / scale[t]) for t in range(5)}
+
+
+def mixed_run(w, mesh, q0, args, ref_state, dofs):
+    """Same steps with the binary32 Krylov inner loop (binary64 defect
+    correction to the same tolerance), timed the same way."""
+    import torch
+    from paper_2605_29598_amd import binding as B
+    sol = B.Solver(mesh, w.phys, w.num, device="cuda:0", precision=B.IMX_MIXED, inner_tol=1e-3)
+    sol.set_state(q0)
+    for _ in range(args.warmup):
+        sol.step(1)
+    torch.cuda.synchronize()
+    sol.timing(True)
+    gm = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gm += sol.step(1).gmres_iters
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rep = sol.timing_report()
+    sol.timing(False)
+    err = field_errors(sol.get_state().cpu().numpy(), ref_state)
+    return {"value": dofs * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+            "gmres_inner_per_step": gm / args.steps, "inner_tol": 1e-3,
+            "max_rel_error_vs_fp64": err,
+            "kernels_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in rep.items() if v[2]}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +125,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scheme", default="R2", choices=["R1", "R2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-inner comparison run")
     ap.add_argument("--profile-steps", action="store_true", help="print progress per step")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -154,6 +193,8 @@ def main():
         "kernels": kernels,
         "mass": sol.total_mass(),
     }
+    if not args.no_mixed:
+        out["fp32_inner"] = mixed_run(w, mesh, q0, args, sol.get_state().cpu().numpy(), dofs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

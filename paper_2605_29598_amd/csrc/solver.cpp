@@ -79,6 +79,7 @@ struct imx_solver {
     // binary32 shadows for the mixed inner loop
     float *Vf = nullptr, *zf = nullptr, *z1f = nullptr, *wf = nullptr, *FBf = nullptr, *FBhf = nullptr;
     float *rhof = nullptr, *pkf = nullptr, *WJf = nullptr, *Gf = nullptr, *nSf = nullptr, *xf = nullptr;
+    float* svf = nullptr;   // binary32 copies of the Krylov scales
     // pinned host scalars
     double* hsc = nullptr;
     // kernel timing (imx_solver_timing)
@@ -166,7 +167,7 @@ static size_t layout(imx_solver* s, char* base) {
     s->partial2 = D(pass2_partial_count(s->dm));
     s->dsc = D(imx_solver::S_N);
     if (s->mixed) {
-        s->Vf = F((size_t)(s->m + 1) * L);
+        s->Vf = F((size_t)(s->m + 1) * s->Lp);
         s->zf = F(L);
         s->z1f = F(L);
         s->wf = F(3 * L);
@@ -174,8 +175,9 @@ static size_t layout(imx_solver* s, char* base) {
         s->FBhf = F(std::max<int64_t>(m.nh, 1) * 4 * Nf);
         s->rhof = F(L);
         s->pkf = F(L);
-        s->xf = F(L);
-        s->WJf = F(L);
+        s->xf = F(s->Lp);
+        s->WJf = F(s->Lp);
+        s->svf = F(64);
         dm.WJf = s->WJf;
         if (m.deformed) {
             s->Gf = F(9 * L);
@@ -194,8 +196,8 @@ static imx_status validate_num(const imx_numerics& n) {
         set_error("invalid numerics (dt > 0, scheme R1/R2, 1 <= gmres_restart <= 32, positive caps)");
         return IMX_EINVAL;
     }
-    if (n.precision == IMX_MIXED) {
-        set_error("IMX_MIXED is not available in this build");
+    if (n.precision == IMX_MIXED && !(n.inner_tol > 0 && n.inner_tol < 1)) {
+        set_error("IMX_MIXED needs 0 < inner_tol < 1");
         return IMX_EINVAL;
     }
     return IMX_OK;
@@ -427,6 +429,133 @@ static imx_status gmres(imx_solver* s, const StageCtx& c, double* x, double bnor
 
 // Solves the pressure system of the current stage context for x (initial
 // guess in, solution out) to gmres_tol.
+static imx_status put_scalars_f(imx_solver* s, float* dev, const float* vals, int n, int slot) {
+    float* h = (float*)(s->hsc + 1536) + slot;
+    std::memcpy(h, vals, n * sizeof(float));
+    HIPCHK(hipMemcpyAsync(dev, h, n * sizeof(float), hipMemcpyHostToDevice, s->st));
+    return IMX_OK;
+}
+
+// One binary32 Arnoldi cycle (at most `maxit` steps) of GMRES for the
+// correction equation A d = r / |r|, started from d = 0 with Vf[0] holding
+// r / |r| (M-norm ~ 1). Accumulates d into s->xf. Returns the step count.
+static imx_status inner_cycle_f32(imx_solver* s, const StageK& k, double beta, double tol, int maxit, int& steps) {
+    const int64_t L = s->Lp;
+    const int m = std::min(s->m, maxit);
+    float* V = s->Vf;
+    double* raw1 = s->dsc + imx_solver::S_RAW1;
+    double* nrm = s->dsc + imx_solver::S_NRM;
+    double* sv = s->dsc + imx_solver::S_SV;
+    double* coef = s->dsc + imx_solver::S_COEF;
+    std::vector<double> H((m + 1) * std::max(m, 1)), g(m + 1), cs(m), sn(m), svh(m + 1), yv(m), cf(m);
+    std::vector<float> svf(m + 1);
+    g[0] = beta;
+    svh[0] = 1.0 / beta;
+    svf[0] = (float)svh[0];
+    CHK(put_scalars(s, sv, &svh[0], 1, 0));
+    CHK(put_scalars_f(s, s->svf, &svf[0], 1, 0));
+    int kk = 0;
+    const double vb = (double)L * 4.0;
+    for (int j = 0; j < m; ++j) {
+        float* Vn = V + (size_t)(j + 1) * L;
+        timed(s, IMX_K_PASS1, field_bytes(s, 6, true) / 2, [&] {
+            launch_pass1<float>(s->dm, s->tab, k, V + (size_t)j * L, s->svf + j, nullptr, s->rhof, s->pkf, nullptr,
+                                s->wf, s->FBf, s->FBhf, s->st);
+        });
+        timed(s, IMX_K_PASS2, field_bytes(s, 6 + (k.scheme == 2 ? 1 : 0), true) / 2, [&] {
+            launch_pass2<float>(s->dm, s->tab, k, nullptr, V + (size_t)j * L, s->svf + j, s->wf, s->pkf, s->rhof,
+                                s->FBf, s->FBhf, Vn, -1.0, 0, s->st);
+        });
+        timed(s, IMX_K_DOTS, (j + 3) * vb,
+              [&] { launch_dots<float>(L, j + 2, V, L, Vn, s->WJf, s->partial, raw1, s->st); });
+        timed(s, IMX_K_ORTHO, (j + 4) * vb, [&] {
+            launch_axpy_reduce<float>(L, j + 1, V, L, raw1, sv, Vn, Vn, s->WJf, 1, s->partial, nrm, s->st);
+        });
+        HIPCHK(hipMemcpyAsync(s->hsc, raw1, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipMemcpyAsync(s->hsc + 128, nrm, sizeof(double), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
+        for (int i = 0; i <= j; ++i) H[i * m + j] = svh[i] * s->hsc[i];
+        const double hnext = std::sqrt(s->hsc[128]);
+        H[(j + 1) * m + j] = hnext;
+        for (int i = 0; i < j; ++i) {
+            const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+            H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+            H[i * m + j] = t;
+        }
+        const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+        cs[j] = H[j * m + j] / den;
+        sn[j] = H[(j + 1) * m + j] / den;
+        H[j * m + j] = den;
+        H[(j + 1) * m + j] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        kk = j + 1;
+        if (!std::isfinite(hnext)) {
+            set_error("mixed GMRES: non-finite Krylov vector");
+            return IMX_ENONFINITE;
+        }
+        if (hnext == 0.0 || std::fabs(g[j + 1]) <= tol * beta) break;
+        svh[j + 1] = 1.0 / hnext;
+        svf[j + 1] = (float)svh[j + 1];
+        CHK(put_scalars(s, sv + j + 1, &svh[j + 1], 1, j + 1));
+        CHK(put_scalars_f(s, s->svf + j + 1, &svf[j + 1], 1, j + 1));
+    }
+    for (int i = kk - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int l = i + 1; l < kk; ++l) t -= H[i * m + l] * yv[l];
+        yv[i] = t / H[i * m + i];
+    }
+    for (int i = 0; i < kk; ++i) cf[i] = yv[i] * svh[i];
+    CHK(put_scalars(s, coef, cf.data(), kk, 100));
+    timed(s, IMX_K_LINCOMB, (kk + 2) * vb, [&] { launch_lincomb<float>(L, kk, V, L, coef, s->xf, s->st); });
+    steps = kk;
+    return IMX_OK;
+}
+
+// Mixed precision: binary64 defect correction x += |r| d, r = b - A x formed
+// in binary64, d from one binary32 GMRES cycle on A d = r/|r| to the relative
+// reduction inner_tol; stops on the same binary64 criterion as the plain path.
+static imx_status pressure_solve_mixed(imx_solver* s, const StageCtx& c, double* x, double bnorm, GmresOut& out) {
+    const int64_t L = s->L;
+    double* bb = s->dsc + imx_solver::S_MISC;
+    timed(s, IMX_K_STAGE, 4 * (double)L * 12.0, [&] {
+        launch_d2f(L, c.rho, s->rhof, s->st);
+        launch_d2f(L, c.pk, s->pkf, s->st);
+    });
+    const bool fixed = s->num.fixed_iterations != 0;
+    int total = 0;
+    double rel = 0.0;
+    for (int outer = 0;; ++outer) {
+        residual(s, c, x, nullptr, s->z1);
+        timed(s, IMX_K_REDUCE, 2 * (double)L * 8.0,
+              [&] { launch_wdot(L, s->z1, nullptr, s->dm.WJ, s->partial, bb, s->st); });
+        CHK(sync_read(s, bb, 1));
+        const double rn = std::sqrt(s->hsc[0]);
+        rel = bnorm > 0 ? rn / bnorm : 0.0;
+        if (!std::isfinite(rn)) {
+            set_error("mixed GMRES: non-finite residual");
+            return IMX_ENONFINITE;
+        }
+        if (rn == 0.0 || total >= s->num.gmres_max || (!fixed && rn <= s->num.gmres_tol * bnorm)) break;
+        // Vf[0] = r / |r| in binary32, d = 0
+        const double inv = 1.0 / rn;
+        CHK(put_scalars(s, bb + 1, &inv, 1, 300));
+        timed(s, IMX_K_STAGE, (double)L * 12.0, [&] {
+            launch_scale_store_f(L, s->z1, bb + 1, s->Vf, s->st);
+            (void)hipMemsetAsync(s->xf, 0, s->Lp * sizeof(float), s->st);
+        });
+        int steps = 0;
+        CHK(inner_cycle_f32(s, c.k, 1.0, s->num.inner_tol, s->num.gmres_max - total, steps));
+        total += steps;
+        CHK(put_scalars(s, bb + 2, &rn, 1, 301));
+        timed(s, IMX_K_STAGE, (double)L * 20.0, [&] { launch_f2d_add(L, s->xf, bb + 2, x, s->st); });
+        if (steps == 0) break;
+    }
+    out.its = total;
+    out.relres = rel;
+    return IMX_OK;
+}
+
 static imx_status pressure_solve(imx_solver* s, const StageCtx& c, double* x, GmresOut& out) {
     const int64_t L = s->L;
     double* bb = s->dsc + imx_solver::S_MISC;
@@ -436,6 +565,7 @@ static imx_status pressure_solve(imx_solver* s, const StageCtx& c, double* x, Gm
           [&] { launch_wdot(L, s->b, nullptr, s->dm.WJ, s->partial, bb, s->st); });
     CHK(sync_read(s, bb, 1));
     const double bnorm = std::sqrt(s->hsc[0]);
+    if (s->num.precision == IMX_MIXED) return pressure_solve_mixed(s, c, x, bnorm, out);
     return gmres(s, c, x, bnorm, s->num.gmres_tol, s->num.gmres_max, s->num.fixed_iterations != 0, out);
 }
 
@@ -632,7 +762,7 @@ imx_status imx_solver_create(const imx_mesh* mesh, const imx_phys* phys, const i
     s->dm.deformed = mesh->m.deformed;
     s->tab = make_tab(mesh->m.basis);
     s->ws_bytes = layout(s, nullptr);
-    if (hipHostMalloc((void**)&s->hsc, 1024 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&s->hsc, 2048 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         delete s;
         set_error("imx_solver_create: pinned host buffer");
         return IMX_ENOMEM;

@@ -204,3 +204,28 @@ def test_step_is_deterministic():
         sol.step(2)
         outs.append(_cpu(sol.get_state()))
     assert np.array_equal(outs[0], outs[1])
+
+
+MIXED_BOUND = 1e-9   # per-field bound of the binary32-inner path (derivation in the design doc)
+
+
+def test_mixed_precision_tiny_box_vs_oracle():
+    """Config 1 in the mixed mode: binary32 Krylov inner loop inside binary64
+    defect correction to the same tolerance, against the FP64 oracle."""
+    B = _B()
+    w = W.tiny_box()
+    gm = B.Mesh(w.mesh)
+    om = OMesh(MeshDesc(**vars(w.mesh)))
+    y0 = W.initial_state(w, om.node_coords())
+    sol = B.Solver(gm, w.phys, w.num, precision=B.IMX_MIXED, inner_tol=1e-3)
+    sol.set_state(y0)
+    st = sol.step(10)
+    g = _cpu(sol.get_state())
+    y = y0
+    for _ in range(10):
+        y, _ = dg.ark2_step(om, dg.Phys(**vars(w.phys)), dg.Numerics(**vars(w.num)), y)
+    scale = state_scales(y)
+    errs = [np.abs(g[t] - y[t]).max() / scale[t] for t in range(5)]
+    assert max(errs) < MIXED_BOUND, errs
+    M0 = dg.total_mass(om, y0)
+    assert abs(sol.total_mass() - M0) <= 1e-13 * M0
