@@ -118,6 +118,104 @@ def mixed_run(w, mesh, q0, args, ref_state, dofs):
             "kernels_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in rep.items() if v[2]}}
 
 
+def served_run(args):
+    """The served ensemble: requests from a seeded Poisson trace are submitted
+    at their arrival times to the server (pool = the HBM budget) and advanced
+    concurrently; the same requests are also run one at a time in arrival
+    order through a plain solver (a queue alone), whose member times give the
+    serial makespan under the same arrivals."""
+    import numpy as np
+    import torch
+    from paper_2605_29598_amd import binding as B
+    from paper_2605_29598_amd import workloads as W
+
+    trace = W.served_trace(n_requests=args.serve_requests, rate_per_s=2.0, elem_min=2000, elem_max=24000,
+                           steps=args.serve_steps, seed=5)
+    meshes, q0s, dofs = [], [], []
+    for r in trace:
+        m = B.Mesh(r.workload.mesh)
+        meshes.append(m)
+        q0s.append(W.initial_state(r.workload, m.node_coords()))
+        dofs.append(5 * m.E * m.Np)
+    total = float(sum(d * r.steps for d, r in zip(dofs, trace)))
+
+    # queue alone: each member's whole life (solver, upload, steps, download) in arrival order
+    dur, alone_steps, finals = [], [], []
+    for r, m, q0 in zip(trace, meshes, q0s):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sol = B.Solver(m, r.workload.phys, r.workload.num)
+        sol.set_state(torch.from_numpy(q0).cuda())
+        for _ in range(r.steps):
+            a = time.perf_counter()
+            sol.step(1)
+            alone_steps.append(1e3 * (time.perf_counter() - a))
+        finals.append(sol.get_state().cpu().numpy())
+        torch.cuda.synchronize()
+        dur.append(time.perf_counter() - t0)
+        del sol
+        print(f"serve: alone {r.workload.name} {dur[-1]:.2f} s", file=sys.stderr, flush=True)
+    end, lat = 0.0, []
+    for r, d in zip(trace, dur):
+        end = max(end, r.arrival_s) + d
+        lat.append(end - r.arrival_s)
+    serial = {"dof_updates_per_s": total / (end - trace[0].arrival_s), "makespan_s": end - trace[0].arrival_s,
+              "step_ms_p50": float(np.percentile(alone_steps, 50)), "step_ms_p99": float(np.percentile(alone_steps, 99)),
+              "request_latency_s_p50": float(np.percentile(lat, 50)),
+              "request_latency_s_p99": float(np.percentile(lat, 99))}
+
+    def served(precision):
+        sv = B.Server(pool_bytes=args.serve_pool_gb << 30, max_running=args.serve_slots)
+        ids, i, t0 = [], 0, time.perf_counter()
+        first = None
+        while True:
+            now = time.perf_counter() - t0
+            while i < len(trace) and trace[i].arrival_s <= now:
+                r = trace[i]
+                ids.append((sv.submit(r.workload.mesh, r.workload.phys, r.workload.num, q0s[i], r.steps,
+                                      precision=precision), time.perf_counter() - t0))
+                first = first if first is not None else ids[-1][1]
+                i += 1
+            nr, nw = sv.tick()
+            if i == len(trace) and nr == 0 and nw == 0:
+                break
+            time.sleep(0.0005)
+        makespan = time.perf_counter() - t0 - first
+        st = sv.query()
+        lat, worst = [], 0.0
+        for k, (rid, t_sub) in enumerate(ids):
+            q, ms = sv.result(rid)
+            if ms.status != B.IMX_OK:
+                raise RuntimeError(f"served member {k} failed with status {ms.status}")
+            lat.append(1e-3 * (ms.queue_ms + ms.run_ms))
+            if precision == B.IMX_FP64:
+                worst = max(worst, float(np.abs(q - finals[k]).max()))
+            else:
+                worst = max(worst, max(field_errors(q, finals[k]).values()))
+        out = {"dof_updates_per_s": total / makespan, "makespan_s": makespan,
+               "step_ms_p50": st.p50_step_ms, "step_ms_p99": st.p99_step_ms,
+               "request_latency_s_p50": float(np.percentile(lat, 50)),
+               "request_latency_s_p99": float(np.percentile(lat, 99)),
+               "pool_gb": args.serve_pool_gb, "pool_peak_gb": st.pool_bytes_peak / 2 ** 30,
+               "slots": args.serve_slots, "completed": st.completed}
+        if precision == B.IMX_FP64:
+            out["max_abs_diff_vs_alone"] = worst
+        else:
+            out["max_rel_error_vs_fp64_alone"] = worst
+        del sv
+        print(f"serve: {'fp64' if precision == B.IMX_FP64 else 'mixed'} makespan {makespan:.2f} s",
+              file=sys.stderr, flush=True)
+        return out
+
+    fp64 = served(B.IMX_FP64)
+    mixed = served(B.IMX_MIXED)
+    return {"workload": f"{len(trace)} requests, Poisson arrivals 2/s, IGW channel or orography members, "
+                        f"elements uniform 2k-24k, degree 2-4, {args.serve_steps} ARK2 steps each",
+            "dof_updates": total, "queue_alone_fp64": serial, "served_fp64": fp64, "served_fp32_inner": mixed,
+            "speedup_served_fp64_vs_queue": fp64["dof_updates_per_s"] / serial["dof_updates_per_s"],
+            "speedup_served_fp32_inner_vs_queue": mixed["dof_updates_per_s"] / serial["dof_updates_per_s"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +225,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-inner comparison run")
     ap.add_argument("--profile-steps", action="store_true", help="print progress per step")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-ensemble run")
+    ap.add_argument("--serve-only", action="store_true", help="run only the served-ensemble comparison")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-steps", type=int, default=20)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-pool-gb", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -136,6 +240,9 @@ def main():
     from paper_2605_29598_amd import binding as B
     from paper_2605_29598_amd import workloads as W
 
+    if args.serve_only:
+        print(json.dumps({"served": served_run(args)}))
+        return
     w = W.igw_channel(scheme=B.IMX_R1 if args.scheme == "R1" else B.IMX_R2)
     mesh = B.Mesh(w.mesh)
     sol = B.Solver(mesh, w.phys, w.num, device="cuda:0")
@@ -195,6 +302,8 @@ def main():
     }
     if not args.no_mixed:
         out["fp32_inner"] = mixed_run(w, mesh, q0, args, sol.get_state().cpu().numpy(), dofs)
+    if not args.no_serve:
+        out["served"] = served_run(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -213,6 +213,51 @@ imx_status imx_solver_timing(imx_solver* s, int enable);
 imx_status imx_solver_timing_report(imx_solver* s, int kind, double* total_ms, double* bytes,
                                     int64_t* launches);
 
+/* ------------------------------------------------------------ serving */
+/* Ensemble server: integrations of different meshes, degrees and physics
+ * share one device memory pool (the HBM budget). Requests wait in arrival
+ * order; imx_server_tick admits every waiting request whose workspace fits
+ * the free pool while fewer than max_running members run, and reaps members
+ * that have finished (their memory returns to the pool). Each running member
+ * owns a HIP stream and a host worker thread that advances it step by step,
+ * so members admitted at different times overlap on the device. A member's
+ * result does not depend on what runs beside it (no shared buffers, fixed
+ * reduction orders). */
+typedef struct imx_server imx_server;
+
+typedef struct {
+    int steps_done;
+    int status;                  /* imx_status of the member's last step */
+    double p50_step_ms, p99_step_ms, mean_step_ms;
+    double queue_ms;             /* submit -> admission */
+    double run_ms;               /* admission -> last step done */
+    int64_t gmres_iters;
+} imx_member_stats;
+
+typedef struct {
+    int64_t submitted, admitted, completed, rejected, running, waiting;
+    size_t pool_bytes, pool_bytes_in_use, pool_bytes_peak;
+    double p50_step_ms, p99_step_ms;   /* over every member step so far */
+    double dof_updates;                /* sum over members of 5 E Np x steps done */
+    double busy_seconds;               /* first admission -> last completion */
+} imx_server_stats;
+
+/* pool_dev: caller-owned device memory of pool_bytes (256-byte aligned) on the
+ * current device; it must outlive the server. */
+imx_status imx_server_create(void* pool_dev, size_t pool_bytes, int max_running, imx_server** out);
+/* Queues nsteps IMEX-ARK2 steps of a member starting from q0_host [5][E][Np]
+ * (copied). IMX_EREJECT if its workspace can never fit the pool. */
+imx_status imx_server_submit(imx_server* sv, const imx_mesh_desc* mesh, const imx_phys* phys,
+                             const imx_numerics* num, const double* q0_host, int nsteps, uint64_t* id);
+/* Reaps finished members and admits waiting ones; returns the counts. */
+imx_status imx_server_tick(imx_server* sv, int* n_running, int* n_waiting);
+/* Final state [5][E][Np] (host) and statistics of a finished member;
+ * IMX_ESTATE while it has not finished, IMX_EINVAL for an unknown id. */
+imx_status imx_server_result(imx_server* sv, uint64_t id, double* q_host, imx_member_stats* stats);
+imx_status imx_server_query(imx_server* sv, imx_server_stats* stats);
+/* Waits for running members, then destroys the server. */
+void imx_server_destroy(imx_server* sv);
+
 /* Description of the last error raised on the calling thread. */
 const char* imx_last_error(void);
 

@@ -56,6 +56,20 @@ class imx_step_stats(ctypes.Structure):
                 ("mass", ctypes.c_double)]
 
 
+class imx_member_stats(ctypes.Structure):
+    _fields_ = [("steps_done", ctypes.c_int), ("status", ctypes.c_int), ("p50_step_ms", ctypes.c_double),
+                ("p99_step_ms", ctypes.c_double), ("mean_step_ms", ctypes.c_double), ("queue_ms", ctypes.c_double),
+                ("run_ms", ctypes.c_double), ("gmres_iters", ctypes.c_int64)]
+
+
+class imx_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("running", ctypes.c_int64), ("waiting", ctypes.c_int64),
+                ("pool_bytes", ctypes.c_size_t), ("pool_bytes_in_use", ctypes.c_size_t),
+                ("pool_bytes_peak", ctypes.c_size_t), ("p50_step_ms", ctypes.c_double),
+                ("p99_step_ms", ctypes.c_double), ("dof_updates", ctypes.c_double), ("busy_seconds", ctypes.c_double)]
+
+
 # name -> (restype, argtypes); the exported symbol set of include/imexdg.h
 SIGNATURES = {
     "imx_last_error": (ctypes.c_char_p, []),
@@ -81,6 +95,14 @@ SIGNATURES = {
     "imx_solver_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
     "imx_solver_timing_report": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                                 ctypes.POINTER(ctypes.c_double), _c_i64p]),
+    "imx_server_create": (ctypes.c_int, [_vp, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "imx_server_submit": (ctypes.c_int, [_vp, ctypes.POINTER(imx_mesh_desc), ctypes.POINTER(imx_phys),
+                                         ctypes.POINTER(imx_numerics), _vp, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+    "imx_server_tick": (ctypes.c_int, [_vp, _c_ip, _c_ip]),
+    "imx_server_result": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, ctypes.POINTER(imx_member_stats)]),
+    "imx_server_query": (ctypes.c_int, [_vp, ctypes.POINTER(imx_server_stats)]),
+    "imx_server_destroy": (None, [_vp]),
 }
 
 KERNEL_KINDS = ["explicit", "pass1", "pass2", "lambda", "dots", "ortho", "lincomb", "stage", "reduce"]
@@ -263,4 +285,87 @@ class Solver:
             except Exception:
                 pass
             _lib.imx_solver_destroy(self.h)
+            self.h = None
+
+
+def member_pool_bytes(mesh: Mesh, phys: W.PhysSpec, num: W.NumSpec, precision=IMX_FP64, inner_tol=1e-3):
+    """Pool bytes a server member of this configuration takes while it runs:
+    the solver workspace plus the device copy of its state, each 256-byte
+    aligned."""
+    ph, nm = phys_struct(phys), num_struct(num, precision, inner_tol)
+    h = _vp()
+    check(lib().imx_solver_create(mesh.h, ctypes.byref(ph), ctypes.byref(nm), None, ctypes.byref(h)),
+          "imx_solver_create")
+    nb = ctypes.c_size_t()
+    try:
+        check(lib().imx_solver_workspace_bytes(h, ctypes.byref(nb)), "imx_solver_workspace_bytes")
+    finally:
+        lib().imx_solver_destroy(h)
+    return nb.value + ((5 * mesh.E * mesh.Np * 8 + 255) // 256) * 256
+
+
+class Server:
+    """Ensemble server over a torch-allocated device pool of `pool_bytes`
+    (the HBM budget); members are (mesh, phys, numerics, q0, nsteps)."""
+
+    def __init__(self, pool_bytes, max_running=4, device="cuda:0"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available")
+        self.device = torch.device(device)
+        self.pool = torch.empty(int(pool_bytes) + 256, dtype=torch.uint8, device=self.device)
+        base = self.pool.data_ptr()
+        off = (-base) % 256
+        torch.cuda.synchronize(self.device)
+        h = _vp()
+        with torch.cuda.device(self.device):
+            check(lib().imx_server_create(ctypes.c_void_p(base + off), int(pool_bytes), int(max_running),
+                                          ctypes.byref(h)), "imx_server_create")
+        self.h = h
+        self.shapes = {}
+
+    def submit(self, spec: W.MeshSpec, phys: W.PhysSpec, num: W.NumSpec, q0, nsteps, precision=IMX_FP64,
+               inner_tol=1e-3):
+        d, boxes = _desc(spec)
+        ph, nm = phys_struct(phys), num_struct(num, precision, inner_tol)
+        q = np.ascontiguousarray(np.asarray(q0, dtype=np.float64))
+        rid = ctypes.c_uint64()
+        with torch.cuda.device(self.device):
+            check(lib().imx_server_submit(self.h, ctypes.byref(d), ctypes.byref(ph), ctypes.byref(nm),
+                                          q.ctypes.data_as(_vp), int(nsteps), ctypes.byref(rid)),
+                  "imx_server_submit")
+        self.shapes[rid.value] = q.shape
+        return rid.value
+
+    def tick(self):
+        r, w = ctypes.c_int(), ctypes.c_int()
+        with torch.cuda.device(self.device):
+            check(lib().imx_server_tick(self.h, ctypes.byref(r), ctypes.byref(w)), "imx_server_tick")
+        return r.value, w.value
+
+    def result(self, rid):
+        """(final state, member stats) or None while the member has not finished."""
+        out = np.empty(self.shapes[rid], dtype=np.float64)
+        st = imx_member_stats()
+        code = lib().imx_server_result(self.h, ctypes.c_uint64(rid), out.ctypes.data_as(_vp), ctypes.byref(st))
+        if code == IMX_ESTATE:
+            return None
+        check(code, "imx_server_result")
+        return out, st
+
+    def query(self):
+        st = imx_server_stats()
+        check(lib().imx_server_query(self.h, ctypes.byref(st)), "imx_server_query")
+        return st
+
+    def drain(self, poll_s=0.001):
+        import time
+        while True:
+            r, w = self.tick()
+            if r == 0 and w == 0:
+                return
+            time.sleep(poll_s)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.imx_server_destroy(self.h)
             self.h = None

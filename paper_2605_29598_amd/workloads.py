@@ -208,3 +208,36 @@ def conserved_from_primitive(rho, u, p):
     q[1:4] = rho * u
     q[4] = p / (GAMMA - 1.0) + 0.5 * rho * (u * u).sum(0)
     return q
+
+
+# ------------------------------------------------------------ served ensemble
+@dataclass
+class Request:
+    arrival_s: float
+    workload: Workload
+    steps: int
+
+
+def served_trace(n_requests=64, rate_per_s=2.0, elem_min=2000, elem_max=200000, degrees=(2, 3, 4), steps=50,
+                 seed=5):
+    """Ensemble requests with Poisson arrivals: exponential gaps of mean
+    1/rate, each member a rotating IGW channel or an orography member with
+    element count uniform in [elem_min, elem_max] (rounded to the nearest
+    layout the family allows), degree drawn from `degrees`, and a seeded
+    1e-6 perturbation of its own."""
+    g = np.random.default_rng(seed)
+    t, out = 0.0, []
+    for k in range(n_requests):
+        t += g.exponential(1.0 / rate_per_s)
+        E = g.uniform(elem_min, elem_max)
+        r = int(g.choice(degrees))
+        if g.uniform() < 0.5:
+            ny = max(2, int(round(np.sqrt(E / 30.0))))
+            w = igw_channel(nx=3 * ny, ny=ny, nz=10, degree=r)
+        else:
+            n = max(3, int(round(np.sqrt(E / 12.0))))
+            w = orography(nx=n, ny=n, nz=12, degree=r)
+        w.noise, w.seed = 1e-6, 1000 + k
+        w.name += "_m%d" % k
+        out.append(Request(t, w, steps))
+    return out
