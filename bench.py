@@ -13,7 +13,6 @@ bytes / HIP-event time on the solver stream), and the CPU oracle timed on a
 bounded sample of the same workload.
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -27,14 +26,6 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "DoF-updates/s per IMEX step (FP64 vs FP32-inner); operator GB/s; p99 latency"
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "vec.hip"):
-        with open(os.path.join(ROOT, "paper_2605_29598_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(kind):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if the
     kernels have not changed since it was taken."""
@@ -43,6 +34,7 @@ def measured_traffic(kind):
         return None
     with open(path) as fh:
         rec = json.load(fh)
+    from paper_2605_29598_amd.profiling import kernel_source_hash
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     k = rec.get("kernels", {}).get(kind)
@@ -231,6 +223,8 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=20)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-pool-gb", type=int, default=64)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only a 1 GiB device-to-device copy, the calibration run for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -240,6 +234,18 @@ def main():
     from paper_2605_29598_amd import binding as B
     from paper_2605_29598_amd import workloads as W
 
+    if args.copy_probe:
+        n = 1 << 30
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / 5
+        print(json.dumps({"copy_bytes": n, "GB_per_s_read_plus_write": 2 * n / el / 1e9}))
+        return
     if args.serve_only:
         print(json.dumps({"served": served_run(args)}))
         return

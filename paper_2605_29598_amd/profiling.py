@@ -1,0 +1,98 @@
+"""HBM traffic per kernel class from rocprofv3 counter runs.
+
+Two `rocprofv3 --pmc` passes over the same command give FETCH_SIZE and
+WRITE_SIZE (KiB per dispatch). Each is scaled by what the same counter reads
+for a plain device copy of known size (run with `bench.py --copy-probe`), so
+the result is in bytes of HBM traffic. The summary is keyed by the kernel
+classes the solver's own timers use and stamped with a hash of the kernel
+sources: a summary taken from other kernels is not used.
+
+    python -m paper_2605_29598_amd.profiling \
+        --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \
+        --copy-bytes 1073741824 --out profiles/pmc_traffic.json
+"""
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+# kernel-name stem -> class reported by the solver's timers
+CLASSES = {
+    "k_explicit": "explicit", "k_pass1": "pass1", "k_pass2": "pass2", "k_lambda": "lambda",
+    "k_dots": "dots", "k_axpy_norm": "ortho", "k_axpy_red": "ortho", "k_lincomb": "lincomb",
+}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "vec.hip"):
+        with open(os.path.join(_HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _load(path, counter):
+    per = collections.defaultdict(list)
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return per
+
+
+def _stem(name):
+    m = re.search(r"(k_[a-z0-9_]+)", name)
+    return m.group(1) if m else name
+
+
+def _copy_factor(path, counter, nbytes):
+    per = _load(path, counter)
+    # the copy of nbytes is the dispatch with the largest count
+    best = max((max(v), k) for k, v in per.items())[0]
+    return nbytes / (best * 1024.0), best
+
+
+def summarize(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes):
+    ff, fraw = _copy_factor(copy_fetch_csv, "FETCH_SIZE", copy_bytes)
+    wf, wraw = _copy_factor(copy_write_csv, "WRITE_SIZE", copy_bytes)
+    F, Wr = _load(fetch_csv, "FETCH_SIZE"), _load(write_csv, "WRITE_SIZE")
+    kernels, classes = {}, collections.defaultdict(lambda: [0.0, 0])
+    for name, v in F.items():
+        w = Wr.get(name, [0.0])
+        fb = ff * 1024.0 * sum(v) / len(v)
+        wb = wf * 1024.0 * sum(w) / len(w)
+        kernels[name] = {"dispatches": len(v), "fetch_bytes": fb, "write_bytes": wb, "bytes_per_dispatch": fb + wb}
+        c = CLASSES.get(_stem(name))
+        if c:
+            classes[c][0] += (fb + wb) * len(v)
+            classes[c][1] += len(v)
+    return {
+        "kernel_source_hash": kernel_source_hash(),
+        "calibration": {"copy_bytes": copy_bytes, "fetch_KiB": fraw, "write_KiB": wraw,
+                        "fetch_factor": ff, "write_factor": wf},
+        "kernels": {c: {"bytes_per_launch": b / n, "dispatches": n} for c, (b, n) in classes.items()},
+        "per_kernel": kernels,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    for a in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--out"):
+        ap.add_argument(a, required=True)
+    ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--command", default="")
+    a = ap.parse_args()
+    rec = summarize(a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes)
+    rec["command"] = a.command
+    with open(a.out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()
