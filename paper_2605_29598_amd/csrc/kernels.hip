@@ -36,6 +36,9 @@ struct Tab {
     R f[2][N];      // f[s][i] = l_i(s)
     R H[2][N][N];   // H[h][a][i] = l_i((h + x_a)/2)
     R w[N];
+    R W2[N * N];        // w_a w_b at face point a + N b
+    R W3[N * N * N];    // w_i w_j w_k at node i + N (j + N k)
+    R iW3[N * N * N];   // 1 / W3
 };
 
 template <int N, typename R>
@@ -49,6 +52,15 @@ static Tab<N, R> to_tab(const HostTab& h) {
         for (int a = 0; a < N; ++a)
             for (int i = 0; i < N; ++i) t.H[hh][a][i] = (R)h.H[(hh * N + a) * N + i];
     for (int i = 0; i < N; ++i) t.w[i] = (R)h.w[i];
+    for (int b = 0; b < N; ++b)
+        for (int a = 0; a < N; ++a) t.W2[a + N * b] = (R)(h.w[a] * h.w[b]);
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                const double W = h.w[i] * h.w[j] * h.w[k];   // the same product as the host's W detJ
+                t.W3[i + N * (j + N * k)] = (R)W;
+                t.iW3[i + N * (j + N * k)] = (R)(1.0 / W);
+            }
     return t;
 }
 
@@ -99,17 +111,19 @@ struct Geom {
     const R* WJ;
     const R* G;
     const R* nS;
+    const double* eg;     // affine elements: h[3], 1/h[3], det J, 1/det J (8 per element)
+    const R* iWJ;         // 1 / WJ (deformed meshes)
 };
 
 template <typename R>
 static Geom<R> geom(const DevMesh& m);
 template <>
 Geom<double> geom<double>(const DevMesh& m) {
-    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJ, m.G, m.nS};
+    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJ, m.G, m.nS, m.eg, m.iWJ};
 }
 template <>
 Geom<float> geom<float>(const DevMesh& m) {
-    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJf, m.Gf, m.nSf};
+    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJf, m.Gf, m.nSf, m.eg, m.iWJf};
 }
 
 constexpr int epb_of(int N) { return N == 2 ? 16 : (N == 3 ? 9 : (N == 4 ? 4 : 2)); }
@@ -136,22 +150,35 @@ __device__ __forceinline__ void split_node(int d, int node, int& m, int& pt) {
     else { m = k; pt = i + N * j; }
 }
 
-// products and sums with one rounding each (no contraction into fma), so that
-// a trace formed from products staged in LDS rounds exactly like face_value
+// products and sums with one rounding each (no contraction into fma)
 __device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
 __device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
 __device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
 __device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
+__device__ __forceinline__ double fma_rn(double a, double b, double c) { return __fma_rn(a, b, c); }
+__device__ __forceinline__ float fma_rn(float a, float b, float c) { return __fmaf_rn(a, b, c); }
 
-// value of a Q_r field (nodal array f of one element) at face point pt:
-// sum over m (in order) of l_m(s) f(m along the normal)
+// Trace of a Q_r field along the normal: sum over m (in order) of
+// l_m(s) v_m as one product and a chain of fused multiply-adds. Every trace
+// of the library, whether its values come from LDS, registers or global
+// memory, is formed by this chain, so both sides of a face see the same
+// bits.
+template <int N, typename R>
+__device__ __forceinline__ R trace_chain(const R* fv, const R* v) {
+    R acc = mul_rn(fv[0], v[0]);
+#pragma unroll
+    for (int m = 1; m < N; ++m) acc = fma_rn(fv[m], v[m], acc);
+    return acc;
+}
+
+// value of a Q_r field (nodal array f of one element) at face point pt
 template <int N, typename R, typename P>
 __device__ __forceinline__ R face_value(const P* f, const R* fv, int d, int pt) {
     const int a = pt % N, b = pt / N;
-    R acc = mul_rn(fv[0], (R)f[node_of<N>(d, 0, a, b)]);
+    R v[N];
 #pragma unroll
-    for (int m = 1; m < N; ++m) acc = add_rn(acc, mul_rn(fv[m], (R)f[node_of<N>(d, m, a, b)]));
-    return acc;
+    for (int m = 0; m < N; ++m) v[m] = (R)f[node_of<N>(d, m, a, b)];
+    return trace_chain<N, R>(fv, v);
 }
 
 // face polynomial with GL values fv (LDS) at GL point pt of quarter h
@@ -547,10 +574,7 @@ k_pass1(const int* __restrict__ elist, int64_t nel, const R* __restrict__ p, con
                     const R pa = sc * face_value<N>(&s_p[le][0], T.f[s], d, pt);
                     R pb = pa;
                     if (kind == CONF) {
-                        R t = mul_rn(T.f[1 - s][0], nbv[r][0]);
-#pragma unroll
-                        for (int m = 1; m < N; ++m) t = add_rn(t, mul_rn(T.f[1 - s][m], nbv[r][m]));
-                        pb = sc * t;
+                        pb = sc * trace_chain<N, R>(T.f[1 - s], nbv[r]);
                     } else if (kind == FINE) {
                         pb = sc * coarse_point<N>(p + (size_t)s_nbr[le][f] * NP, T.f[1 - s], T, d,
                                                   g.aux[e * 6 + f] & 3, pt);
@@ -671,7 +695,7 @@ k_pass1(const int* __restrict__ elist, int64_t nel, const R* __restrict__ p, con
             wv[1] = v[1];
             wv[2] = v[2];
         } else {
-            const R si = (R)1 / ((R)1 + beta * beta);
+            const R si = (R)sk.rot_si;
             wv[0] = si * (v[0] + beta * v[1]);
             wv[1] = si * (-beta * v[0] + v[1]);
             wv[2] = v[2];
@@ -684,7 +708,7 @@ k_pass1(const int* __restrict__ elist, int64_t nel, const R* __restrict__ p, con
     if (!FB) return;
     __syncthreads();
     // face buffers: (rho h)^k (w . nS) on this element's side of every face
-    const R hfac = gam / (gam - (R)1);
+    const R hfac = (R)sk.hfac;
     if (!slow) {
         if (act)
             for (int it = node; it < 6 * NF; it += NP) {
@@ -760,7 +784,7 @@ k_pass2(const int* __restrict__ elist, int64_t nel, const R* __restrict__ Gp, co
     if (act) {
         wj = g.WJ[e * NP + node];
         for (int c = 0; c < 3; ++c) wv[c] = w[c * fs + e * NP + node];
-        rh = gam / (gam - (R)1) * pk[e * NP + node];
+        rh = (R)sk.hfac * pk[e * NP + node];
         if (sk.scheme == 2) rl = rho[e * NP + node];
         if (Gp) gp = Gp[e * NP + node];
         if (p) pv = (pscale ? pscale[0] : (R)1) * p[e * NP + node];
@@ -841,7 +865,7 @@ k_pass2(const int* __restrict__ elist, int64_t nel, const R* __restrict__ Gp, co
         acc -= div_T<N>(&s_vol[le][0][0], T, node);
         const R cdt = (R)sk.c_dt;
         res = gp;
-        if (p) res -= pv / (gam - (R)1);
+        if (p) res -= pv * (R)sk.igm1;
         res -= cdt * acc / wj;
         if (sk.scheme == 2) res -= cdt * (R)sk.g * rl * wv[2];
         res *= alpha;
@@ -873,6 +897,301 @@ k_pass2(const int* __restrict__ elist, int64_t nel, const R* __restrict__ Gp, co
         double t = 0;
         for (int k = 0; k < threads_of(N) / 64; ++k) t += s_red[k][tid];
         partial[(size_t)blockIdx.x * (nv + 1) + tid] = t;
+    }
+}
+
+// =====================================================================
+// Schur complement inside the Krylov loop: z = M^{-1} S (sc x). Specialised
+// instances of passes 1 and 2 for the elements without a coarse hanging face:
+// no right-hand side, the scheme and the geometry class (affine or
+// isoparametric) fixed at compile time, one coefficient cr = 1/(W detJ rho_l)
+// per node instead of W detJ and rho_l with two divisions, and on affine
+// elements W detJ, the face areas and the metric formed from the tensor
+// weights and the element's edge lengths instead of read per node.
+// =====================================================================
+template <int N, typename R, bool AFF>
+struct ElemGeo {
+    // scalar members (an array here would be indexed through scratch memory)
+    R hi0 = 0, hi1 = 0, hi2 = 0, dJ = 0, idJ = 0, A0 = 0, A1 = 0, A2 = 0;
+    __device__ __forceinline__ void load(const double* __restrict__ eg, int e) {
+        if constexpr (AFF) {
+            const double* q = eg + (size_t)e * 8;
+            const double h0 = q[0], h1 = q[1], h2 = q[2];
+            hi0 = (R)q[3];
+            hi1 = (R)q[4];
+            hi2 = (R)q[5];
+            dJ = (R)q[6];
+            idJ = (R)q[7];
+            A0 = (R)(h1 * h2);   // area factor h_t1 h_t2 of the faces normal to x, y, z
+            A1 = (R)(h0 * h2);
+            A2 = (R)(h0 * h1);
+        }
+    }
+    __device__ __forceinline__ R hi(int d) const { return d == 0 ? hi0 : (d == 1 ? hi1 : hi2); }
+};
+
+template <int N, typename R, bool AFF, int SCH>
+__global__ void __launch_bounds__(threads_of(N))
+k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
+      const R* __restrict__ cr, const R* __restrict__ pk, R* __restrict__ w, R* __restrict__ FB, Geom<R> g,
+      const Tab<N, R>* __restrict__ Tg, StageK sk) {
+    constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
+    constexpr int NR = (6 * NF + NP - 1) / NP;   // face points per lane
+    constexpr int LF = AFF ? 6 * NF : 18 * NF, LV = AFF ? NP : 3 * NP;
+    __shared__ R s_p[EPB][NP];
+    __shared__ R s_pk[EPB][NP];
+    __shared__ R s_w[EPB][3][NP];
+    __shared__ R s_u[EPB][LF > LV ? LF : LV];
+    __shared__ R s_A[EPB][3];   // affine: face area factor h_t1 h_t2 per direction
+    __shared__ Tab<N, R> T;
+    load_tab<N, R>(Tg, &T);
+    const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
+    const int slot = (int)xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+    const bool act = le < EPB && slot < nel;
+    const int e = act ? (elist ? elist[slot] : slot) : 0;
+    const unsigned fs = (unsigned)g.E * NP, o = (unsigned)e * NP + node;
+    const R sc = pscale ? pscale[0] : (R)1;
+    R* U = &s_u[le][0];
+    // all global loads before the first barrier: own values, the lane's face
+    // table entries and the neighbour values along the normal
+    R crv = 0, nbv[NR][N];
+    int kf[NR], nf[NR];
+    ElemGeo<N, R, AFF> eg;
+    if (act) {
+        s_p[le][node] = p[o];
+        s_pk[le][node] = pk[o];
+        crv = cr[o];
+        eg.load(g.eg, e);
+        if (AFF && node < 3) s_A[le][node] = node == 0 ? eg.A0 : (node == 1 ? eg.A1 : eg.A2);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int it = node + r * NP;
+            const int f = it < 6 * NF ? it / NF : 5;
+            kf[r] = it < 6 * NF ? g.kind[e * 6 + f] : WALL;
+            nf[r] = g.nbr[e * 6 + f];
+            const int pt = it - f * NF, d = f >> 1, a = pt % N, b = pt / N;
+            const bool ld = kf[r] == CONF;
+            const R* src = p + (size_t)(unsigned)(ld ? nf[r] : 0) * NP;
+#pragma unroll
+            for (int m = 0; m < N; ++m) nbv[r][m] = ld ? src[node_of<N>(d, m, a, b)] : (R)0;
+        }
+    }
+    __syncthreads();
+    // {p} n dS at every face point
+    if (act)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int it = node + r * NP;
+            if (it >= 6 * NF) continue;
+            const int f = it / NF, pt = it - f * NF, d = f >> 1, s = f & 1;
+            R vals[N];
+#pragma unroll
+            for (int m = 0; m < N; ++m) vals[m] = s_p[le][node_of<N>(d, m, pt % N, pt / N)];
+            const R pa = sc * trace_chain<N, R>(T.f[s], vals);
+            R pb = pa;
+            if (kf[r] == CONF) pb = sc * trace_chain<N, R>(T.f[1 - s], nbv[r]);
+            else if (kf[r] == FINE)
+                pb = sc * coarse_point<N>(p + (size_t)(unsigned)nf[r] * NP, T.f[1 - s], T, d, g.aux[e * 6 + f] & 3, pt);
+            const R avg = (R)0.5 * (pa + pb);
+            if constexpr (AFF) {
+                const R Af = T.W2[pt] * s_A[le][d];
+                U[f * NF + pt] = avg * (s ? Af : -Af);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) U[(f * 3 + c) * NF + pt] = avg * g.nS[((size_t)(e * 6 + f) * 3 + c) * NF + pt];
+            }
+        }
+    __syncthreads();
+    R acc[3] = {0, 0, 0};
+    if (act) {
+        if constexpr (AFF) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                int m, pt;
+                split_node<N>(d, node, m, pt);
+                acc[d] += T.f[0][m] * U[(2 * d) * NF + pt];
+                acc[d] += T.f[1][m] * U[(2 * d + 1) * NF + pt];
+            }
+        } else {
+            for (int f = 0; f < 6; ++f) {
+                int m, pt;
+                split_node<N>(f >> 1, node, m, pt);
+                const R lf = T.f[f & 1][m];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[c] += lf * U[(f * 3 + c) * NF + pt];
+            }
+        }
+    }
+    __syncthreads();
+    // volume: -int (sc p) div(phi_c)
+    const R pv = act ? sc * s_p[le][node] : (R)0;
+    if constexpr (AFF) {
+        if (act) U[node] = (T.W3[node] * eg.dJ) * pv;
+        __syncthreads();
+        if (act) {
+            const int i = node % N, j = (node / N) % N, k = node / (N * N);
+            R d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                d0 += T.D[q][i] * U[q + N * (j + N * k)];
+                d1 += T.D[q][j] * U[i + N * (q + N * k)];
+                d2 += T.D[q][k] * U[i + N * (j + N * q)];
+            }
+            acc[0] -= d0 * eg.hi0;
+            acc[1] -= d1 * eg.hi1;
+            acc[2] -= d2 * eg.hi2;
+        }
+    } else {
+        for (int c = 0; c < 3; ++c) {
+            if (act)
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) U[dd * NP + node] = g.G[(size_t)((dd * 3 + c) * fs) + o] * pv;
+            __syncthreads();
+            if (act) acc[c] -= div_T<N>(U, T, node);
+            __syncthreads();
+        }
+    }
+    // w = (I + beta J)^{-1} A^{-1} (-B p) [R2] or A^{-1}(-B p) [R1]
+    if (act) {
+        const R cdt = (R)sk.c_dt, beta = (R)sk.beta;
+        R v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = -(cdt * acc[c]) * crv;
+        R wv[3];
+        if constexpr (SCH == 2) {
+            const R si = (R)sk.rot_si;
+            wv[0] = si * (v[0] + beta * v[1]);
+            wv[1] = si * (-beta * v[0] + v[1]);
+            wv[2] = v[2];
+        } else {
+            wv[0] = v[0];
+            wv[1] = v[1];
+            wv[2] = v[2];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            w[(size_t)(c * fs + o)] = wv[c];
+            s_w[le][c][node] = wv[c];
+        }
+    }
+    __syncthreads();
+    // face buffer: (rho h)^k (w . n dS) on this element's side of each face
+    if (act) {
+        const R hfac = (R)sk.hfac;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int it = node + r * NP;
+            if (it >= 6 * NF || kf[r] == WALL) continue;
+            const int f = it / NF, pt = it - f * NF, d = f >> 1, s = f & 1;
+            const int a = pt % N, b = pt / N;
+            R vk[N];
+#pragma unroll
+            for (int m = 0; m < N; ++m) vk[m] = s_pk[le][node_of<N>(d, m, a, b)];
+            const R hk = hfac * trace_chain<N, R>(T.f[s], vk);
+            R fbv;
+            if constexpr (AFF) {
+                R vw[N];
+#pragma unroll
+                for (int m = 0; m < N; ++m) vw[m] = s_w[le][d][node_of<N>(d, m, a, b)];
+                const R Af = T.W2[pt] * s_A[le][d];
+                fbv = hk * (trace_chain<N, R>(T.f[s], vw) * (s ? Af : -Af));
+            } else {
+                R wn = 0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    R vw[N];
+#pragma unroll
+                    for (int m = 0; m < N; ++m) vw[m] = s_w[le][c][node_of<N>(d, m, a, b)];
+                    wn += trace_chain<N, R>(T.f[s], vw) * g.nS[((size_t)(e * 6 + f) * 3 + c) * NF + pt];
+                }
+                fbv = hk * wn;
+            }
+            FB[(size_t)(unsigned)(e * 6 + f) * NF + pt] = fbv;
+        }
+    }
+}
+
+template <int N, typename R, bool AFF, int SCH>
+__global__ void __launch_bounds__(threads_of(N))
+k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
+      const R* __restrict__ w, const R* __restrict__ pk, const R* __restrict__ rho, const R* __restrict__ FB,
+      const R* __restrict__ FBh, R* __restrict__ out, int dual, Geom<R> g, const Tab<N, R>* __restrict__ Tg,
+      StageK sk) {
+    constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
+    constexpr int NR = (6 * NF + NP - 1) / NP;
+    __shared__ R s_face[EPB][6 * NF];
+    __shared__ R s_vol[EPB][3][NP];
+    __shared__ Tab<N, R> T;
+    load_tab<N, R>(Tg, &T);
+    const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
+    const int slot = (int)xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+    const bool act = le < EPB && slot < nel;
+    const int e = act ? (elist ? elist[slot] : slot) : 0;
+    const unsigned fs = (unsigned)g.E * NP, o = (unsigned)e * NP + node;
+    R* U = &s_face[le][0];
+    R wv[3] = {0, 0, 0}, rh = 0, rl = 0, pv = 0;
+    ElemGeo<N, R, AFF> eg;
+    if (act) {
+        eg.load(g.eg, e);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) wv[c] = w[(size_t)(c * fs + o)];
+        rh = (R)sk.hfac * pk[o];
+        if constexpr (SCH == 2) rl = rho[o];
+        pv = (pscale ? pscale[0] : (R)1) * p[o];
+        // {(rho h)^k w} . n dS from the two sides' face buffers
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int it = node + r * NP;
+            if (it >= 6 * NF) continue;
+            const int f = it / NF, pt = it - f * NF;
+            const int kind = g.kind[e * 6 + f];
+            R v = 0;
+            if (kind == CONF) {
+                const int nb = g.nbr[e * 6 + f];
+                v = (R)0.5 * (FB[(size_t)(unsigned)(e * 6 + f) * NF + pt] - FB[(size_t)(unsigned)(nb * 6 + (f ^ 1)) * NF + pt]);
+            } else if (kind == FINE) {
+                const int aux = g.aux[e * 6 + f];
+                v = (R)0.5 * (FB[(size_t)(unsigned)(e * 6 + f) * NF + pt] -
+                              FBh[(size_t)(unsigned)((aux >> 2) * 4 + (aux & 3)) * NF + pt]);
+            }
+            U[f * NF + pt] = v;
+        }
+        // contravariant (rho h)^k w for the volume term
+        if constexpr (AFF) {
+            const R wj = T.W3[node] * eg.dJ;
+#pragma unroll
+            for (int dd = 0; dd < 3; ++dd) s_vol[le][dd][node] = rh * ((wj * eg.hi(dd)) * wv[dd]);
+        } else {
+#pragma unroll
+            for (int dd = 0; dd < 3; ++dd) {
+                R v = 0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v += g.G[(size_t)((dd * 3 + c) * fs) + o] * wv[c];
+                s_vol[le][dd][node] = rh * v;
+            }
+        }
+    }
+    __syncthreads();
+    if (!act) return;
+    R acc = 0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        int m, pt;
+        split_node<N>(f >> 1, node, m, pt);
+        acc += T.f[f & 1][m] * U[f * NF + pt];
+    }
+    acc -= div_T<N>(&s_vol[le][0][0], T, node);
+    const R iwj = AFF ? T.iW3[node] * eg.idJ : g.iWJ[o];
+    const R cdt = (R)sk.c_dt;
+    R res = -(pv * (R)sk.igm1);
+    res -= cdt * acc * iwj;
+    if constexpr (SCH == 2) res -= cdt * (R)sk.g * rl * wv[2];
+    // z = -res = M^{-1} S (sc x); the dual form is S (sc x) = -res W detJ
+    if (dual) {
+        const R wj = AFF ? T.W3[node] * eg.dJ : g.WJ[o];
+        out[o] = -res * wj;
+    } else {
+        out[o] = -res;
     }
 }
 
@@ -1110,6 +1429,70 @@ template void launch_pass2<float>(const DevMesh&, const HostTab&, const StageK&,
                                   const float*, const float*, const float*, const float*, const float*,
                                   const float*, float*, double, int, hipStream_t, const float*, int, double*,
                                   double*);
+
+template <typename R, int N, bool AFF, int SCH>
+static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
+                 const R* pk, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st) {
+    constexpr int EPB = epb_of(N);
+    const Tab<N, R>* T = (const Tab<N, R>*)tab_ptr<R>(m);
+    const int64_t nf = m.ncoarse ? m.E - m.ncoarse : m.E, ns = m.ncoarse;
+    const int64_t bf = (nf + EPB - 1) / EPB, bs = (ns + EPB - 1) / EPB;
+    const int* fl = m.ncoarse ? m.reg_list : nullptr;
+    if (!out) {
+        if (bf > 0)
+            hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_of(N)), 0, st, fl, (int)nf, x,
+                               xs, cr, pk, w, FB, geom<R>(m), T, sk);
+        if (bs > 0)
+            hipLaunchKernelGGL((k_pass1<N, R, true>), dim3((unsigned)bs), dim3(threads_of(N)), 0, st, m.crs_list, ns,
+                               x, xs, (const R*)nullptr, rho, pk, (const R*)nullptr, w, FB, FBh, geom<R>(m), T, sk);
+    } else {
+        if (bf > 0)
+            hipLaunchKernelGGL((k_mv2<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_of(N)), 0, st, fl, (int)nf, x,
+                               xs, (const R*)w, pk, rho, (const R*)FB, (const R*)FBh, out, dual, geom<R>(m), T, sk);
+        if (bs > 0)
+            hipLaunchKernelGGL((k_pass2<N, R, true>), dim3((unsigned)bs), dim3(threads_of(N)), 0, st, m.crs_list, ns,
+                               (const R*)nullptr, x, xs, (const R*)w, pk, rho, (const R*)FB, (const R*)FBh, out,
+                               (R)-1.0, dual, geom<R>(m), T, sk, (const R*)nullptr, 0, (int64_t)0,
+                               (double*)nullptr);
+    }
+}
+
+template <typename R>
+static void mv_dispatch(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
+                        const R* pk, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st) {
+#define MV(NN)                                                                                            \
+    do {                                                                                                  \
+        if (!m.deformed) {                                                                                \
+            if (sk.scheme == 2) mv_n<R, NN, true, 2>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st);  \
+            else mv_n<R, NN, true, 1>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st);                 \
+        } else {                                                                                          \
+            if (sk.scheme == 2) mv_n<R, NN, false, 2>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st); \
+            else mv_n<R, NN, false, 1>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st);                \
+        }                                                                                                 \
+    } while (0)
+    IMX_DISPATCH_N(m.n, MV)
+#undef MV
+}
+
+template <typename R>
+void launch_mv1(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
+                const R* pk, R* w, R* FB, R* FBh, hipStream_t st) {
+    mv_dispatch<R>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, nullptr, 0, st);
+}
+template <typename R>
+void launch_mv2(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* w, const R* pk,
+                const R* rho, const R* FB, const R* FBh, R* out, int dual, hipStream_t st) {
+    mv_dispatch<R>(m, sk, x, xs, (const R*)nullptr, rho, pk, (R*)w, (R*)FB, (R*)FBh, out, dual, st);
+}
+template void launch_mv1<double>(const DevMesh&, const StageK&, const double*, const double*, const double*,
+                                 const double*, const double*, double*, double*, double*, hipStream_t);
+template void launch_mv1<float>(const DevMesh&, const StageK&, const float*, const float*, const float*,
+                                const float*, const float*, float*, float*, float*, hipStream_t);
+template void launch_mv2<double>(const DevMesh&, const StageK&, const double*, const double*, const double*,
+                                 const double*, const double*, const double*, const double*, double*, int,
+                                 hipStream_t);
+template void launch_mv2<float>(const DevMesh&, const StageK&, const float*, const float*, const float*,
+                                const float*, const float*, const float*, const float*, float*, int, hipStream_t);
 
 size_t pass2_partial_count(const DevMesh& m) {
     const int e = m.n == 2 ? 16 : (m.n == 3 ? 9 : (m.n == 4 ? 4 : 2));

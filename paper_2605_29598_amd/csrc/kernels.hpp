@@ -27,6 +27,9 @@ struct DevMesh {
     const float* WJf = nullptr;
     const float* Gf = nullptr;
     const float* nSf = nullptr;
+    const double* eg = nullptr;     // [E*8] affine elements: h[3], 1/h[3], det J, 1/det J
+    const double* iWJ = nullptr;    // [E*Np] 1 / WJ (deformed meshes)
+    const float* iWJf = nullptr;
     int64_t ncoarse = 0;            // elements owning a coarse hanging face
     const int* reg_list = nullptr;  // [E - ncoarse] the other elements
     const int* crs_list = nullptr;  // [ncoarse]
@@ -44,6 +47,9 @@ struct StageK {
     double c_dt;    // a_ll * dt
     double beta;    // a_ll * dt * f
     double gamma, g;
+    double hfac;    // gamma / (gamma - 1): (rho h) = hfac p
+    double igm1;    // 1 / (gamma - 1)
+    double rot_si;  // 1 / (1 + beta^2), the scale of (I + beta J)^{-1} on the horizontal block
     int scheme;     // 1: R1, 2: R2
 };
 
@@ -78,6 +84,18 @@ void launch_pass2(const DevMesh& m, const HostTab& t, const StageK& sk, const R*
                   R* out, double alpha, int dual, hipStream_t st, const R* V = nullptr, int nv = 0,
                   double* partial = nullptr, double* dots = nullptr);
 size_t pass2_partial_count(const DevMesh& m);
+
+// Schur complement inside the Krylov loop (no right-hand side):
+// launch_mv1: w and face buffers of x scaled by *xs (xs may be null), cr = 1 / (WJ rho_l);
+// launch_mv2: out = M^{-1} S (xs x) (dual = 0) or S (xs x) (dual = 1), after launch_mv1.
+template <typename R>
+void launch_mv1(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
+                const R* pk, R* w, R* FB, R* FBh, hipStream_t st);
+template <typename R>
+void launch_mv2(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* w, const R* pk,
+                const R* rho, const R* FB, const R* FBh, R* out, int dual, hipStream_t st);
+// cr = 1 / (WJ rho), and its binary32 copy when crf != null
+void launch_stage_coef(int64_t L, const double* rho, const double* WJ, double* cr, float* crf, hipStream_t st);
 void launch_final_sum(const double* partial, int nb, int nv, double* out, hipStream_t st);
 
 // Gp = G0h - M^{-1}Lambda^k - rho kappa^k [R1: - c g rho uk_z]

@@ -79,6 +79,8 @@ struct imx_solver {
     // binary32 shadows for the mixed inner loop
     float *Vf = nullptr, *zf = nullptr, *z1f = nullptr, *wf = nullptr, *FBf = nullptr, *FBhf = nullptr;
     float *rhof = nullptr, *pkf = nullptr, *WJf = nullptr, *Gf = nullptr, *nSf = nullptr, *xf = nullptr;
+    double* cr = nullptr;    // 1 / (WJ rho_l) of the current stage
+    float* crf = nullptr;
     float* svf = nullptr;   // binary32 copies of the Krylov scales
     // pinned host scalars
     double* hsc = nullptr;
@@ -136,10 +138,13 @@ static size_t layout(imx_solver* s, char* base) {
     dm.tab = D(tab_bytes(m.n, 0) / 8 + 1);
     dm.tabf = D(tab_bytes(m.n, 1) / 8 + 1);
     dm.WJ = D(s->Lp);
+    dm.eg = D(E * 8);
     if (m.deformed) {
         dm.G = D(9 * L);
         dm.nS = D((size_t)E * 6 * 3 * Nf);
+        dm.iWJ = D(L);
     }
+    s->cr = D(L);
     if (s->phys.sponge_lambda != 0.0) dm.sponge = D(L);
     s->y = D(5 * L);
     s->ybak = D(5 * L);
@@ -178,12 +183,14 @@ static size_t layout(imx_solver* s, char* base) {
         s->xf = F(s->Lp);
         s->WJf = F(s->Lp);
         s->svf = F(64);
+        s->crf = F(L);
         dm.WJf = s->WJf;
         if (m.deformed) {
             s->Gf = F(9 * L);
             s->nSf = F((size_t)E * 6 * 3 * Nf);
             dm.Gf = s->Gf;
             dm.nSf = s->nSf;
+            dm.iWJf = F(L);
         }
     }
     return Lo.off;
@@ -209,6 +216,9 @@ static StageK stage_k(const imx_solver* s, double a_ll) {
     k.beta = a_ll * s->num.dt * s->phys.f;
     k.gamma = s->phys.gamma;
     k.g = s->phys.g;
+    k.hfac = s->phys.gamma / (s->phys.gamma - 1.0);
+    k.igm1 = 1.0 / (s->phys.gamma - 1.0);
+    k.rot_si = 1.0 / (1.0 + k.beta * k.beta);
     k.scheme = s->num.scheme;
     return k;
 }
@@ -291,7 +301,7 @@ struct StageCtx {
 
 // r = M^{-1}(RHS - S x) with x scaled by *xs (device) if xs != null
 static void residual(imx_solver* s, const StageCtx& c, const double* x, const double* xs, double* out) {
-    const double n1 = (x ? 1 : 0) + 3 + 1 + 1 + 3 + (c.k.scheme == 1 ? 3 : 0);   // x, Fh, rho, pk, w (, uk)
+    const double n1 = (x ? 1 : 0) + 3 + 1 + 3 + (c.k.scheme == 1 ? 3 : 0);   // x, Fh, rho, w (, uk)
     timed(s, IMX_K_PASS1, field_bytes(s, n1, true), [&] {
         launch_pass1<double>(s->dm, s->tab, c.k, x, xs, c.Fh, c.rho, c.pk, c.uk, s->w, s->FB, s->FBh, s->st);
     });
@@ -301,15 +311,15 @@ static void residual(imx_solver* s, const StageCtx& c, const double* x, const do
     });
 }
 
-// z = M^{-1} S (xs * x); with V != null also dots[i] = <V_i, z>_M (i < nv), dots[nv] = <z, z>_M
-static void matvec(imx_solver* s, const StageCtx& c, const double* x, const double* xs, double* out,
-                   const double* V = nullptr, int nv = 0, double* dots = nullptr) {
-    timed(s, IMX_K_PASS1, field_bytes(s, 6, true), [&] {   // x, rho, pk, w
-        launch_pass1<double>(s->dm, s->tab, c.k, x, xs, nullptr, c.rho, c.pk, c.uk, s->w, s->FB, s->FBh, s->st);
+// z = M^{-1} S (xs * x)
+static void matvec(imx_solver* s, const StageCtx& c, const double* x, const double* xs, double* out) {
+    // algorithmic fields of pass 1: x, rho, w (the lagged pressure read for the
+    // face buffers is an implementation cost, not counted)
+    timed(s, IMX_K_PASS1, field_bytes(s, 5, true), [&] {
+        launch_mv1<double>(s->dm, c.k, x, xs, s->cr, c.rho, c.pk, s->w, s->FB, s->FBh, s->st);
     });
-    timed(s, IMX_K_PASS2, field_bytes(s, 6 + (c.k.scheme == 2 ? 1 : 0) + nv, true), [&] {   // x, w, pk, (rho), out, V
-        launch_pass2<double>(s->dm, s->tab, c.k, nullptr, x, xs, s->w, c.pk, c.rho, s->FB, s->FBh, out, -1.0, 0,
-                             s->st, V, nv, s->partial2, dots);
+    timed(s, IMX_K_PASS2, field_bytes(s, 6 + (c.k.scheme == 2 ? 1 : 0), true), [&] {   // x, w, pk, (rho), out
+        launch_mv2<double>(s->dm, c.k, x, xs, s->w, c.pk, c.rho, s->FB, s->FBh, out, 0, s->st);
     });
 }
 
@@ -458,13 +468,13 @@ static imx_status inner_cycle_f32(imx_solver* s, const StageK& k, double beta, d
     const double vb = (double)L * 4.0;
     for (int j = 0; j < m; ++j) {
         float* Vn = V + (size_t)(j + 1) * L;
-        timed(s, IMX_K_PASS1, field_bytes(s, 6, true) / 2, [&] {
-            launch_pass1<float>(s->dm, s->tab, k, V + (size_t)j * L, s->svf + j, nullptr, s->rhof, s->pkf, nullptr,
-                                s->wf, s->FBf, s->FBhf, s->st);
+        timed(s, IMX_K_PASS1, field_bytes(s, 5, true) / 2, [&] {
+            launch_mv1<float>(s->dm, k, V + (size_t)j * L, s->svf + j, s->crf, s->rhof, s->pkf, s->wf, s->FBf,
+                              s->FBhf, s->st);
         });
         timed(s, IMX_K_PASS2, field_bytes(s, 6 + (k.scheme == 2 ? 1 : 0), true) / 2, [&] {
-            launch_pass2<float>(s->dm, s->tab, k, nullptr, V + (size_t)j * L, s->svf + j, s->wf, s->pkf, s->rhof,
-                                s->FBf, s->FBhf, Vn, -1.0, 0, s->st);
+            launch_mv2<float>(s->dm, k, V + (size_t)j * L, s->svf + j, s->wf, s->pkf, s->rhof, s->FBf, s->FBhf, Vn,
+                              0, s->st);
         });
         timed(s, IMX_K_DOTS, (j + 3) * vb,
               [&] { launch_dots<float>(L, j + 2, V, L, Vn, s->WJf, s->partial, raw1, s->st); });
@@ -576,6 +586,8 @@ static imx_status stage_solve(imx_solver* s, double a_ll, const double* rho, con
     const bool fixed = s->num.fixed_iterations != 0;
     StageK k = stage_k(s, a_ll);
     imx_solve_stats stats{};
+    timed(s, IMX_K_STAGE, (double)L * (s->mixed ? 28.0 : 24.0),
+          [&] { launch_stage_coef(L, rho, s->dm.WJ, s->cr, s->mixed ? s->crf : nullptr, s->st); });
     bool converged = false;
     double* bb = s->dsc + imx_solver::S_MISC;
     for (int it = 0; it < s->num.picard_max; ++it) {
@@ -751,6 +763,11 @@ imx_status imx_solver_create(const imx_mesh* mesh, const imx_phys* phys, const i
     s->Nf = mesh->m.Nf;
     s->L = s->E * s->Np;
     s->Lp = (s->L + 3) & ~int64_t(3);
+    if (9 * s->L >= (int64_t(1) << 31) || s->E * 6 * s->Nf >= (int64_t(1) << 31)) {
+        delete s;
+        set_error("imx_solver_create: mesh too large (9 E Np and 6 E Nf must stay below 2^31)");
+        return IMX_EINVAL;
+    }
     s->m = num->gmres_restart;
     s->mixed = num->precision == IMX_MIXED;
     s->dm.E = s->E;
@@ -792,8 +809,10 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
     // zero first: the padding of the Krylov-stride vectors (and WJ) stays zero
     HIPCHK(hipMemsetAsync(s->ws, 0, s->ws_bytes, s->st));
     const Mesh& m = *s->mesh;
+    // host staging vectors are reused and go out of scope: each upload completes before the next
     auto up = [&](const void* dst, const void* src, size_t n) -> imx_status {
         HIPCHK(hipMemcpyAsync((void*)dst, src, n, hipMemcpyHostToDevice, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
         return IMX_OK;
     };
     CHK(up(s->dm.kind, m.fkind.data(), m.fkind.size() * sizeof(int)));
@@ -814,15 +833,32 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
     std::vector<double> hinv(m.h.size());
     for (size_t i = 0; i < hinv.size(); ++i) hinv[i] = 1.0 / m.h[i];
     CHK(up(s->dm.hinv, hinv.data(), hinv.size() * sizeof(double)));
+    // per element: h[3], 1/h[3], det J = h0 (h1 h2) (the host geometry's product), 1 / det J
+    std::vector<double> eg((size_t)s->E * 8);
+    for (int64_t e = 0; e < s->E; ++e) {
+        const double* h = &m.h[3 * e];
+        double* q = &eg[8 * e];
+        for (int c = 0; c < 3; ++c) {
+            q[c] = h[c];
+            q[3 + c] = hinv[3 * e + c];
+        }
+        q[6] = h[0] * (h[1] * h[2]);
+        q[7] = 1.0 / q[6];
+    }
+    CHK(up(s->dm.eg, eg.data(), eg.size() * sizeof(double)));
     std::vector<char> tabimg(tab_bytes(m.n, 0)), tabimgf(tab_bytes(m.n, 1));
     fill_tab(s->tab, 0, tabimg.data());
     fill_tab(s->tab, 1, tabimgf.data());
     CHK(up(s->dm.tab, tabimg.data(), tabimg.size()));
     CHK(up(s->dm.tabf, tabimgf.data(), tabimgf.size()));
     CHK(up(s->dm.WJ, m.WJ.data(), m.WJ.size() * sizeof(double)));
+    std::vector<double> iwj;
     if (m.deformed) {
         CHK(up(s->dm.G, m.G.data(), m.G.size() * sizeof(double)));
         CHK(up(s->dm.nS, m.nS.data(), m.nS.size() * sizeof(double)));
+        iwj.resize(s->L);
+        for (int64_t i = 0; i < s->L; ++i) iwj[i] = 1.0 / m.WJ[i];
+        CHK(up(s->dm.iWJ, iwj.data(), iwj.size() * sizeof(double)));
     }
     std::vector<double> spl;
     if (s->dm.sponge) {
@@ -849,6 +885,8 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
             CHK(up(s->Gf, tmp.data(), tmp.size() * sizeof(float)));
             tmp.assign(m.nS.begin(), m.nS.end());
             CHK(up(s->nSf, tmp.data(), tmp.size() * sizeof(float)));
+            std::vector<float> iwf(iwj.begin(), iwj.end());
+            CHK(up(s->dm.iWJf, iwf.data(), iwf.size() * sizeof(float)));
         }
     }
     HIPCHK(hipMemsetAsync(s->dsc, 0, imx_solver::S_N * sizeof(double), s->st));
@@ -904,6 +942,7 @@ imx_status imx_implicit_setup(imx_solver* s, const double* rho_l, const double* 
     if (!rho_l || !p_lag || !u_lag) return IMX_EINVAL;
     const size_t L = s->L * sizeof(double);
     HIPCHK(hipMemcpyAsync(s->rho, rho_l, L, hipMemcpyDeviceToDevice, s->st));
+    launch_stage_coef(s->L, s->rho, s->dm.WJ, s->cr, s->mixed ? s->crf : nullptr, s->st);
     HIPCHK(hipMemcpyAsync(s->p, p_lag, L, hipMemcpyDeviceToDevice, s->st));
     HIPCHK(hipMemcpyAsync(s->u, u_lag, 3 * L, hipMemcpyDeviceToDevice, s->st));
     return IMX_OK;
@@ -914,13 +953,11 @@ imx_status imx_schur_apply(imx_solver* s, const double* pin, double* out) {
     if (!pin || !out) return IMX_EINVAL;
     const double a_ll = TAB.at[1][1];
     StageK k = stage_k(s, a_ll);
-    timed(s, IMX_K_PASS1, field_bytes(s, 6, true), [&] {
-        launch_pass1<double>(s->dm, s->tab, k, pin, nullptr, nullptr, s->rho, s->p, s->u, s->w, s->FB, s->FBh,
-                             s->st);
+    timed(s, IMX_K_PASS1, field_bytes(s, 5, true), [&] {
+        launch_mv1<double>(s->dm, k, pin, nullptr, s->cr, s->rho, s->p, s->w, s->FB, s->FBh, s->st);
     });
     timed(s, IMX_K_PASS2, field_bytes(s, 6 + (k.scheme == 2 ? 1 : 0), true), [&] {
-        launch_pass2<double>(s->dm, s->tab, k, nullptr, pin, nullptr, s->w, s->p, s->rho, s->FB, s->FBh, out, -1.0,
-                             1, s->st);
+        launch_mv2<double>(s->dm, k, pin, nullptr, s->w, s->p, s->rho, s->FB, s->FBh, out, 1, s->st);
     });
     HIPCHK(hipGetLastError());
     return IMX_OK;

@@ -463,6 +463,18 @@ void launch_scale_div(int64_t L, int nf, const double* in, const double* WJ, dou
     hipLaunchKernelGGL(k_scale_div, dim3(grid_for(L)), dim3(TPB), 0, st, L, nf, in, WJ, out);
 }
 
+__global__ void k_stage_coef(int64_t L, const double* __restrict__ rho, const double* __restrict__ WJ,
+                             double* __restrict__ cr, float* __restrict__ crf) {
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) {
+        const double c = 1.0 / (WJ[x] * rho[x]);
+        cr[x] = c;
+        if (crf) crf[x] = (float)c;
+    }
+}
+void launch_stage_coef(int64_t L, const double* rho, const double* WJ, double* cr, float* crf, hipStream_t st) {
+    hipLaunchKernelGGL(k_stage_coef, dim3(grid_for(L)), dim3(TPB), 0, st, L, rho, WJ, cr, crf);
+}
+
 __global__ void k_d2f(int64_t L, const double* __restrict__ in, float* __restrict__ out) {
     for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) out[x] = (float)in[x];
 }
