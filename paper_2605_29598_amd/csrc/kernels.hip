@@ -499,7 +499,9 @@ template <int N, typename R, bool SLOW>
 __global__ void __launch_bounds__(threads_of(N))
 k_pass1(const int* __restrict__ elist, int64_t nel, const R* __restrict__ p, const R* __restrict__ pscale, const R* __restrict__ Fh,
         const R* __restrict__ rho, const R* __restrict__ pk, const R* __restrict__ uk, R* __restrict__ w,
-        R* __restrict__ FB, R* __restrict__ FBh, Geom<R> g, const Tab<N, R>* __restrict__ Tg, StageK sk) {
+        R* __restrict__ FB, R* __restrict__ FBh, Geom<R> g, const Tab<N, R>* __restrict__ Tg, StageK sk,
+        const int* __restrict__ ctrl) {
+    if (ctrl && *ctrl != 0) return;
     constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
     constexpr int L_FAST = 6 * 3 * NF, L_SLOW = 4 * NF + NF + 3 * NF + 4 * 3 * NF, L_VOL = 3 * NP;
     constexpr int NR = (6 * NF + NP - 1) / NP;   // face points per lane
@@ -765,7 +767,8 @@ k_pass2(const int* __restrict__ elist, int64_t nel, const R* __restrict__ Gp, co
         const R* __restrict__ pscale, const R* __restrict__ w, const R* __restrict__ pk, const R* __restrict__ rho,
         const R* __restrict__ FB, const R* __restrict__ FBh, R* __restrict__ out, R alpha, int dual, Geom<R> g,
         const Tab<N, R>* __restrict__ Tg, StageK sk, const R* __restrict__ V, int nv, int64_t ldv,
-        double* __restrict__ partial) {
+        double* __restrict__ partial, const int* __restrict__ ctrl) {
+    if (ctrl && *ctrl != 0) return;
     constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
     constexpr int L_FACE = SLOW ? 5 * NF : 6 * NF;
     __shared__ R s_face[EPB][L_FACE];
@@ -934,7 +937,8 @@ template <int N, typename R, bool AFF, int SCH>
 __global__ void __launch_bounds__(threads_of(N))
 k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
       const R* __restrict__ cr, const R* __restrict__ pk, R* __restrict__ w, R* __restrict__ FB, Geom<R> g,
-      const Tab<N, R>* __restrict__ Tg, StageK sk) {
+      const Tab<N, R>* __restrict__ Tg, StageK sk, const int* __restrict__ ctrl) {
+    if (ctrl && *ctrl != 0) return;   // the Krylov cycle has stopped
     constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
     constexpr int NR = (6 * NF + NP - 1) / NP;   // face points per lane
     constexpr int LF = AFF ? 6 * NF : 18 * NF, LV = AFF ? NP : 3 * NP;
@@ -1116,7 +1120,8 @@ __global__ void __launch_bounds__(threads_of(N))
 k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
       const R* __restrict__ w, const R* __restrict__ pk, const R* __restrict__ rho, const R* __restrict__ FB,
       const R* __restrict__ FBh, R* __restrict__ out, int dual, Geom<R> g, const Tab<N, R>* __restrict__ Tg,
-      StageK sk) {
+      StageK sk, const int* __restrict__ ctrl) {
+    if (ctrl && *ctrl != 0) return;
     constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
     constexpr int NR = (6 * NF + NP - 1) / NP;
     __shared__ R s_face[EPB][6 * NF];
@@ -1158,7 +1163,8 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
         }
         // contravariant (rho h)^k w for the volume term
         if constexpr (AFF) {
-            const R wj = T.W3[node] * eg.dJ;
+            // the LDS copy of the tables is not visible before the first barrier
+            const R wj = Tg->W3[node] * eg.dJ;
 #pragma unroll
             for (int dd = 0; dd < 3; ++dd) s_vol[le][dd][node] = rh * ((wj * eg.hi(dd)) * wv[dd]);
         } else {
@@ -1382,7 +1388,7 @@ void launch_pass1(const DevMesh& m, const HostTab&, const StageK& sk, const R* p
                   const R* Fh, const R* rho, const R* pk, const R* uk, R* w, R* FB, R* FBh, hipStream_t st) {
 #define CALL(NN)                                                                                         \
     launch_split<NN>(m, k_pass1<NN, R, false>, k_pass1<NN, R, true>, st, p, pscale, Fh, rho, pk, uk, w, FB, \
-                     FBh, geom<R>(m), (const Tab<NN, R>*)tab_ptr<R>(m), sk)
+                     FBh, geom<R>(m), (const Tab<NN, R>*)tab_ptr<R>(m), sk, (const int*)nullptr)
     IMX_DISPATCH_N(m.n, CALL)
 #undef CALL
 }
@@ -1405,11 +1411,11 @@ static void pass2_n(const DevMesh& m, const StageK& sk, const R* Gp, const R* p,
     if (bf > 0)
         hipLaunchKernelGGL((k_pass2<N, R, false>), dim3((unsigned)bf), dim3(threads_of(N)), 0, st,
                            m.ncoarse ? m.reg_list : nullptr, nf, Gp, p, pscale, w, pk, rho, FB, FBh, out, (R)alpha,
-                           dual, geom<R>(m), T, sk, V, nv, L, partial);
+                           dual, geom<R>(m), T, sk, V, nv, L, partial, (const int*)nullptr);
     if (bs > 0)
         hipLaunchKernelGGL((k_pass2<N, R, true>), dim3((unsigned)bs), dim3(threads_of(N)), 0, st, m.crs_list, ns, Gp,
                            p, pscale, w, pk, rho, FB, FBh, out, (R)alpha, dual, geom<R>(m), T, sk, V, nv, L,
-                           partial ? partial + (size_t)bf * (nv + 1) : nullptr);
+                           partial ? partial + (size_t)bf * (nv + 1) : nullptr, (const int*)nullptr);
     if (V) launch_final_sum(partial, (int)(bf + bs), nv + 1, dots, st);
 }
 
@@ -1432,7 +1438,7 @@ template void launch_pass2<float>(const DevMesh&, const HostTab&, const StageK&,
 
 template <typename R, int N, bool AFF, int SCH>
 static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
-                 const R* pk, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st) {
+                 const R* pk, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st, const int* ctrl) {
     constexpr int EPB = epb_of(N);
     const Tab<N, R>* T = (const Tab<N, R>*)tab_ptr<R>(m);
     const int64_t nf = m.ncoarse ? m.E - m.ncoarse : m.E, ns = m.ncoarse;
@@ -1441,33 +1447,35 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
     if (!out) {
         if (bf > 0)
             hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_of(N)), 0, st, fl, (int)nf, x,
-                               xs, cr, pk, w, FB, geom<R>(m), T, sk);
+                               xs, cr, pk, w, FB, geom<R>(m), T, sk, ctrl);
         if (bs > 0)
             hipLaunchKernelGGL((k_pass1<N, R, true>), dim3((unsigned)bs), dim3(threads_of(N)), 0, st, m.crs_list, ns,
-                               x, xs, (const R*)nullptr, rho, pk, (const R*)nullptr, w, FB, FBh, geom<R>(m), T, sk);
+                               x, xs, (const R*)nullptr, rho, pk, (const R*)nullptr, w, FB, FBh, geom<R>(m), T, sk,
+                               ctrl);
     } else {
         if (bf > 0)
             hipLaunchKernelGGL((k_mv2<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_of(N)), 0, st, fl, (int)nf, x,
-                               xs, (const R*)w, pk, rho, (const R*)FB, (const R*)FBh, out, dual, geom<R>(m), T, sk);
+                               xs, (const R*)w, pk, rho, (const R*)FB, (const R*)FBh, out, dual, geom<R>(m), T, sk,
+                               ctrl);
         if (bs > 0)
             hipLaunchKernelGGL((k_pass2<N, R, true>), dim3((unsigned)bs), dim3(threads_of(N)), 0, st, m.crs_list, ns,
                                (const R*)nullptr, x, xs, (const R*)w, pk, rho, (const R*)FB, (const R*)FBh, out,
                                (R)-1.0, dual, geom<R>(m), T, sk, (const R*)nullptr, 0, (int64_t)0,
-                               (double*)nullptr);
+                               (double*)nullptr, ctrl);
     }
 }
 
 template <typename R>
 static void mv_dispatch(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
-                        const R* pk, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st) {
+                        const R* pk, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st, const int* ctrl) {
 #define MV(NN)                                                                                            \
     do {                                                                                                  \
         if (!m.deformed) {                                                                                \
-            if (sk.scheme == 2) mv_n<R, NN, true, 2>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st);  \
-            else mv_n<R, NN, true, 1>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st);                 \
+            if (sk.scheme == 2) mv_n<R, NN, true, 2>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);  \
+            else mv_n<R, NN, true, 1>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);                 \
         } else {                                                                                          \
-            if (sk.scheme == 2) mv_n<R, NN, false, 2>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st); \
-            else mv_n<R, NN, false, 1>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st);                \
+            if (sk.scheme == 2) mv_n<R, NN, false, 2>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl); \
+            else mv_n<R, NN, false, 1>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);                \
         }                                                                                                 \
     } while (0)
     IMX_DISPATCH_N(m.n, MV)
@@ -1476,23 +1484,24 @@ static void mv_dispatch(const DevMesh& m, const StageK& sk, const R* x, const R*
 
 template <typename R>
 void launch_mv1(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
-                const R* pk, R* w, R* FB, R* FBh, hipStream_t st) {
-    mv_dispatch<R>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, nullptr, 0, st);
+                const R* pk, R* w, R* FB, R* FBh, hipStream_t st, const int* ctrl) {
+    mv_dispatch<R>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, nullptr, 0, st, ctrl);
 }
 template <typename R>
 void launch_mv2(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* w, const R* pk,
-                const R* rho, const R* FB, const R* FBh, R* out, int dual, hipStream_t st) {
-    mv_dispatch<R>(m, sk, x, xs, (const R*)nullptr, rho, pk, (R*)w, (R*)FB, (R*)FBh, out, dual, st);
+                const R* rho, const R* FB, const R* FBh, R* out, int dual, hipStream_t st, const int* ctrl) {
+    mv_dispatch<R>(m, sk, x, xs, (const R*)nullptr, rho, pk, (R*)w, (R*)FB, (R*)FBh, out, dual, st, ctrl);
 }
 template void launch_mv1<double>(const DevMesh&, const StageK&, const double*, const double*, const double*,
-                                 const double*, const double*, double*, double*, double*, hipStream_t);
+                                 const double*, const double*, double*, double*, double*, hipStream_t, const int*);
 template void launch_mv1<float>(const DevMesh&, const StageK&, const float*, const float*, const float*,
-                                const float*, const float*, float*, float*, float*, hipStream_t);
+                                const float*, const float*, float*, float*, float*, hipStream_t, const int*);
 template void launch_mv2<double>(const DevMesh&, const StageK&, const double*, const double*, const double*,
                                  const double*, const double*, const double*, const double*, double*, int,
-                                 hipStream_t);
+                                 hipStream_t, const int*);
 template void launch_mv2<float>(const DevMesh&, const StageK&, const float*, const float*, const float*,
-                                const float*, const float*, const float*, const float*, float*, int, hipStream_t);
+                                const float*, const float*, const float*, const float*, float*, int, hipStream_t,
+                                const int*);
 
 size_t pass2_partial_count(const DevMesh& m) {
     const int e = m.n == 2 ? 16 : (m.n == 3 ? 9 : (m.n == 4 ? 4 : 2));

@@ -88,12 +88,15 @@ size_t pass2_partial_count(const DevMesh& m);
 // Schur complement inside the Krylov loop (no right-hand side):
 // launch_mv1: w and face buffers of x scaled by *xs (xs may be null), cr = 1 / (WJ rho_l);
 // launch_mv2: out = M^{-1} S (xs x) (dual = 0) or S (xs x) (dual = 1), after launch_mv1.
+// With ctrl != null every workgroup returns at once while *ctrl != 0 (a
+// Krylov cycle that has stopped on the device).
 template <typename R>
 void launch_mv1(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
-                const R* pk, R* w, R* FB, R* FBh, hipStream_t st);
+                const R* pk, R* w, R* FB, R* FBh, hipStream_t st, const int* ctrl = nullptr);
 template <typename R>
 void launch_mv2(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* w, const R* pk,
-                const R* rho, const R* FB, const R* FBh, R* out, int dual, hipStream_t st);
+                const R* rho, const R* FB, const R* FBh, R* out, int dual, hipStream_t st,
+                const int* ctrl = nullptr);
 // cr = 1 / (WJ rho), and its binary32 copy when crf != null
 void launch_stage_coef(int64_t L, const double* rho, const double* WJ, double* cr, float* crf, hipStream_t st);
 void launch_final_sum(const double* partial, int nb, int nv, double* out, hipStream_t st);
@@ -125,13 +128,32 @@ constexpr int MAXV = 33;   // restart length <= 32
 // out[i] = sum WJ * V_i * z  (i < nv), V_i = V + i*ldv, all length L (R = double or float)
 template <typename R>
 void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R* WJ, double* partial,
-                 double* out, hipStream_t st);
+                 double* out, hipStream_t st, const int* ctrl = nullptr);
 // z1 = z - sum_i c_i V_i with c_i = raw[i]*s[i]^2 ; then out[i] = sum WJ V_i z1 (if dots) or
 // out[0] = sum WJ z1^2 (norm)
 template <typename R>
 void launch_axpy_reduce(int64_t L, int nv, const R* V, int64_t ldv, const double* raw, const double* s,
                         const R* z, R* z1, const R* WJ, int mode_norm, double* partial, double* out,
-                        hipStream_t st);
+                        hipStream_t st, const int* ctrl = nullptr);
+
+// State of one restarted-GMRES cycle kept on the device (restart length <= GM).
+constexpr int GM = 32;
+struct GState {
+    double H[(GM + 1) * GM];   // Hessenberg matrix, row i column j at H[i * GM + j], rotated in place
+    double g[GM + 1];          // rotated right-hand side |r0| e_1
+    double cs[GM], sn[GM];     // Givens rotations
+    double sv[GM + 1];         // basis scales: V_i / |V_i| = sv_i V_i
+    double tolb;               // stop when |g_{j+1}| <= tolb (unless fixed)
+    int status;                // 0 running, 1 stopped, 2 second Gram-Schmidt pass needed, 3 non-finite
+    int k;                     // columns completed in this cycle
+    int its;                   // matrix-vector products of the whole solve
+    int maxit, fixed;
+    float svf[GM + 1];         // binary32 copies of sv
+};
+// Column j: raw = first-pass projections <V_i, z> (i <= j) and raw[j+1] = |z|^2,
+// nrm = |z1|^2 after the update. raw2 == null: first pass (may set status 2);
+// raw2 != null: finishes a column after the host's second pass.
+void launch_givens(GState* G, int j, const double* raw, const double* raw2, const double* nrm, hipStream_t st);
 // x += sum_i coef[i] V_i
 template <typename R>
 void launch_lincomb(int64_t L, int nv, const R* V, int64_t ldv, const double* coef, R* x, hipStream_t st);

@@ -81,6 +81,8 @@ struct imx_solver {
     float *rhof = nullptr, *pkf = nullptr, *WJf = nullptr, *Gf = nullptr, *nSf = nullptr, *xf = nullptr;
     double* cr = nullptr;    // 1 / (WJ rho_l) of the current stage
     float* crf = nullptr;
+    GState* gst = nullptr;   // device state of the running Krylov cycle
+    GState* hgs = nullptr;   // pinned host copies: [0] upload, [1] download
     float* svf = nullptr;   // binary32 copies of the Krylov scales
     // pinned host scalars
     double* hsc = nullptr;
@@ -171,6 +173,10 @@ static size_t layout(imx_solver* s, char* base) {
     s->partial = D((size_t)RED_BLOCKS * MAXV + (size_t)RED_BLOCKS * 34);
     s->partial2 = D(pass2_partial_count(s->dm));
     s->dsc = D(imx_solver::S_N);
+    {
+        size_t o = Lo.take(sizeof(GState));
+        s->gst = base ? (GState*)(base + o) : nullptr;
+    }
     if (s->mixed) {
         s->Vf = F((size_t)(s->m + 1) * s->Lp);
         s->zf = F(L);
@@ -258,7 +264,8 @@ static hipEvent_t timing_event(imx_solver* s) {
         if (s->trec.size() > 4096) timing_flush(s);
         if (s->tpool.empty()) {
             hipEvent_t e;
-            (void)hipEventCreate(&e);
+            // no system-scope fences: these events only time kernels on the device
+            (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
             return e;
         }
     }
@@ -311,124 +318,133 @@ static void residual(imx_solver* s, const StageCtx& c, const double* x, const do
     });
 }
 
-// z = M^{-1} S (xs * x)
-static void matvec(imx_solver* s, const StageCtx& c, const double* x, const double* xs, double* out) {
-    // algorithmic fields of pass 1: x, rho, w (the lagged pressure read for the
-    // face buffers is an implementation cost, not counted)
-    timed(s, IMX_K_PASS1, field_bytes(s, 5, true), [&] {
-        launch_mv1<double>(s->dm, c.k, x, xs, s->cr, c.rho, c.pk, s->w, s->FB, s->FBh, s->st);
-    });
-    timed(s, IMX_K_PASS2, field_bytes(s, 6 + (c.k.scheme == 2 ? 1 : 0), true), [&] {   // x, w, pk, (rho), out
-        launch_mv2<double>(s->dm, c.k, x, xs, s->w, c.pk, c.rho, s->FB, s->FBh, out, 0, s->st);
-    });
-}
-
 struct GmresOut {
     int its = 0;
     double relres = 0.0;
 };
 
-// Restarted GMRES(m) for A x = b, A = M^{-1} S, in the M inner product, with
-// classical Gram-Schmidt (a second pass on severe cancellation) and Givens
-// rotations on the host (Saad, Alg. 6.9). x: initial guess in, solution out. Stops when the
-// Givens residual estimate reaches tol*|b| (unless `fixed`), after maxit
-// products, or on breakdown; the final residual is recomputed.
-static imx_status gmres(imx_solver* s, const StageCtx& c, double* x, double bnorm, double tol, int maxit,
-                        bool fixed, GmresOut& out) {
-    const int64_t L = s->Lp;   // Krylov vector stride (element kernels touch the first E*Np)
-    const int m = s->m;
-    double* V = s->V;
+// One cycle of GMRES(m) on the device (Saad, Alg. 6.9) from V_0 = r0 (unscaled,
+// |r0|_M = beta): for each column the matrix-vector product, one classical
+// Gram-Schmidt pass (projections and |z|^2 in one read of the basis, then the
+// update and |z1|^2), and the Givens step in a one-thread kernel. The host
+// queues the columns in chunks and reads the cycle state once per chunk;
+// kernels of a cycle that has stopped return at once. A column with severe
+// cancellation (|z1|^2 < 1e-6 |z|^2) stops the chunk and gets a second pass
+// from the host. `mv(j, x, xs_d, xs_f, out, ctrl)` queues out = A (xs x).
+template <typename R, typename MV>
+static imx_status arnoldi_cycle(imx_solver* s, R* V, const R* WJ, int m, double beta, double tolb, int its0,
+                                int maxit, bool fixed, MV&& mv, const GState*& out) {
+    const int64_t L = s->Lp;
+    GState* G = s->gst;
+    GState* up = s->hgs;
+    GState* dn = s->hgs + 1;
     double* raw1 = s->dsc + imx_solver::S_RAW1;
     double* raw2 = s->dsc + imx_solver::S_RAW2;
     double* nrm = s->dsc + imx_solver::S_NRM;
-    double* sv = s->dsc + imx_solver::S_SV;
+    std::memset(up, 0, sizeof(GState));
+    up->g[0] = beta;
+    up->sv[0] = 1.0 / beta;
+    up->svf[0] = (float)up->sv[0];
+    up->tolb = tolb;
+    up->its = its0;
+    up->maxit = maxit;
+    up->fixed = fixed ? 1 : 0;
+    HIPCHK(hipMemcpyAsync(G, up, sizeof(GState), hipMemcpyHostToDevice, s->st));
+    const int* ctrl = &G->status;
+    const double vb = (double)L * sizeof(R);
+    auto column = [&](int j, const double* raw2p, const int* c) {
+        R* Vn = V + (size_t)(j + 1) * L;
+        double* raw = raw2p ? raw2 : raw1;
+        const int nd = raw2p ? j + 1 : j + 2;   // the second pass needs no |z|^2
+        timed(s, IMX_K_DOTS, (nd + 1) * vb, [&] { launch_dots<R>(L, nd, V, L, Vn, WJ, s->partial, raw, s->st, c); });
+        timed(s, IMX_K_ORTHO, (j + 4) * vb, [&] {
+            launch_axpy_reduce<R>(L, j + 1, V, L, raw, G->sv, Vn, Vn, WJ, 1, s->partial, nrm, s->st, c);
+        });
+        launch_givens(G, j, raw1, raw2p, nrm, s->st);
+    };
+    constexpr int CHUNK = 8;
+    int j = 0;
+    while (j < m) {
+        const int jend = std::min(m, j + CHUNK);
+        for (int jj = j; jj < jend; ++jj) {
+            mv(jj, V + (size_t)jj * L, &G->sv[jj], &G->svf[jj], V + (size_t)(jj + 1) * L, ctrl);
+            column(jj, nullptr, ctrl);
+        }
+        HIPCHK(hipMemcpyAsync(dn, G, sizeof(GState), hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
+        if (dn->status == 2) {
+            const int jc = dn->k;
+            column(jc, raw2, nullptr);
+            HIPCHK(hipMemcpyAsync(dn, G, sizeof(GState), hipMemcpyDeviceToHost, s->st));
+            HIPCHK(hipStreamSynchronize(s->st));
+            j = jc + 1;
+            if (dn->status != 0) break;
+            continue;
+        }
+        if (dn->status != 0) break;
+        j = jend;
+    }
+    out = dn;
+    if (dn->status == 3) {
+        set_error("GMRES: non-finite Krylov vector");
+        return IMX_ENONFINITE;
+    }
+    return IMX_OK;
+}
+
+// y = H^{-1} g (upper triangular k x k of a finished cycle), coefficients y_i sv_i
+static void cycle_coefficients(const GState& G, int k, double* cf) {
+    double yv[GM];
+    for (int i = k - 1; i >= 0; --i) {
+        double t = G.g[i];
+        for (int l = i + 1; l < k; ++l) t -= G.H[i * GM + l] * yv[l];
+        yv[i] = t / G.H[i * GM + i];
+    }
+    for (int i = 0; i < k; ++i) cf[i] = yv[i] * G.sv[i];
+}
+
+// Restarted GMRES(m) for A x = b, A = M^{-1} S, in the M inner product. x:
+// initial guess in, solution out. Stops when the Givens residual estimate
+// reaches tol*|b| (unless `fixed`), after maxit products, or on breakdown;
+// every restart recomputes the true residual.
+static imx_status gmres(imx_solver* s, const StageCtx& c, double* x, double bnorm, double tol, int maxit,
+                        bool fixed, GmresOut& out) {
+    const int64_t L = s->Lp;   // Krylov vector stride (element kernels touch the first E*Np)
+    double* V = s->V;
     double* coef = s->dsc + imx_solver::S_COEF;
     double* bb = s->dsc + imx_solver::S_MISC;
-    std::vector<double> H((m + 1) * m), g(m + 1), cs(m), sn(m), svh(m + 1), yv(m), cf(m);
     residual(s, c, x, nullptr, V);
     timed(s, IMX_K_REDUCE, 2 * (double)L * 8.0,
           [&] { launch_wdot(L, V, nullptr, s->dm.WJ, s->partial, bb, s->st); });
     CHK(sync_read(s, bb, 1));
     double beta = std::sqrt(s->hsc[0]);
     int its = 0;
+    auto mv = [&](int, const double* xj, const double* xs, const float*, double* o, const int* ctrl) {
+        timed(s, IMX_K_PASS1, field_bytes(s, 5, true), [&] {
+            launch_mv1<double>(s->dm, c.k, xj, xs, s->cr, c.rho, c.pk, s->w, s->FB, s->FBh, s->st, ctrl);
+        });
+        timed(s, IMX_K_PASS2, field_bytes(s, 6 + (c.k.scheme == 2 ? 1 : 0), true), [&] {
+            launch_mv2<double>(s->dm, c.k, xj, xs, s->w, c.pk, c.rho, s->FB, s->FBh, o, 0, s->st, ctrl);
+        });
+    };
     while (true) {
         if (!std::isfinite(beta)) {
             set_error("GMRES: non-finite residual");
             return IMX_ENONFINITE;
         }
         if (beta == 0.0 || its >= maxit || (!fixed && beta <= tol * bnorm)) break;
-        std::fill(H.begin(), H.end(), 0.0);
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        svh[0] = 1.0 / beta;
-        CHK(put_scalars(s, sv, &svh[0], 1, 0));
-        int k = 0;
-        for (int j = 0; j < m; ++j) {
-            // z = A (sv_j V_j), its projections <V_i, z> and norm, then one
-            // classical Gram-Schmidt update that also yields the new norm.
-            // A second pass runs only on severe cancellation (|z1| < 1e-3 |z|).
-            double* Vn = V + (size_t)(j + 1) * L;
-            // z is built in the slot of the next basis vector: its projections on
-            // V_0..V_j and its own norm come out of one multi-dot pass
-            matvec(s, c, V + (size_t)j * L, sv + j, Vn);
-            ++its;
-            const double vb = (double)L * 8.0;
-            timed(s, IMX_K_DOTS, (j + 3) * vb,
-                  [&] { launch_dots<double>(L, j + 2, V, L, Vn, s->dm.WJ, s->partial, raw1, s->st); });
-            timed(s, IMX_K_ORTHO, (j + 4) * vb, [&] {
-                launch_axpy_reduce<double>(L, j + 1, V, L, raw1, sv, Vn, Vn, s->dm.WJ, 1, s->partial, nrm, s->st);
-            });
-            HIPCHK(hipMemcpyAsync(s->hsc, raw1, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s->st));
-            HIPCHK(hipMemcpyAsync(s->hsc + 128, nrm, sizeof(double), hipMemcpyDeviceToHost, s->st));
-            HIPCHK(hipStreamSynchronize(s->st));
-            for (int i = 0; i <= j; ++i) H[i * m + j] = svh[i] * s->hsc[i];
-            if (s->hsc[128] < 1e-6 * s->hsc[j + 1]) {
-                timed(s, IMX_K_DOTS, (j + 3) * vb, [&] {
-                    launch_dots<double>(L, j + 1, V, L, Vn, s->dm.WJ, s->partial, raw2, s->st);
-                });
-                timed(s, IMX_K_ORTHO, (j + 4) * vb, [&] {
-                    launch_axpy_reduce<double>(L, j + 1, V, L, raw2, sv, Vn, Vn, s->dm.WJ, 1, s->partial, nrm, s->st);
-                });
-                HIPCHK(hipMemcpyAsync(s->hsc + 64, raw2, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s->st));
-                HIPCHK(hipMemcpyAsync(s->hsc + 128, nrm, sizeof(double), hipMemcpyDeviceToHost, s->st));
-                HIPCHK(hipStreamSynchronize(s->st));
-                for (int i = 0; i <= j; ++i) H[i * m + j] += svh[i] * s->hsc[64 + i];
-            }
-            const double hnext = std::sqrt(s->hsc[128]);
-            H[(j + 1) * m + j] = hnext;
-            for (int i = 0; i < j; ++i) {
-                const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
-                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
-                H[i * m + j] = t;
-            }
-            const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
-            cs[j] = H[j * m + j] / den;
-            sn[j] = H[(j + 1) * m + j] / den;
-            H[j * m + j] = den;
-            H[(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            k = j + 1;
-            if (!std::isfinite(hnext)) {
-                set_error("GMRES: non-finite Krylov vector");
-                return IMX_ENONFINITE;
-            }
-            if (hnext == 0.0 || its >= maxit || (!fixed && std::fabs(g[j + 1]) <= tol * bnorm)) break;
-            svh[j + 1] = 1.0 / hnext;
-            CHK(put_scalars(s, sv + j + 1, &svh[j + 1], 1, j + 1));
-        }
-        for (int i = k - 1; i >= 0; --i) {
-            double t = g[i];
-            for (int l = i + 1; l < k; ++l) t -= H[i * m + l] * yv[l];
-            yv[i] = t / H[i * m + i];
-        }
-        for (int i = 0; i < k; ++i) cf[i] = yv[i] * svh[i];
-        CHK(put_scalars(s, coef, cf.data(), k, 100));
+        const GState* G = nullptr;
+        CHK(arnoldi_cycle<double>(s, V, s->dm.WJ, s->m, beta, tol * bnorm, its, maxit, fixed, mv, G));
+        const int k = G->k;
+        its = G->its;
+        double cf[GM];
+        cycle_coefficients(*G, k, cf);
+        CHK(put_scalars(s, coef, cf, k, 100));
         timed(s, IMX_K_LINCOMB, (k + 2) * (double)L * 8.0,
               [&] { launch_lincomb<double>(L, k, V, L, coef, x, s->st); });
         residual(s, c, x, nullptr, V);
         timed(s, IMX_K_REDUCE, 2 * (double)L * 8.0,
-          [&] { launch_wdot(L, V, nullptr, s->dm.WJ, s->partial, bb, s->st); });
+              [&] { launch_wdot(L, V, nullptr, s->dm.WJ, s->partial, bb, s->st); });
         CHK(sync_read(s, bb, 1));
         beta = std::sqrt(s->hsc[0]);
     }
@@ -439,12 +455,6 @@ static imx_status gmres(imx_solver* s, const StageCtx& c, double* x, double bnor
 
 // Solves the pressure system of the current stage context for x (initial
 // guess in, solution out) to gmres_tol.
-static imx_status put_scalars_f(imx_solver* s, float* dev, const float* vals, int n, int slot) {
-    float* h = (float*)(s->hsc + 1536) + slot;
-    std::memcpy(h, vals, n * sizeof(float));
-    HIPCHK(hipMemcpyAsync(dev, h, n * sizeof(float), hipMemcpyHostToDevice, s->st));
-    return IMX_OK;
-}
 
 // One binary32 Arnoldi cycle (at most `maxit` steps) of GMRES for the
 // correction equation A d = r / |r|, started from d = 0 with Vf[0] holding
@@ -452,72 +462,23 @@ static imx_status put_scalars_f(imx_solver* s, float* dev, const float* vals, in
 static imx_status inner_cycle_f32(imx_solver* s, const StageK& k, double beta, double tol, int maxit, int& steps) {
     const int64_t L = s->Lp;
     const int m = std::min(s->m, maxit);
-    float* V = s->Vf;
-    double* raw1 = s->dsc + imx_solver::S_RAW1;
-    double* nrm = s->dsc + imx_solver::S_NRM;
-    double* sv = s->dsc + imx_solver::S_SV;
     double* coef = s->dsc + imx_solver::S_COEF;
-    std::vector<double> H((m + 1) * std::max(m, 1)), g(m + 1), cs(m), sn(m), svh(m + 1), yv(m), cf(m);
-    std::vector<float> svf(m + 1);
-    g[0] = beta;
-    svh[0] = 1.0 / beta;
-    svf[0] = (float)svh[0];
-    CHK(put_scalars(s, sv, &svh[0], 1, 0));
-    CHK(put_scalars_f(s, s->svf, &svf[0], 1, 0));
-    int kk = 0;
-    const double vb = (double)L * 4.0;
-    for (int j = 0; j < m; ++j) {
-        float* Vn = V + (size_t)(j + 1) * L;
+    auto mv = [&](int, const float* xj, const double*, const float* xs, float* o, const int* ctrl) {
         timed(s, IMX_K_PASS1, field_bytes(s, 5, true) / 2, [&] {
-            launch_mv1<float>(s->dm, k, V + (size_t)j * L, s->svf + j, s->crf, s->rhof, s->pkf, s->wf, s->FBf,
-                              s->FBhf, s->st);
+            launch_mv1<float>(s->dm, k, xj, xs, s->crf, s->rhof, s->pkf, s->wf, s->FBf, s->FBhf, s->st, ctrl);
         });
         timed(s, IMX_K_PASS2, field_bytes(s, 6 + (k.scheme == 2 ? 1 : 0), true) / 2, [&] {
-            launch_mv2<float>(s->dm, k, V + (size_t)j * L, s->svf + j, s->wf, s->pkf, s->rhof, s->FBf, s->FBhf, Vn,
-                              0, s->st);
+            launch_mv2<float>(s->dm, k, xj, xs, s->wf, s->pkf, s->rhof, s->FBf, s->FBhf, o, 0, s->st, ctrl);
         });
-        timed(s, IMX_K_DOTS, (j + 3) * vb,
-              [&] { launch_dots<float>(L, j + 2, V, L, Vn, s->WJf, s->partial, raw1, s->st); });
-        timed(s, IMX_K_ORTHO, (j + 4) * vb, [&] {
-            launch_axpy_reduce<float>(L, j + 1, V, L, raw1, sv, Vn, Vn, s->WJf, 1, s->partial, nrm, s->st);
-        });
-        HIPCHK(hipMemcpyAsync(s->hsc, raw1, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s->st));
-        HIPCHK(hipMemcpyAsync(s->hsc + 128, nrm, sizeof(double), hipMemcpyDeviceToHost, s->st));
-        HIPCHK(hipStreamSynchronize(s->st));
-        for (int i = 0; i <= j; ++i) H[i * m + j] = svh[i] * s->hsc[i];
-        const double hnext = std::sqrt(s->hsc[128]);
-        H[(j + 1) * m + j] = hnext;
-        for (int i = 0; i < j; ++i) {
-            const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
-            H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
-            H[i * m + j] = t;
-        }
-        const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
-        cs[j] = H[j * m + j] / den;
-        sn[j] = H[(j + 1) * m + j] / den;
-        H[j * m + j] = den;
-        H[(j + 1) * m + j] = 0.0;
-        g[j + 1] = -sn[j] * g[j];
-        g[j] = cs[j] * g[j];
-        kk = j + 1;
-        if (!std::isfinite(hnext)) {
-            set_error("mixed GMRES: non-finite Krylov vector");
-            return IMX_ENONFINITE;
-        }
-        if (hnext == 0.0 || std::fabs(g[j + 1]) <= tol * beta) break;
-        svh[j + 1] = 1.0 / hnext;
-        svf[j + 1] = (float)svh[j + 1];
-        CHK(put_scalars(s, sv + j + 1, &svh[j + 1], 1, j + 1));
-        CHK(put_scalars_f(s, s->svf + j + 1, &svf[j + 1], 1, j + 1));
-    }
-    for (int i = kk - 1; i >= 0; --i) {
-        double t = g[i];
-        for (int l = i + 1; l < kk; ++l) t -= H[i * m + l] * yv[l];
-        yv[i] = t / H[i * m + i];
-    }
-    for (int i = 0; i < kk; ++i) cf[i] = yv[i] * svh[i];
-    CHK(put_scalars(s, coef, cf.data(), kk, 100));
-    timed(s, IMX_K_LINCOMB, (kk + 2) * vb, [&] { launch_lincomb<float>(L, kk, V, L, coef, s->xf, s->st); });
+    };
+    const GState* G = nullptr;
+    CHK(arnoldi_cycle<float>(s, s->Vf, s->WJf, m, beta, tol * beta, 0, m, false, mv, G));
+    const int kk = G->k;
+    double cf[GM];
+    cycle_coefficients(*G, kk, cf);
+    CHK(put_scalars(s, coef, cf, kk, 100));
+    timed(s, IMX_K_LINCOMB, (kk + 2) * (double)L * 4.0,
+          [&] { launch_lincomb<float>(L, kk, s->Vf, L, coef, s->xf, s->st); });
     steps = kk;
     return IMX_OK;
 }
@@ -784,6 +745,12 @@ imx_status imx_solver_create(const imx_mesh* mesh, const imx_phys* phys, const i
         set_error("imx_solver_create: pinned host buffer");
         return IMX_ENOMEM;
     }
+    if (hipHostMalloc((void**)&s->hgs, 2 * sizeof(GState), hipHostMallocDefault) != hipSuccess) {
+        (void)hipHostFree(s->hsc);
+        delete s;
+        set_error("imx_solver_create: pinned host buffer");
+        return IMX_ENOMEM;
+    }
     *out = s;
     return IMX_OK;
 }
@@ -1036,6 +1003,7 @@ void imx_solver_destroy(imx_solver* s) {
     timing_flush(s);
     for (auto e : s->tpool) (void)hipEventDestroy(e);
     if (s->hsc) (void)hipHostFree(s->hsc);
+    if (s->hgs) (void)hipHostFree(s->hgs);
     delete s;
 }
 

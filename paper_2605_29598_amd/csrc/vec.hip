@@ -39,7 +39,9 @@ __device__ __forceinline__ void block_sum(double* v, double* red) {
 }
 
 // final fixed-order sum of partials[nb][nv] -> out[nv], one workgroup per value
-__global__ void k_final_sum(const double* __restrict__ partial, int nb, int nv, double* __restrict__ out) {
+__global__ void k_final_sum(const double* __restrict__ partial, int nb, int nv, double* __restrict__ out,
+                            const int* __restrict__ ctrl) {
+    if (ctrl && *ctrl != 0) return;
     __shared__ double red[TPB];
     const int v = blockIdx.x;
     double s = 0;
@@ -53,8 +55,9 @@ __global__ void k_final_sum(const double* __restrict__ partial, int nb, int nv, 
     if (threadIdx.x == 0) out[v] = red[0];
 }
 
-static void final_sum(const double* partial, int nb, int nv, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_final_sum, dim3(nv), dim3(TPB), 0, st, partial, nb, nv, out);
+static void final_sum(const double* partial, int nb, int nv, double* out, hipStream_t st,
+                      const int* ctrl = nullptr) {
+    hipLaunchKernelGGL(k_final_sum, dim3(nv), dim3(TPB), 0, st, partial, nb, nv, out, ctrl);
 }
 void launch_final_sum(const double* partial, int nb, int nv, double* out, hipStream_t st) {
     final_sum(partial, nb, nv, out, st);
@@ -94,7 +97,8 @@ static unsigned stream_grid(int64_t L) {
 template <typename R, int CH>
 __global__ void __launch_bounds__(TPB)
 k_dots(int64_t L, int nv, int v0, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z,
-       const R* __restrict__ WJ, double* __restrict__ partial, int nvtot) {
+       const R* __restrict__ WJ, double* __restrict__ partial, int nvtot, const int* __restrict__ ctrl) {
+    if (ctrl && *ctrl != 0) return;
     using VT = typename Vec16<R>::T;
     constexpr int W = Vec16<R>::W;
     __shared__ double red[(TPB / 64 + 1) * CH];
@@ -121,26 +125,29 @@ k_dots(int64_t L, int nv, int v0, const R* __restrict__ V, int64_t ldv, const R*
 
 template <typename R>
 void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R* WJ, double* partial,
-                 double* out, hipStream_t st) {
-    // fewer, longer-running workgroups: the block reduction of up to 32 sums
-    // is amortised over more entries per lane
-    const unsigned g = stream_grid(L) > 2048 ? 2048 : stream_grid(L);
+                 double* out, hipStream_t st, const int* ctrl) {
+    // fewer, longer-running workgroups (1024 measured best against 512..4096 on
+    // the 3 M-entry channel basis): the block reduction of up to 16 sums is
+    // amortised over more entries per lane
+    const unsigned g = stream_grid(L) > 1024 ? 1024 : stream_grid(L);
     // at most 16 running sums per lane (keeps 7 waves per SIMD); longer bases
     // take several passes that re-read z and the weights
     const int nch = (nv + 15) / 16, per = (nv + nch - 1) / nch;
     for (int v0 = 0; v0 < nv; v0 += per) {
         const int c = nv - v0 < per ? nv - v0 : per;
         if (c <= 8)
-            hipLaunchKernelGGL((k_dots<R, 8>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv);
+            hipLaunchKernelGGL((k_dots<R, 8>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv,
+                               ctrl);
         else
-            hipLaunchKernelGGL((k_dots<R, 16>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv);
+            hipLaunchKernelGGL((k_dots<R, 16>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv,
+                               ctrl);
     }
-    final_sum(partial, (int)g, nv, out, st);
+    final_sum(partial, (int)g, nv, out, st, ctrl);
 }
 template void launch_dots<double>(int64_t, int, const double*, int64_t, const double*, const double*, double*,
-                                  double*, hipStream_t);
+                                  double*, hipStream_t, const int*);
 template void launch_dots<float>(int64_t, int, const float*, int64_t, const float*, const float*, double*, double*,
-                                 hipStream_t);
+                                 hipStream_t, const int*);
 
 // --------------------------------------------- Gram-Schmidt update (+ reduce)
 // z1 = z - sum_i raw[i] s[i]^2 V_i; then dots of z1 with all V_i (mode 0) or
@@ -203,7 +210,9 @@ k_axpy_red(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const double
 template <typename R, int CH>
 __global__ void __launch_bounds__(TPB)
 k_axpy_norm(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const double* __restrict__ raw,
-            const double* __restrict__ s, const R* z, R* z1, const R* __restrict__ WJ, double* __restrict__ partial) {
+            const double* __restrict__ s, const R* z, R* z1, const R* __restrict__ WJ, double* __restrict__ partial,
+            const int* __restrict__ ctrl) {
+    if (ctrl && *ctrl != 0) return;
     using VT = typename Vec16<R>::T;
     constexpr int W = Vec16<R>::W;
     __shared__ double red[(TPB / 64 + 1)];
@@ -243,19 +252,19 @@ k_axpy_norm(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const doubl
 template <typename R>
 void launch_axpy_reduce(int64_t L, int nv, const R* V, int64_t ldv, const double* raw, const double* s,
                         const R* z, R* z1, const R* WJ, int mode_norm, double* partial, double* out,
-                        hipStream_t st) {
+                        hipStream_t st, const int* ctrl) {
     const unsigned g = stream_grid(L);
     if (mode_norm) {
         if (nv <= 8)
             hipLaunchKernelGGL((k_axpy_norm<R, 8>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
-                               partial);
+                               partial, ctrl);
         else if (nv <= 16)
             hipLaunchKernelGGL((k_axpy_norm<R, 16>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
-                               partial);
+                               partial, ctrl);
         else
             hipLaunchKernelGGL((k_axpy_norm<R, 32>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
-                               partial);
-        final_sum(partial, (int)g, 1, out, st);
+                               partial, ctrl);
+        final_sum(partial, (int)g, 1, out, st, ctrl);
         return;
     }
     if (nv <= 8)
@@ -271,9 +280,64 @@ void launch_axpy_reduce(int64_t L, int nv, const R* V, int64_t ldv, const double
 }
 template void launch_axpy_reduce<double>(int64_t, int, const double*, int64_t, const double*, const double*,
                                          const double*, double*, const double*, int, double*, double*,
-                                         hipStream_t);
+                                         hipStream_t, const int*);
 template void launch_axpy_reduce<float>(int64_t, int, const float*, int64_t, const double*, const double*,
-                                        const float*, float*, const float*, int, double*, double*, hipStream_t);
+                                        const float*, float*, const float*, int, double*, double*, hipStream_t,
+                                        const int*);
+
+// ------------------------------------------------- Arnoldi step on the device
+// Column j of the Hessenberg matrix from the Gram-Schmidt projections, the
+// Givens rotations and the residual estimate (Saad, Alg. 6.9), by one thread:
+// the Krylov loop then needs no host round trip per iteration.
+__global__ void k_givens(GState* __restrict__ G, int j, const double* __restrict__ raw,
+                         const double* __restrict__ raw2, const double* __restrict__ nrm) {
+    if (threadIdx.x != 0) return;
+    if (raw2 == nullptr) {
+        if (G->status != 0) return;
+        // severe cancellation in the single classical Gram-Schmidt pass: the
+        // host runs a second pass and finishes the column
+        if (nrm[0] < 1e-6 * raw[j + 1]) {
+            G->status = 2;
+            return;
+        }
+    } else {
+        if (G->status != 2) return;
+        G->status = 0;
+    }
+    double* H = G->H;
+    for (int i = 0; i <= j; ++i) {
+        double h = G->sv[i] * raw[i];
+        if (raw2) h += G->sv[i] * raw2[i];
+        H[i * GM + j] = h;
+    }
+    const double hnext = sqrt(nrm[0]);
+    H[(j + 1) * GM + j] = hnext;
+    for (int i = 0; i < j; ++i) {
+        const double t = G->cs[i] * H[i * GM + j] + G->sn[i] * H[(i + 1) * GM + j];
+        H[(i + 1) * GM + j] = -G->sn[i] * H[i * GM + j] + G->cs[i] * H[(i + 1) * GM + j];
+        H[i * GM + j] = t;
+    }
+    const double den = hypot(H[j * GM + j], H[(j + 1) * GM + j]);
+    G->cs[j] = H[j * GM + j] / den;
+    G->sn[j] = H[(j + 1) * GM + j] / den;
+    H[j * GM + j] = den;
+    H[(j + 1) * GM + j] = 0.0;
+    G->g[j + 1] = -G->sn[j] * G->g[j];
+    G->g[j] = G->cs[j] * G->g[j];
+    G->k = j + 1;
+    G->its += 1;
+    if (!isfinite(hnext)) {
+        G->status = 3;
+    } else if (hnext == 0.0 || G->its >= G->maxit || (!G->fixed && fabs(G->g[j + 1]) <= G->tolb)) {
+        G->status = 1;
+    } else {
+        G->sv[j + 1] = 1.0 / hnext;
+        G->svf[j + 1] = (float)G->sv[j + 1];
+    }
+}
+void launch_givens(GState* G, int j, const double* raw, const double* raw2, const double* nrm, hipStream_t st) {
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, G, j, raw, raw2, nrm);
+}
 
 // ----------------------------------------------------------- linear combination
 template <typename R>

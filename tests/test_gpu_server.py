@@ -29,11 +29,19 @@ def _members():
     hang = W.MeshSpec(8e3, 8e3, 4e3, 4, 4, 2, 2,
                       ref_boxes=[(2e3, 6e3, 2e3, 6e3, 0, 2e3)])
     terr = W.MeshSpec(8e3, 8e3, 4e3, 3, 3, 2, 3, terrain=W.GAUSS, h0=400, a=2e3, xc=4e3, yc=4e3)
+    # affine members of three degrees next to a terrain-following one, long
+    # enough to overlap on the device: every element kernel then runs on
+    # compute units whose LDS another kernel (other degree, other tables) has
+    # just used
+    box3 = W.MeshSpec(12e3, 12e3, 10e3, 10, 10, 6, 3)
+    box4 = W.MeshSpec(12e3, 12e3, 10e3, 8, 8, 5, 4)
     out = [
         (tiny.mesh, tiny.phys, tiny.num, 4),
         (hang, W.PhysSpec(f=1e-4), W.NumSpec(dt=2.0, scheme=dg.R1), 3),
         (terr, W.PhysSpec(f=1e-4), W.NumSpec(dt=2.0), 3),
         (tiny.mesh, tiny.phys, W.NumSpec(dt=1.0), 5),
+        (box3, W.PhysSpec(f=1e-4), W.NumSpec(dt=2.0), 6),
+        (box4, W.PhysSpec(f=1e-4), W.NumSpec(dt=2.0), 6),
     ]
     return [(spec, ph, nm, W.initial_state(tiny, OMesh(MeshDesc(**vars(spec))).node_coords()), n)
             for spec, ph, nm, n in out]
@@ -61,7 +69,7 @@ def test_mix_equals_alone_bitwise():
     B = _B()
     mem = _members()
     ref = [_alone(*m) for m in mem]
-    sv = B.Server(pool_bytes=2 << 30, max_running=4)
+    sv = B.Server(pool_bytes=4 << 30, max_running=6)
     ids = [sv.submit(*m) for m in mem]
     _drain(sv)
     st = sv.query()
