@@ -74,6 +74,32 @@ __device__ __forceinline__ void load_tab(const Tab<N, R>* __restrict__ src, Tab<
     for (int i = threadIdx.x; i < NW; i += blockDim.x) b[i] = a[i];
 }
 
+size_t fofs_count(int n) {
+    const int NP = n * n * n, NF = n * n, NR = (6 * NF + NP - 1) / NP;
+    return (size_t)NR * NP;
+}
+
+void fill_fofs(int n, uint64_t* out) {
+    const int NP = n * n * n, NF = n * n, NR = (6 * NF + NP - 1) / NP;
+    for (int r = 0; r < NR; ++r)
+        for (int node = 0; node < NP; ++node) {
+            const int it = node + r * NP;
+            uint64_t w = 0;
+            if (it < 6 * NF) {
+                const int f = it / NF, pt = it % NF, d = f >> 1, a = pt % n, b = pt / n;
+                for (int m = 0; m < n; ++m) {
+                    const int nd = d == 0 ? m + n * (a + n * b) : (d == 1 ? a + n * (m + n * b) : a + n * (b + n * m));
+                    w |= (uint64_t)nd << (8 * m);
+                }
+                w |= (uint64_t)f << 40;
+                w |= (uint64_t)pt << 48;
+            } else {
+                w |= (uint64_t)6 << 40;
+            }
+            out[r * NP + node] = w;
+        }
+}
+
 size_t tab_bytes(int n, int f32) {
     switch (n) {
         case 2: return f32 ? sizeof(Tab<2, float>) : sizeof(Tab<2, double>);
@@ -113,17 +139,18 @@ struct Geom {
     const R* nS;
     const double* eg;     // affine elements: h[3], 1/h[3], det J, 1/det J (8 per element)
     const R* iWJ;         // 1 / WJ (deformed meshes)
+    const uint64_t* fofs; // face-point words per (round, lane), see fo_node
 };
 
 template <typename R>
 static Geom<R> geom(const DevMesh& m);
 template <>
 Geom<double> geom<double>(const DevMesh& m) {
-    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJ, m.G, m.nS, m.eg, m.iWJ};
+    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJ, m.G, m.nS, m.eg, m.iWJ, m.fofs};
 }
 template <>
 Geom<float> geom<float>(const DevMesh& m) {
-    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJf, m.Gf, m.nSf, m.eg, m.iWJf};
+    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJf, m.Gf, m.nSf, m.eg, m.iWJf, m.fofs};
 }
 
 constexpr int epb_of(int N) { return N == 2 ? 16 : (N == 3 ? 9 : (N == 4 ? 4 : 2)); }
@@ -136,6 +163,15 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G) {
     const int64_t q = G >> 3, r = G & 7, x = b & 7, i = b >> 3;
     return x * q + (x < r ? x : r) + i;
 }
+
+// Face points of the all-faces kernels: lane `node` of an element handles the
+// points it = node + r NP (r < NR) of the element's 6 (r+1)^2 face points.
+// Per (r, node) a host-built 64-bit word holds the offsets within the element
+// of the N nodes along the face normal through that point (bytes 0..N-1), the
+// face (byte 5; 6 when the lane has no point in round r) and the point (byte 6).
+__device__ __forceinline__ int fo_node(uint64_t w, int m) { return (int)((w >> (8 * m)) & 0xff); }
+__device__ __forceinline__ int fo_face(uint64_t w) { return (int)((w >> 40) & 0xff); }
+__device__ __forceinline__ int fo_point(uint64_t w) { return (int)((w >> 48) & 0xff); }
 
 template <int N>
 __device__ __forceinline__ int node_of(int d, int m, int a, int b) {
@@ -947,6 +983,7 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
     __shared__ R s_w[EPB][3][NP];
     __shared__ R s_u[EPB][LF > LV ? LF : LV];
     __shared__ R s_A[EPB][3];   // affine: face area factor h_t1 h_t2 per direction
+    __shared__ R s_v[AFF ? EPB : 1][NP];   // affine: W detJ sc p for the volume term
     __shared__ Tab<N, R> T;
     load_tab<N, R>(Tg, &T);
     const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
@@ -960,24 +997,29 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
     // table entries and the neighbour values along the normal
     R crv = 0, nbv[NR][N];
     int kf[NR], nf[NR];
+    uint64_t fo[NR];   // this lane's face points: node offsets along the normal, face, point
     ElemGeo<N, R, AFF> eg;
     if (act) {
         s_p[le][node] = p[o];
         s_pk[le][node] = pk[o];
         crv = cr[o];
         eg.load(g.eg, e);
-        if (AFF && node < 3) s_A[le][node] = node == 0 ? eg.A0 : (node == 1 ? eg.A1 : eg.A2);
+        if constexpr (AFF) {
+            if (node < 3) s_A[le][node] = node == 0 ? eg.A0 : (node == 1 ? eg.A1 : eg.A2);
+            // (the LDS copy of the tables is not visible before the first barrier)
+            s_v[le][node] = (Tg->W3[node] * eg.dJ) * (sc * p[o]);
+        }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int it = node + r * NP;
-            const int f = it < 6 * NF ? it / NF : 5;
-            kf[r] = it < 6 * NF ? g.kind[e * 6 + f] : WALL;
-            nf[r] = g.nbr[e * 6 + f];
-            const int pt = it - f * NF, d = f >> 1, a = pt % N, b = pt / N;
+            fo[r] = g.fofs[r * NP + node];
+            const bool full = (r + 1) * NP <= 6 * NF;   // every lane has a point in this round
+            const int f = fo_face(fo[r]);
+            kf[r] = (full || f < 6) ? g.kind[e * 6 + f] : WALL;
+            nf[r] = g.nbr[e * 6 + ((full || f < 6) ? f : 5)];
             const bool ld = kf[r] == CONF;
             const R* src = p + (size_t)(unsigned)(ld ? nf[r] : 0) * NP;
 #pragma unroll
-            for (int m = 0; m < N; ++m) nbv[r][m] = ld ? src[node_of<N>(d, m, a, b)] : (R)0;
+            for (int m = 0; m < N; ++m) nbv[r][m] = ld ? src[fo_node(fo[r], m)] : (R)0;
         }
     }
     __syncthreads();
@@ -985,12 +1027,12 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
     if (act)
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int it = node + r * NP;
-            if (it >= 6 * NF) continue;
-            const int f = it / NF, pt = it - f * NF, d = f >> 1, s = f & 1;
+            const int f = fo_face(fo[r]);
+            if ((r + 1) * NP > 6 * NF && f >= 6) continue;
+            const int pt = fo_point(fo[r]), d = f >> 1, s = f & 1;
             R vals[N];
 #pragma unroll
-            for (int m = 0; m < N; ++m) vals[m] = s_p[le][node_of<N>(d, m, pt % N, pt / N)];
+            for (int m = 0; m < N; ++m) vals[m] = s_p[le][fo_node(fo[r], m)];
             const R pa = sc * trace_chain<N, R>(T.f[s], vals);
             R pb = pa;
             if (kf[r] == CONF) pb = sc * trace_chain<N, R>(T.f[1 - s], nbv[r]);
@@ -1005,6 +1047,20 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
                 for (int c = 0; c < 3; ++c) U[(f * 3 + c) * NF + pt] = avg * g.nS[((size_t)(e * 6 + f) * 3 + c) * NF + pt];
             }
         }
+    // affine volume term (after the face points: their registers are free) -int (sc p) div(phi_c), from s_v
+    R vol[3] = {0, 0, 0};
+    if constexpr (AFF) {
+        if (act) {
+            const int i = node % N, j = (node / N) % N, k = node / (N * N);
+            const R* Uv = &s_v[le][0];
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                vol[0] += T.D[q][i] * Uv[q + N * (j + N * k)];
+                vol[1] += T.D[q][j] * Uv[i + N * (q + N * k)];
+                vol[2] += T.D[q][k] * Uv[i + N * (j + N * q)];
+            }
+        }
+    }
     __syncthreads();
     R acc[3] = {0, 0, 0};
     if (act) {
@@ -1026,26 +1082,16 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
             }
         }
     }
-    __syncthreads();
-    // volume: -int (sc p) div(phi_c)
-    const R pv = act ? sc * s_p[le][node] : (R)0;
     if constexpr (AFF) {
-        if (act) U[node] = (T.W3[node] * eg.dJ) * pv;
-        __syncthreads();
         if (act) {
-            const int i = node % N, j = (node / N) % N, k = node / (N * N);
-            R d0 = 0, d1 = 0, d2 = 0;
-#pragma unroll
-            for (int q = 0; q < N; ++q) {
-                d0 += T.D[q][i] * U[q + N * (j + N * k)];
-                d1 += T.D[q][j] * U[i + N * (q + N * k)];
-                d2 += T.D[q][k] * U[i + N * (j + N * q)];
-            }
-            acc[0] -= d0 * eg.hi0;
-            acc[1] -= d1 * eg.hi1;
-            acc[2] -= d2 * eg.hi2;
+            acc[0] -= vol[0] * eg.hi0;
+            acc[1] -= vol[1] * eg.hi1;
+            acc[2] -= vol[2] * eg.hi2;
         }
     } else {
+        // volume: -int (sc p) div(phi_c), one metric row at a time through U
+        __syncthreads();
+        const R pv = act ? sc * s_p[le][node] : (R)0;
         for (int c = 0; c < 3; ++c) {
             if (act)
 #pragma unroll
@@ -1084,19 +1130,18 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
         const R hfac = (R)sk.hfac;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int it = node + r * NP;
-            if (it >= 6 * NF || kf[r] == WALL) continue;
-            const int f = it / NF, pt = it - f * NF, d = f >> 1, s = f & 1;
-            const int a = pt % N, b = pt / N;
+            const int f = fo_face(fo[r]);
+            if (((r + 1) * NP > 6 * NF && f >= 6) || kf[r] == WALL) continue;
+            const int pt = fo_point(fo[r]), d = f >> 1, s = f & 1;
             R vk[N];
 #pragma unroll
-            for (int m = 0; m < N; ++m) vk[m] = s_pk[le][node_of<N>(d, m, a, b)];
+            for (int m = 0; m < N; ++m) vk[m] = s_pk[le][fo_node(fo[r], m)];
             const R hk = hfac * trace_chain<N, R>(T.f[s], vk);
             R fbv;
             if constexpr (AFF) {
                 R vw[N];
 #pragma unroll
-                for (int m = 0; m < N; ++m) vw[m] = s_w[le][d][node_of<N>(d, m, a, b)];
+                for (int m = 0; m < N; ++m) vw[m] = s_w[le][d][fo_node(fo[r], m)];
                 const R Af = T.W2[pt] * s_A[le][d];
                 fbv = hk * (trace_chain<N, R>(T.f[s], vw) * (s ? Af : -Af));
             } else {
@@ -1105,7 +1150,7 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
                 for (int c = 0; c < 3; ++c) {
                     R vw[N];
 #pragma unroll
-                    for (int m = 0; m < N; ++m) vw[m] = s_w[le][c][node_of<N>(d, m, a, b)];
+                    for (int m = 0; m < N; ++m) vw[m] = s_w[le][c][fo_node(fo[r], m)];
                     wn += trace_chain<N, R>(T.f[s], vw) * g.nS[((size_t)(e * 6 + f) * 3 + c) * NF + pt];
                 }
                 fbv = hk * wn;
@@ -1146,9 +1191,10 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
         // {(rho h)^k w} . n dS from the two sides' face buffers
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int it = node + r * NP;
-            if (it >= 6 * NF) continue;
-            const int f = it / NF, pt = it - f * NF;
+            const uint64_t fo = g.fofs[r * NP + node];
+            const int f = fo_face(fo);
+            if ((r + 1) * NP > 6 * NF && f >= 6) continue;
+            const int pt = fo_point(fo);
             const int kind = g.kind[e * 6 + f];
             R v = 0;
             if (kind == CONF) {
@@ -1355,12 +1401,8 @@ static void launch_split(const DevMesh& m, KF fast, KS slow, hipStream_t st, Arg
         const int64_t nb = (n + EPB - 1) / EPB;
         hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(threads_of(N)), 0, st, list, n, args...);
     };
-    if (m.ncoarse == 0) {
-        go(fast, nullptr, m.E);
-    } else {
-        go(fast, m.reg_list, m.E - m.ncoarse);
-        go(slow, m.crs_list, m.ncoarse);
-    }
+    go(fast, m.ncoarse ? m.reg_list : nullptr, m.E - m.ncoarse);
+    if (m.ncoarse) go(slow, m.crs_list, m.ncoarse);
 }
 
 #define IMX_DISPATCH_N(n, CALL) \

@@ -30,6 +30,7 @@ struct DevMesh {
     const double* eg = nullptr;     // [E*8] affine elements: h[3], 1/h[3], det J, 1/det J
     const double* iWJ = nullptr;    // [E*Np] 1 / WJ (deformed meshes)
     const float* iWJf = nullptr;
+    const uint64_t* fofs = nullptr; // [fofs_count(n)] face-point words of the all-faces kernels
     int64_t ncoarse = 0;            // elements owning a coarse hanging face
     const int* reg_list = nullptr;  // [E - ncoarse] the other elements
     const int* crs_list = nullptr;  // [ncoarse]
@@ -61,6 +62,9 @@ struct HostTab {
 HostTab make_tab(const Basis1D& b);
 // device layout of the basis tables of degree n-1: size and host-side image
 size_t tab_bytes(int n, int f32);
+// per-lane face-point words (node offsets along the normal, face, point)
+size_t fofs_count(int n);
+void fill_fofs(int n, uint64_t* out);
 void fill_tab(const HostTab& h, int f32, void* out);
 
 // --- element kernels (templated on the floating type R = double / float)

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.hpp"
@@ -138,6 +139,7 @@ static size_t layout(imx_solver* s, char* base) {
     dm.h = D(E * 3);
     dm.hinv = D(E * 3);
     dm.tab = D(tab_bytes(m.n, 0) / 8 + 1);
+    dm.fofs = (const uint64_t*)D(fofs_count(m.n));
     dm.tabf = D(tab_bytes(m.n, 1) / 8 + 1);
     dm.WJ = D(s->Lp);
     dm.eg = D(E * 8);
@@ -786,6 +788,12 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
     CHK(up(s->dm.nbr, m.fnbr.data(), m.fnbr.size() * sizeof(int)));
     CHK(up(s->dm.aux, m.faux.data(), m.faux.size() * sizeof(int)));
     if (m.nh) CHK(up(s->dm.hang, m.hang.data(), m.hang.size() * sizeof(int)));
+    // element lists of the all-faces kernels (elements without a coarse face)
+    // and of the face-by-face kernels, on meshes with hanging faces; the first
+    // is ordered tile by tile over 8 x 8 base columns so that face neighbours
+    // are processed close together in time and meet in the same L2. (On
+    // meshes without them the kernels take the natural order: the list's
+    // dependent load per element cost more than the saved re-reads.)
     std::vector<int> reg, crs;
     if (s->dm.ncoarse) {
         for (int64_t e = 0; e < s->E; ++e) {
@@ -793,9 +801,15 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
             for (int f = 0; f < 6; ++f) c |= m.fkind[6 * e + f] == COARSE;
             (c ? crs : reg).push_back((int)e);
         }
+        constexpr int TILE = 8;
+        auto key = [&](int e) {
+            const int bx = m.base[3 * e], by = m.base[3 * e + 1];
+            return std::make_tuple(by / TILE, bx / TILE, by, bx);
+        };
+        std::stable_sort(reg.begin(), reg.end(), [&](int a, int b) { return key(a) < key(b); });
         CHK(up(s->dm.reg_list, reg.data(), reg.size() * sizeof(int)));
-        CHK(up(s->dm.crs_list, crs.data(), crs.size() * sizeof(int)));
     }
+    if (!crs.empty()) CHK(up(s->dm.crs_list, crs.data(), crs.size() * sizeof(int)));
     CHK(up(s->dm.h, m.h.data(), m.h.size() * sizeof(double)));
     std::vector<double> hinv(m.h.size());
     for (size_t i = 0; i < hinv.size(); ++i) hinv[i] = 1.0 / m.h[i];
@@ -817,6 +831,9 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
     fill_tab(s->tab, 0, tabimg.data());
     fill_tab(s->tab, 1, tabimgf.data());
     CHK(up(s->dm.tab, tabimg.data(), tabimg.size()));
+    std::vector<uint64_t> fo(fofs_count(m.n));
+    fill_fofs(m.n, fo.data());
+    CHK(up(s->dm.fofs, fo.data(), fo.size() * sizeof(uint64_t)));
     CHK(up(s->dm.tabf, tabimgf.data(), tabimgf.size()));
     CHK(up(s->dm.WJ, m.WJ.data(), m.WJ.size() * sizeof(double)));
     std::vector<double> iwj;

@@ -96,9 +96,11 @@ static unsigned stream_grid(int64_t L) {
 // partial[b][v0 + i] = sum over the block's entries of WJ * V_i * z
 template <typename R, int CH>
 __global__ void __launch_bounds__(TPB)
-k_dots(int64_t L, int nv, int v0, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z,
+k_dots(int64_t L, int per, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z,
        const R* __restrict__ WJ, double* __restrict__ partial, int nvtot, const int* __restrict__ ctrl) {
     if (ctrl && *ctrl != 0) return;
+    // chunk blockIdx.x of the vectors, V_{v0} .. V_{v0 + nv - 1}, over entry range blockIdx.y
+    const int v0 = blockIdx.x * per, nv = nvtot - v0 < per ? nvtot - v0 : per;
     using VT = typename Vec16<R>::T;
     constexpr int W = Vec16<R>::W;
     __shared__ double red[(TPB / 64 + 1) * CH];
@@ -106,7 +108,7 @@ k_dots(int64_t L, int nv, int v0, const R* __restrict__ V, int64_t ldv, const R*
 #pragma unroll
     for (int i = 0; i < CH; ++i) acc[i] = 0;
     const int64_t nvec = L / W;   // ldv and L are multiples of W (checked by the launcher)
-    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < nvec; x += (int64_t)gridDim.x * TPB) {
+    for (int64_t x = blockIdx.y * (int64_t)TPB + threadIdx.x; x < nvec; x += (int64_t)gridDim.y * TPB) {
         const VT zz = ((const VT*)z)[x], ww = ((const VT*)WJ)[x];
         double wz[W];
 #pragma unroll
@@ -120,7 +122,7 @@ k_dots(int64_t L, int nv, int v0, const R* __restrict__ V, int64_t ldv, const R*
             }
     }
     block_sum<CH>(acc, red);
-    if (threadIdx.x < nv) partial[(size_t)blockIdx.x * nvtot + v0 + threadIdx.x] = red[TPB / 64 * CH + threadIdx.x];
+    if (threadIdx.x < nv) partial[(size_t)blockIdx.y * nvtot + v0 + threadIdx.x] = red[TPB / 64 * CH + threadIdx.x];
 }
 
 template <typename R>
@@ -131,17 +133,14 @@ void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R
     // amortised over more entries per lane
     const unsigned g = stream_grid(L) > 1024 ? 1024 : stream_grid(L);
     // at most 16 running sums per lane (keeps 7 waves per SIMD); longer bases
-    // take several passes that re-read z and the weights
+    // are split into chunks that each re-read z and the weights
     const int nch = (nv + 15) / 16, per = (nv + nch - 1) / nch;
-    for (int v0 = 0; v0 < nv; v0 += per) {
-        const int c = nv - v0 < per ? nv - v0 : per;
-        if (c <= 8)
-            hipLaunchKernelGGL((k_dots<R, 8>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv,
-                               ctrl);
-        else
-            hipLaunchKernelGGL((k_dots<R, 16>), dim3(g), dim3(TPB), 0, st, L, c, v0, V, ldv, z, WJ, partial, nv,
-                               ctrl);
-    }
+    // the chunks of one entry range are consecutive workgroups (grid x), so z
+    // and the weights are re-read close together in time
+    if (per <= 8)
+        hipLaunchKernelGGL((k_dots<R, 8>), dim3(nch, g), dim3(TPB), 0, st, L, per, V, ldv, z, WJ, partial, nv, ctrl);
+    else
+        hipLaunchKernelGGL((k_dots<R, 16>), dim3(nch, g), dim3(TPB), 0, st, L, per, V, ldv, z, WJ, partial, nv, ctrl);
     final_sum(partial, (int)g, nv, out, st, ctrl);
 }
 template void launch_dots<double>(int64_t, int, const double*, int64_t, const double*, const double*, double*,
