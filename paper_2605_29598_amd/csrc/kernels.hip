@@ -263,6 +263,22 @@ __device__ __forceinline__ void area(const Geom<R>& g, const Tab<N, R>& T, int64
     nS[d] = s ? A : -A;
 }
 
+// the same with the geometry class known at compile time
+template <int N, typename R, bool AFF>
+__device__ __forceinline__ void area_t(const Geom<R>& g, const Tab<N, R>& T, int64_t e, int f, int pt, R nS[3]) {
+    constexpr int NF = N * N;
+    if constexpr (!AFF) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nS[c] = g.nS[((e * 6 + f) * 3 + c) * NF + pt];
+    } else {
+        const int d = f >> 1, s = f & 1;
+        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+        const R A = T.w[pt % N] * T.w[pt / N] * (R)(g.h[3 * e + t1] * g.h[3 * e + t2]);
+        nS[0] = nS[1] = nS[2] = 0;
+        nS[d] = s ? A : -A;
+    }
+}
+
 // W detJ (d xi_d / d x_c) at a node
 template <int N, typename R>
 __device__ __forceinline__ R metric(const Geom<R>& g, int64_t e, int node, int d, int c, R wj) {
@@ -290,9 +306,11 @@ __device__ __forceinline__ R div_T(const R* G, const Tab<N, R>& T, int node) {
 // (rho, m, E with Rusanov dissipation on rho, m, rho kappa), 5..7 stiff
 // pressure {p} nS, 8 stiff enthalpy {rho h u}.nS + Rusanov on rho e.
 template <typename R>
-__device__ __forceinline__ void euler_flux(const R* qa, const R* qbin, const R* nS, bool wall, R gam, R* fl) {
+__device__ __forceinline__ void euler_flux(const R* qa, const R* qbin, const R* nS, bool wall, R gm1, R igm1, R hfac,
+                                           R* fl) {
     const R dS = sqrt(nS[0] * nS[0] + nS[1] * nS[1] + nS[2] * nS[2]);
-    const R nh[3] = {nS[0] / dS, nS[1] / dS, nS[2] / dS};
+    const R idS = (R)1 / dS;
+    const R nh[3] = {nS[0] * idS, nS[1] * idS, nS[2] * idS};
     R qb[5];
     if (wall) {
         const R mn = qa[1] * nh[0] + qa[2] * nh[1] + qa[3] * nh[2];
@@ -302,32 +320,30 @@ __device__ __forceinline__ void euler_flux(const R* qa, const R* qbin, const R* 
     } else {
         for (int t = 0; t < 5; ++t) qb[t] = qbin[t];
     }
-    const R gm1 = gam - (R)1;
+    const R irA = (R)1 / qa[0], irB = (R)1 / qb[0];
     R uA[3], uB[3];
     for (int c = 0; c < 3; ++c) {
-        uA[c] = qa[1 + c] / qa[0];
-        uB[c] = qb[1 + c] / qb[0];
+        uA[c] = qa[1 + c] * irA;
+        uB[c] = qb[1 + c] * irB;
     }
     const R kA = (R)0.5 * (uA[0] * uA[0] + uA[1] * uA[1] + uA[2] * uA[2]);
     const R kB = (R)0.5 * (uB[0] * uB[0] + uB[1] * uB[1] + uB[2] * uB[2]);
     const R pA = gm1 * (qa[4] - qa[0] * kA);
     const R pB = gm1 * (qb[4] - qb[0] * kB);
-    const R unA = uA[0] * nh[0] + uA[1] * nh[1] + uA[2] * nh[2];
-    const R unB = uB[0] * nh[0] + uB[1] * nh[1] + uB[2] * nh[2];
-    const R lam = fmax(fabs(unA), fabs(unB));
-    const R mnA = qa[1] * nS[0] + qa[2] * nS[1] + qa[3] * nS[2];
-    const R mnB = qb[1] * nS[0] + qb[2] * nS[1] + qb[3] * nS[2];
     const R unSA = uA[0] * nS[0] + uA[1] * nS[1] + uA[2] * nS[2];
     const R unSB = uB[0] * nS[0] + uB[1] * nS[1] + uB[2] * nS[2];
-    const R hl = (R)0.5 * lam * dS;
+    // lambda dS = max(|u_A . n|, |u_B . n|) dS = max(|u_A . nS|, |u_B . nS|)
+    const R hl = (R)0.5 * fmax(fabs(unSA), fabs(unSB));
+    const R mnA = qa[1] * nS[0] + qa[2] * nS[1] + qa[3] * nS[2];
+    const R mnB = qb[1] * nS[0] + qb[2] * nS[1] + qb[3] * nS[2];
     fl[0] = (R)0.5 * (mnA + mnB) + hl * (qa[0] - qb[0]);
     for (int c = 0; c < 3; ++c)
         fl[1 + c] = (R)0.5 * (qa[1 + c] * unSA + qb[1 + c] * unSB) + hl * (qa[1 + c] - qb[1 + c]);
     fl[4] = (R)0.5 * (kA * mnA + kB * mnB) + hl * (qa[0] * kA - qb[0] * kB);
     const R pavg = (R)0.5 * (pA + pB);
     for (int c = 0; c < 3; ++c) fl[5 + c] = pavg * nS[c];
-    const R hA = gam / gm1 * pA, hB = gam / gm1 * pB;
-    fl[8] = (R)0.5 * (hA * unSA + hB * unSB) + hl * (pA - pB) / gm1;
+    const R hA = hfac * pA, hB = hfac * pB;
+    fl[8] = (R)0.5 * (hA * unSA + hB * unSB) + hl * (pA - pB) * igm1;
 }
 
 // (rho h)^k (w . nS) at a face point, rounded the same way wherever formed
@@ -357,7 +373,7 @@ __device__ __forceinline__ R coarse_point(const P* f, const R* fv, const Tab<N, 
 // =====================================================================
 // Explicit residual: fNS = M^{-1} T_NS, fS = M^{-1} T_S (momentum, energy)
 // =====================================================================
-template <int N, typename R, bool SLOW>
+template <int N, typename R, bool SLOW, bool AFF>
 __global__ void __launch_bounds__(threads_of(N))
 k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, R* __restrict__ fNS, R* __restrict__ fS, Geom<R> g, const Tab<N, R>* __restrict__ Tg,
            PhysK ph, const double* __restrict__ sponge) {
@@ -373,7 +389,7 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
     const bool act = le < EPB && slot < nel;
     const int64_t e = act ? (elist ? (int64_t)elist[slot] : slot) : 0;
     const size_t fs = (size_t)g.E * NP;
-    const R gam = (R)ph.gamma;
+    const R gm1 = (R)ph.gm1, igm1 = (R)ph.igm1, hfac = (R)ph.hfac;
     if (act)
         for (int t = 0; t < 5; ++t) s_q[le][t][node] = q[t * fs + e * NP + node];
     constexpr bool slow = SLOW;
@@ -396,8 +412,8 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
                     for (int t = 0; t < 5; ++t)
                         qb[t] = coarse_point<N>(q + t * fs + (size_t)nbr * NP, T.f[1 - s], T, d,
                                                 g.aux[e * 6 + f] & 3, pt);
-                area<N>(g, T, e, f, pt, nS);
-                euler_flux<R>(qa, qb, nS, kind == WALL, gam, fl);
+                area_t<N, R, AFF>(g, T, e, f, pt, nS);
+                euler_flux<R>(qa, qb, nS, kind == WALL, gm1, igm1, hfac, fl);
                 for (int o = 0; o < 9; ++o) U[(f * 9 + o) * NF + pt] = fl[o];
             }
         __syncthreads();
@@ -437,7 +453,7 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
                             qa[t] = sub_interp<N>(s_own + t * NF, T, hs, pt);
                             qb[t] = face_value<N>(q + t * fs + (size_t)fn * NP, T.f[1 - s], d, pt);
                         }
-                        area<N>(g, T, fn, f ^ 1, pt, nS);
+                        area_t<N, R, AFF>(g, T, fn, f ^ 1, pt, nS);
                         for (int c = 0; c < 3; ++c) nS[c] = -nS[c];
                     } else {
                         for (int t = 0; t < 5; ++t) qa[t] = s_own[t * NF + pt];
@@ -447,9 +463,9 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
                             for (int t = 0; t < 5; ++t) qb[t] = sub_interp<N>(s_nb + t * NF, T, aux & 3, pt);
                         else
                             wall = true;
-                        area<N>(g, T, e, f, pt, nS);
+                        area_t<N, R, AFF>(g, T, e, f, pt, nS);
                     }
-                    euler_flux<R>(qa, qb, nS, wall, gam, fl);
+                    euler_flux<R>(qa, qb, nS, wall, gm1, igm1, hfac, fl);
                     if (kind == COARSE)
                         for (int o = 0; o < 9; ++o) s_sub[(hs * 9 + o) * NF + pt] = fl[o];
                     else
@@ -482,8 +498,8 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
         const R irho = (R)1 / rho;
         for (int c = 0; c < 3; ++c) u[c] = s_q[le][1 + c][node] * irho;
         kin = (R)0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-        p = (gam - (R)1) * (s_q[le][4][node] - rho * kin);
-        wj = g.WJ[e * NP + node];
+        p = gm1 * (s_q[le][4][node] - rho * kin);
+        wj = AFF ? T.W3[node] * (R)g.eg[e * 8 + 6] : g.WJ[e * NP + node];
     }
     for (int r3 = 0; r3 < 3; ++r3) {
         if (act)
@@ -500,13 +516,20 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
                 } else if (o < 8) {
                     for (int c = 0; c < 3; ++c) F[c] = (c == o - 5) ? p : (R)0;
                 } else {
-                    const R rh = gam / (gam - (R)1) * p;
+                    const R rh = hfac * p;
                     for (int c = 0; c < 3; ++c) F[c] = rh * u[c];
                 }
-                for (int dd = 0; dd < 3; ++dd) {
-                    R v = 0;
-                    for (int c = 0; c < 3; ++c) v += metric<N>(g, e, node, dd, c, wj) * F[c];
-                    U[(o3 * 3 + dd) * NP + node] = v;
+                if constexpr (AFF) {
+#pragma unroll
+                    for (int dd = 0; dd < 3; ++dd) U[(o3 * 3 + dd) * NP + node] = (wj * (R)g.hinv[3 * e + dd]) * F[dd];
+                } else {
+#pragma unroll
+                    for (int dd = 0; dd < 3; ++dd) {
+                        R v = 0;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) v += g.G[((size_t)(dd * 3 + c) * g.E + e) * NP + node] * F[c];
+                        U[(o3 * 3 + dd) * NP + node] = v;
+                    }
                 }
             }
         __syncthreads();
@@ -523,7 +546,7 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
         const R lam = (R)sponge[e * NP + node];
         for (int c = 0; c < 3; ++c) acc[1 + c] -= wj * lam * (s_q[le][1 + c][node] - rho * (R)ph.su[c]);
     }
-    const R iwj = (R)1 / wj;
+    const R iwj = AFF ? T.iW3[node] * (R)g.eg[e * 8 + 7] : g.iWJ[e * NP + node];
     for (int t = 0; t < 5; ++t) fNS[t * fs + e * NP + node] = acc[t] * iwj;
     for (int t = 0; t < 4; ++t) fS[t * fs + e * NP + node] = acc[5 + t] * iwj;
 }
@@ -1250,13 +1273,14 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
 // =====================================================================
 // Picard refresh: Gp = G0h - M^{-1} Lambda^k - rho kappa^k [- R1 gravity lag]
 // =====================================================================
+// lambda/2 ((rho e)_A - (rho e)_B) dS with lambda = max(|u_A . n|, |u_B . n|):
+// the unit normal's 1/dS cancels against dS
 template <int N>
-__device__ __forceinline__ double lambda_flux(const double* a, const double* b, const double* nS, double gm1) {
-    const double dS = sqrt(nS[0] * nS[0] + nS[1] * nS[1] + nS[2] * nS[2]);
-    const double unA = (a[0] * nS[0] + a[1] * nS[1] + a[2] * nS[2]) / dS;
-    const double unB = (b[0] * nS[0] + b[1] * nS[1] + b[2] * nS[2]) / dS;
+__device__ __forceinline__ double lambda_flux(const double* a, const double* b, const double* nS, double igm1) {
+    const double unA = a[0] * nS[0] + a[1] * nS[1] + a[2] * nS[2];
+    const double unB = b[0] * nS[0] + b[1] * nS[1] + b[2] * nS[2];
     const double lam = fmax(fabs(unA), fabs(unB));
-    return 0.5 * lam * (a[3] - b[3]) / gm1 * dS;
+    return 0.5 * lam * (a[3] - b[3]) * igm1;
 }
 
 template <int N, bool SLOW>
@@ -1277,7 +1301,7 @@ k_lambda(const int* __restrict__ elist, int64_t nel, const double* __restrict__ 
     const bool act = le < EPB && slot < nel;
     const int64_t e = act ? (elist ? (int64_t)elist[slot] : slot) : 0;
     const size_t fs = (size_t)g.E * NP;
-    const R gm1 = sk.gamma - 1.0;
+    const R igm1 = sk.igm1;
     R* U = &s_u[le][0];
     // fields 0..2: u^k, 3: p^k
     auto src = [&](int t) -> const R* { return t < 3 ? uk + t * fs : pk; };
@@ -1301,7 +1325,7 @@ k_lambda(const int* __restrict__ elist, int64_t nel, const double* __restrict__ 
                                                               g.aux[e * 6 + f] & 3, pt);
                     }
                     area<N>(g, T, e, f, pt, nS);
-                    v = lambda_flux<N>(a, b, nS, gm1);
+                    v = lambda_flux<N>(a, b, nS, igm1);
                 }
                 U[f * NF + pt] = v;
             }
@@ -1353,7 +1377,7 @@ k_lambda(const int* __restrict__ elist, int64_t nel, const double* __restrict__ 
                         }
                         area<N>(g, T, e, f, pt, nS);
                     }
-                    const R v = lambda_flux<N>(a, b, nS, gm1);
+                    const R v = lambda_flux<N>(a, b, nS, igm1);
                     if (kind == COARSE) s_sub[hs * NF + pt] = v;
                     else s_fl[pt] = v;
                 }
@@ -1374,10 +1398,10 @@ k_lambda(const int* __restrict__ elist, int64_t nel, const double* __restrict__ 
         }
     }
     if (!act) return;
-    const R wj = g.WJ[e * NP + node];
+    const R iwj = g.deformed ? g.iWJ[e * NP + node] : T.iW3[node] * g.eg[e * 8 + 7];
     const R r = rho[e * NP + node];
     const R u0 = s_q[le][0][node], u1 = s_q[le][1][node], u2 = s_q[le][2][node];
-    R res = G0h[e * NP + node] - sk.c_dt * acc / wj - r * 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
+    R res = G0h[e * NP + node] - sk.c_dt * acc * iwj - r * 0.5 * (u0 * u0 + u1 * u1 + u2 * u2);
     if (sk.scheme == 1) res -= sk.c_dt * sk.g * r * u2;
     Gp[e * NP + node] = res;
 }
@@ -1416,9 +1440,15 @@ static void launch_split(const DevMesh& m, KF fast, KS slow, hipStream_t st, Arg
 template <typename R>
 void launch_explicit(const DevMesh& m, const HostTab&, const PhysK& ph, const R* q, R* fNS, R* fS,
                      hipStream_t st) {
-#define CALL(NN)                                                                                      \
-    launch_split<NN>(m, k_explicit<NN, R, false>, k_explicit<NN, R, true>, st, q, fNS, fS, geom<R>(m), \
-                     (const Tab<NN, R>*)tab_ptr<R>(m), ph, m.sponge)
+#define CALL(NN)                                                                                            \
+    do {                                                                                                    \
+        if (m.deformed)                                                                                     \
+            launch_split<NN>(m, k_explicit<NN, R, false, false>, k_explicit<NN, R, true, false>, st, q, fNS, \
+                             fS, geom<R>(m), (const Tab<NN, R>*)tab_ptr<R>(m), ph, m.sponge);              \
+        else                                                                                                \
+            launch_split<NN>(m, k_explicit<NN, R, false, true>, k_explicit<NN, R, true, true>, st, q, fNS,  \
+                             fS, geom<R>(m), (const Tab<NN, R>*)tab_ptr<R>(m), ph, m.sponge);               \
+    } while (0)
     IMX_DISPATCH_N(m.n, CALL)
 #undef CALL
 }

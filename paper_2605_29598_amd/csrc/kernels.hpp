@@ -40,6 +40,7 @@ struct DevMesh {
 
 struct PhysK {
     double gamma, g, f;
+    double gm1, igm1, hfac;   // gamma - 1, 1 / (gamma - 1), gamma / (gamma - 1)
     double su[3];
     int sponge;
 };

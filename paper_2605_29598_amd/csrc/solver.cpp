@@ -598,6 +598,9 @@ static PhysK phys_k(const imx_solver* s) {
     k.gamma = s->phys.gamma;
     k.g = s->phys.g;
     k.f = s->phys.f;
+    k.gm1 = s->phys.gamma - 1.0;
+    k.igm1 = 1.0 / (s->phys.gamma - 1.0);
+    k.hfac = s->phys.gamma / (s->phys.gamma - 1.0);
     for (int c = 0; c < 3; ++c) k.su[c] = s->phys.sponge_u[c];
     k.sponge = s->phys.sponge_lambda != 0.0;
     return k;
