@@ -132,15 +132,13 @@ void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R
     // the 3 M-entry channel basis): the block reduction of up to 16 sums is
     // amortised over more entries per lane
     const unsigned g = stream_grid(L) > 1024 ? 1024 : stream_grid(L);
-    // at most 16 running sums per lane (keeps 7 waves per SIMD); longer bases
-    // are split into chunks that each re-read z and the weights
-    const int nch = (nv + 15) / 16, per = (nv + nch - 1) / nch;
+    // at most 8 running sums per lane (36 VGPRs, full occupancy; measured
+    // faster than 4, 6 and 16 on the channel basis); longer bases are split
+    // into chunks that each re-read z and the weights
+    const int nch = (nv + 7) / 8, per = (nv + nch - 1) / nch;
     // the chunks of one entry range are consecutive workgroups (grid x), so z
     // and the weights are re-read close together in time
-    if (per <= 8)
-        hipLaunchKernelGGL((k_dots<R, 8>), dim3(nch, g), dim3(TPB), 0, st, L, per, V, ldv, z, WJ, partial, nv, ctrl);
-    else
-        hipLaunchKernelGGL((k_dots<R, 16>), dim3(nch, g), dim3(TPB), 0, st, L, per, V, ldv, z, WJ, partial, nv, ctrl);
+    hipLaunchKernelGGL((k_dots<R, 8>), dim3(nch, g), dim3(TPB), 0, st, L, per, V, ldv, z, WJ, partial, nv, ctrl);
     final_sum(partial, (int)g, nv, out, st, ctrl);
 }
 template void launch_dots<double>(int64_t, int, const double*, int64_t, const double*, const double*, double*,
