@@ -134,7 +134,12 @@ def served_run(args):
     from paper_2605_29598_amd import binding as B
     from paper_2605_29598_amd import workloads as W
 
-    trace = W.served_trace(n_requests=args.serve_requests, rate_per_s=2.0, elem_min=2000, elem_max=24000,
+    # members are scaled down from the full ensemble (E uniform in 2k-200k, 50
+    # steps, Poisson arrivals at 2/s); the arrival rate is scaled up by the same
+    # factor as the work per member, so the offered load matches the full trace
+    e_lo, e_hi = 2000, 24000
+    rate = 2.0 * ((2000 + 200000) / (e_lo + e_hi)) * (50.0 / args.serve_steps)
+    trace = W.served_trace(n_requests=args.serve_requests, rate_per_s=rate, elem_min=e_lo, elem_max=e_hi,
                            steps=args.serve_steps, seed=5)
     meshes, q0s, dofs = [], [], []
     for r in trace:
@@ -216,8 +221,9 @@ def served_run(args):
 
     fp64 = served(B.IMX_FP64)
     mixed = served(B.IMX_MIXED)
-    return {"workload": f"{len(trace)} requests, Poisson arrivals 2/s, IGW channel or orography members, "
-                        f"elements uniform 2k-24k, degree 2-4, {args.serve_steps} ARK2 steps each",
+    return {"workload": f"{len(trace)} requests, Poisson arrivals at {rate:.1f}/s (the full ensemble's 2/s scaled "
+                        f"by its work per member), IGW channel or orography members, elements uniform 2k-24k, "
+                        f"degree 2-4, {args.serve_steps} ARK2 steps each",
             "dof_updates": total, "queue_alone_fp64": serial, "served_fp64": fp64, "served_fp32_inner": mixed,
             "speedup_served_fp64_vs_queue": fp64["dof_updates_per_s"] / serial["dof_updates_per_s"],
             "speedup_served_fp32_inner_vs_queue": mixed["dof_updates_per_s"] / serial["dof_updates_per_s"]}
