@@ -135,8 +135,8 @@ struct Geom {
     const double* h;
     const double* hinv;   // 1 / h, per element and direction
     const R* WJ;
-    const R* G;
-    const R* nS;
+    const R* G;     // terrain-following meshes: W cof(J) entries (0,0), (1,1), (2,0), (2,1), (2,2) as [5][E][Np]
+    const R* nS;    // terrain-following meshes: n dS as [E][10][Nf] (x, y faces: normal component; z faces: 3)
     const double* eg;     // affine elements: h[3], 1/h[3], det J, 1/det J (8 per element)
     const R* iWJ;         // 1 / WJ (deformed meshes)
     const uint64_t* fofs; // face-point words per (round, lane), see fo_node
@@ -155,6 +155,9 @@ Geom<float> geom<float>(const DevMesh& m) {
 
 constexpr int epb_of(int N) { return N == 2 ? 16 : (N == 3 ? 9 : (N == 4 ? 4 : 2)); }
 constexpr int threads_of(int N) { return ((epb_of(N) * N * N * N + 63) / 64) * 64; }
+// elements per workgroup of the specialised Krylov-loop passes
+constexpr int epb_mv(int N) { return epb_of(N); }
+constexpr int threads_mv(int N) { return ((epb_mv(N) * N * N * N + 63) / 64) * 64; }
 
 // Consecutive workgroups are dispatched round-robin over the 8 XCDs; give
 // every XCD a contiguous run of logical blocks so that neighbouring elements
@@ -247,13 +250,37 @@ __device__ __forceinline__ R sub_interp_T(const R* sv, const Tab<N, R>& T, int h
     return acc;
 }
 
+// The terrain-following (Gal-Chen) map keeps x and y affine in the reference
+// coordinates, so W cof(J) vanishes at (0,1), (0,2), (1,0), (1,2) and the n dS
+// of the x- and y-faces has only its normal component: only the other
+// entries are stored (the host checks that the dropped ones are zero).
+template <int N, typename R>
+__device__ __forceinline__ void nS_gc(const Geom<R>& g, int64_t e, int f, int pt, R nS[3]) {
+    constexpr int NF = N * N;
+    const R* b = g.nS + (size_t)e * 10 * NF;
+    if (f < 4) {
+        nS[0] = nS[1] = nS[2] = 0;
+        nS[f >> 1] = b[f * NF + pt];
+    } else {
+        const int s0 = 4 + 3 * (f - 4);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nS[c] = b[(s0 + c) * NF + pt];
+    }
+}
+// W cof(J)[dd][c] at entry o = e Np + node of a field of E Np values
+template <typename R>
+__device__ __forceinline__ R G_gc(const Geom<R>& g, size_t fsz, int dd, int c, size_t o) {
+    if (dd == 0) return c == 0 ? g.G[o] : (R)0;
+    if (dd == 1) return c == 1 ? g.G[fsz + o] : (R)0;
+    return g.G[(size_t)(2 + c) * fsz + o];
+}
+
 // W2-weighted outward area vector of face f of element e at point pt
 template <int N, typename R>
 __device__ __forceinline__ void area(const Geom<R>& g, const Tab<N, R>& T, int64_t e, int f, int pt, R nS[3]) {
     constexpr int NF = N * N;
     if (g.deformed) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) nS[c] = g.nS[((e * 6 + f) * 3 + c) * NF + pt];
+        nS_gc<N, R>(g, e, f, pt, nS);
         return;
     }
     const int d = f >> 1, s = f & 1;
@@ -268,8 +295,7 @@ template <int N, typename R, bool AFF>
 __device__ __forceinline__ void area_t(const Geom<R>& g, const Tab<N, R>& T, int64_t e, int f, int pt, R nS[3]) {
     constexpr int NF = N * N;
     if constexpr (!AFF) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) nS[c] = g.nS[((e * 6 + f) * 3 + c) * NF + pt];
+        nS_gc<N, R>(g, e, f, pt, nS);
     } else {
         const int d = f >> 1, s = f & 1;
         const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
@@ -283,7 +309,7 @@ __device__ __forceinline__ void area_t(const Geom<R>& g, const Tab<N, R>& T, int
 template <int N, typename R>
 __device__ __forceinline__ R metric(const Geom<R>& g, int64_t e, int node, int d, int c, R wj) {
     constexpr int NP = N * N * N;
-    if (g.deformed) return g.G[((size_t)(d * 3 + c) * g.E + e) * NP + node];
+    if (g.deformed) return G_gc<R>(g, (size_t)g.E * NP, d, c, (size_t)e * NP + node);
     return d == c ? wj * (R)g.hinv[3 * e + d] : (R)0;
 }
 
@@ -527,7 +553,7 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
                     for (int dd = 0; dd < 3; ++dd) {
                         R v = 0;
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) v += g.G[((size_t)(dd * 3 + c) * g.E + e) * NP + node] * F[c];
+                        for (int c = 0; c < 3; ++c) v += G_gc<R>(g, fs, dd, c, (size_t)e * NP + node) * F[c];
                         U[(o3 * 3 + dd) * NP + node] = v;
                     }
                 }
@@ -993,12 +1019,12 @@ struct ElemGeo {
 };
 
 template <int N, typename R, bool AFF, int SCH>
-__global__ void __launch_bounds__(threads_of(N))
+__global__ void __launch_bounds__(threads_mv(N))
 k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
       const R* __restrict__ cr, const R* __restrict__ pk, R* __restrict__ w, R* __restrict__ FB, Geom<R> g,
       const Tab<N, R>* __restrict__ Tg, StageK sk, const int* __restrict__ ctrl) {
     if (ctrl && *ctrl != 0) return;   // the Krylov cycle has stopped
-    constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
+    constexpr int NP = N * N * N, NF = N * N, EPB = epb_mv(N);
     constexpr int NR = (6 * NF + NP - 1) / NP;   // face points per lane
     constexpr int LF = AFF ? 6 * NF : 18 * NF, LV = AFF ? NP : 3 * NP;
     __shared__ R s_p[EPB][NP];
@@ -1066,8 +1092,12 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
                 const R Af = T.W2[pt] * s_A[le][d];
                 U[f * NF + pt] = avg * (s ? Af : -Af);
             } else {
+                {
+                    R nS[3];
+                    nS_gc<N, R>(g, e, f, pt, nS);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) U[(f * 3 + c) * NF + pt] = avg * g.nS[((size_t)(e * 6 + f) * 3 + c) * NF + pt];
+                    for (int c = 0; c < 3; ++c) U[(f * 3 + c) * NF + pt] = avg * nS[c];
+                }
             }
         }
     // affine volume term (after the face points: their registers are free) -int (sc p) div(phi_c), from s_v
@@ -1118,7 +1148,7 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
         for (int c = 0; c < 3; ++c) {
             if (act)
 #pragma unroll
-                for (int dd = 0; dd < 3; ++dd) U[dd * NP + node] = g.G[(size_t)((dd * 3 + c) * fs) + o] * pv;
+                for (int dd = 0; dd < 3; ++dd) U[dd * NP + node] = G_gc<R>(g, fs, dd, c, o) * pv;
             __syncthreads();
             if (act) acc[c] -= div_T<N>(U, T, node);
             __syncthreads();
@@ -1168,13 +1198,14 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
                 const R Af = T.W2[pt] * s_A[le][d];
                 fbv = hk * (trace_chain<N, R>(T.f[s], vw) * (s ? Af : -Af));
             } else {
-                R wn = 0;
+                R wn = 0, nS[3];
+                nS_gc<N, R>(g, e, f, pt, nS);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     R vw[N];
 #pragma unroll
                     for (int m = 0; m < N; ++m) vw[m] = s_w[le][c][fo_node(fo[r], m)];
-                    wn += trace_chain<N, R>(T.f[s], vw) * g.nS[((size_t)(e * 6 + f) * 3 + c) * NF + pt];
+                    wn += trace_chain<N, R>(T.f[s], vw) * nS[c];
                 }
                 fbv = hk * wn;
             }
@@ -1184,13 +1215,13 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
 }
 
 template <int N, typename R, bool AFF, int SCH>
-__global__ void __launch_bounds__(threads_of(N))
+__global__ void __launch_bounds__(threads_mv(N))
 k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
       const R* __restrict__ w, const R* __restrict__ pk, const R* __restrict__ rho, const R* __restrict__ FB,
       const R* __restrict__ FBh, R* __restrict__ out, int dual, Geom<R> g, const Tab<N, R>* __restrict__ Tg,
       StageK sk, const int* __restrict__ ctrl) {
     if (ctrl && *ctrl != 0) return;
-    constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
+    constexpr int NP = N * N * N, NF = N * N, EPB = epb_mv(N);
     constexpr int NR = (6 * NF + NP - 1) / NP;
     __shared__ R s_face[EPB][6 * NF];
     __shared__ R s_vol[EPB][3][NP];
@@ -1241,7 +1272,7 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
             for (int dd = 0; dd < 3; ++dd) {
                 R v = 0;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) v += g.G[(size_t)((dd * 3 + c) * fs) + o] * wv[c];
+                for (int c = 0; c < 3; ++c) v += G_gc<R>(g, fs, dd, c, o) * wv[c];
                 s_vol[le][dd][node] = rh * v;
             }
         }
@@ -1599,14 +1630,14 @@ template void launch_pass2<float>(const DevMesh&, const HostTab&, const StageK&,
 template <typename R, int N, bool AFF, int SCH>
 static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
                  const R* pk, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st, const int* ctrl) {
-    constexpr int EPB = epb_of(N);
+    constexpr int EPB = epb_of(N), EPBM = epb_mv(N);
     const Tab<N, R>* T = (const Tab<N, R>*)tab_ptr<R>(m);
     const int64_t nf = m.ncoarse ? m.E - m.ncoarse : m.E, ns = m.ncoarse;
-    const int64_t bf = (nf + EPB - 1) / EPB, bs = (ns + EPB - 1) / EPB;
+    const int64_t bf = (nf + EPBM - 1) / EPBM, bs = (ns + EPB - 1) / EPB;
     const int* fl = m.ncoarse ? m.reg_list : nullptr;
     if (!out) {
         if (bf > 0)
-            hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_of(N)), 0, st, fl, (int)nf, x,
+            hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, st, fl, (int)nf, x,
                                xs, cr, pk, w, FB, geom<R>(m), T, sk, ctrl);
         if (bs > 0)
             hipLaunchKernelGGL((k_pass1<N, R, true>), dim3((unsigned)bs), dim3(threads_of(N)), 0, st, m.crs_list, ns,
@@ -1614,7 +1645,7 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
                                ctrl);
     } else {
         if (bf > 0)
-            hipLaunchKernelGGL((k_mv2<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_of(N)), 0, st, fl, (int)nf, x,
+            hipLaunchKernelGGL((k_mv2<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, st, fl, (int)nf, x,
                                xs, (const R*)w, pk, rho, (const R*)FB, (const R*)FBh, out, dual, geom<R>(m), T, sk,
                                ctrl);
         if (bs > 0)

@@ -144,8 +144,8 @@ static size_t layout(imx_solver* s, char* base) {
     dm.WJ = D(s->Lp);
     dm.eg = D(E * 8);
     if (m.deformed) {
-        dm.G = D(9 * L);
-        dm.nS = D((size_t)E * 6 * 3 * Nf);
+        dm.G = D(5 * L);
+        dm.nS = D((size_t)E * 10 * Nf);
         dm.iWJ = D(L);
     }
     s->cr = D(L);
@@ -194,8 +194,8 @@ static size_t layout(imx_solver* s, char* base) {
         s->crf = F(L);
         dm.WJf = s->WJf;
         if (m.deformed) {
-            s->Gf = F(9 * L);
-            s->nSf = F((size_t)E * 6 * 3 * Nf);
+            s->Gf = F(5 * L);
+            s->nSf = F((size_t)E * 10 * Nf);
             dm.Gf = s->Gf;
             dm.nSf = s->nSf;
             dm.iWJf = F(L);
@@ -291,10 +291,12 @@ static void timed(imx_solver* s, int kind, double bytes, Fn&& launch) {
 }
 
 // algorithmic bytes of one launch: nfields nodal fields of the element kernels
-// plus the geometry (per element 10 Np + 9 Nf values when deformed)
+// plus the stored geometry of terrain-following elements
 static double field_bytes(const imx_solver* s, double nfields, bool geometry) {
     double b = nfields * (double)s->L * 8.0;
-    if (geometry && s->mesh->deformed) b += (double)s->E * (10.0 * s->Np + 9.0 * s->Nf) * 8.0;
+    // stored geometry of a terrain-following element: W detJ (or its inverse),
+    // 5 entries of W cof(J) per node, 10 n dS values per face point
+    if (geometry && s->mesh->deformed) b += (double)s->E * (6.0 * s->Np + 10.0 * s->Nf) * 8.0;
     return b;
 }
 
@@ -852,10 +854,43 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
     CHK(up(s->dm.fofs, fo.data(), fo.size() * sizeof(uint64_t)));
     CHK(up(s->dm.tabf, tabimgf.data(), tabimgf.size()));
     CHK(up(s->dm.WJ, m.WJ.data(), m.WJ.size() * sizeof(double)));
-    std::vector<double> iwj;
+    std::vector<double> iwj, g5, n10;
     if (m.deformed) {
-        CHK(up(s->dm.G, m.G.data(), m.G.size() * sizeof(double)));
-        CHK(up(s->dm.nS, m.nS.data(), m.nS.size() * sizeof(double)));
+        // terrain-following geometry: x and y are affine in the reference
+        // coordinates, so only 5 entries of W cof(J) and, on x- and y-faces,
+        // only the normal component of n dS can be nonzero; keep those
+        const size_t Lz = (size_t)s->L, NF = (size_t)s->Nf;
+        const int keep[5][2] = {{0, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}};
+        g5.resize(5 * Lz);
+        for (int k = 0; k < 5; ++k)
+            std::memcpy(&g5[k * Lz], &m.G[(keep[k][0] * 3 + keep[k][1]) * Lz], Lz * sizeof(double));
+        bool ok = true;
+        for (int dd = 0; dd < 2; ++dd)
+            for (int c = 0; c < 3; ++c)
+                if (c != dd)
+                    for (size_t i = 0; i < Lz; ++i) ok &= m.G[(dd * 3 + c) * Lz + i] == 0.0;
+        n10.resize((size_t)s->E * 10 * NF);
+        for (int64_t e = 0; e < s->E; ++e) {
+            const double* src = &m.nS[(size_t)e * 18 * NF];
+            double* dst = &n10[(size_t)e * 10 * NF];
+            for (int f = 0; f < 6; ++f)
+                for (int c = 0; c < 3; ++c)
+                    for (size_t pt = 0; pt < NF; ++pt) {
+                        const double v = src[(f * 3 + c) * NF + pt];
+                        if (f < 4) {
+                            if (c == f / 2) dst[f * NF + pt] = v;
+                            else ok &= v == 0.0;
+                        } else {
+                            dst[(4 + 3 * (f - 4) + c) * NF + pt] = v;
+                        }
+                    }
+        }
+        if (!ok) {
+            set_error("imx_solver_bind_workspace: geometry is not of terrain-following form");
+            return IMX_EINVAL;
+        }
+        CHK(up(s->dm.G, g5.data(), g5.size() * sizeof(double)));
+        CHK(up(s->dm.nS, n10.data(), n10.size() * sizeof(double)));
         iwj.resize(s->L);
         for (int64_t i = 0; i < s->L; ++i) iwj[i] = 1.0 / m.WJ[i];
         CHK(up(s->dm.iWJ, iwj.data(), iwj.size() * sizeof(double)));
@@ -881,9 +916,9 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
         tmp.assign(m.WJ.begin(), m.WJ.end());
         CHK(up(s->WJf, tmp.data(), tmp.size() * sizeof(float)));
         if (m.deformed) {
-            tmp.assign(m.G.begin(), m.G.end());
+            tmp.assign(g5.begin(), g5.end());
             CHK(up(s->Gf, tmp.data(), tmp.size() * sizeof(float)));
-            tmp.assign(m.nS.begin(), m.nS.end());
+            tmp.assign(n10.begin(), n10.end());
             CHK(up(s->nSf, tmp.data(), tmp.size() * sizeof(float)));
             std::vector<float> iwf(iwj.begin(), iwj.end());
             CHK(up(s->dm.iWJf, iwf.data(), iwf.size() * sizeof(float)));

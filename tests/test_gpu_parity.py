@@ -229,3 +229,34 @@ def test_mixed_precision_tiny_box_vs_oracle():
     assert max(errs) < MIXED_BOUND, errs
     M0 = dg.total_mass(om, y0)
     assert abs(sol.total_mass() - M0) <= 1e-13 * M0
+
+
+def test_mixed_precision_r3_affine_vs_oracle():
+    """The binary32 Krylov loop on an r = 3 affine mesh (the one-wavefront-per-
+    element pass 2), 4 steps of R1 against the FP64 oracle."""
+    B = _B()
+    w = W.tiny_box(degree=3, scheme=dg.R1)
+    gm = B.Mesh(w.mesh)
+    om = OMesh(MeshDesc(**vars(w.mesh)))
+    y0 = W.initial_state(w, om.node_coords())
+    sol = B.Solver(gm, w.phys, w.num, precision=B.IMX_MIXED, inner_tol=1e-3)
+    sol.set_state(y0)
+    sol.step(4)
+    g = _cpu(sol.get_state())
+    y = y0
+    for _ in range(4):
+        y, _ = dg.ark2_step(om, dg.Phys(**vars(w.phys)), dg.Numerics(**vars(w.num)), y)
+    scale = state_scales(y)
+    errs = [np.abs(g[t] - y[t]).max() / scale[t] for t in range(5)]
+    assert max(errs) < MIXED_BOUND, errs
+
+
+def test_ark2_steps_r3_affine_parity_fixed():
+    """Fixed-count ARK2 steps on an r = 3 affine mesh (both Schur passes in
+    their r = 3 forms), R2, against the oracle."""
+    w = W.tiny_box(degree=3)
+    num = W.NumSpec(dt=2.0, picard_max=3, gmres_max=12, gmres_restart=8, fixed_iterations=True)
+    g, o, y0, gst, ost, _ = _run_steps(w.mesh, w.phys, num, w, 2)
+    scale = state_scales(o)
+    for t in range(5):
+        assert np.abs(g[t] - o[t]).max() < TOL * scale[t], (t, np.abs(g[t] - o[t]).max() / scale[t])
