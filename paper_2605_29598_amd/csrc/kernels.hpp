@@ -135,7 +135,8 @@ template <typename R>
 void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R* WJ, double* partial,
                  double* out, hipStream_t st, const int* ctrl = nullptr);
 // z1 = z - sum_i c_i V_i with c_i = raw[i]*s[i]^2 ; then out[i] = sum WJ V_i z1 (if dots) or
-// out[0] = sum WJ z1^2 (norm)
+// out[0] = sum WJ z1^2 (norm; with out = null the axpy_norm_blocks(L) partial
+// sums are left in partial for the caller)
 template <typename R>
 void launch_axpy_reduce(int64_t L, int nv, const R* V, int64_t ldv, const double* raw, const double* s,
                         const R* z, R* z1, const R* WJ, int mode_norm, double* partial, double* out,
@@ -155,10 +156,14 @@ struct GState {
     int maxit, fixed;
     float svf[GM + 1];         // binary32 copies of sv
 };
-// Column j: raw = first-pass projections <V_i, z> (i <= j) and raw[j+1] = |z|^2,
-// nrm = |z1|^2 after the update. raw2 == null: first pass (may set status 2);
-// raw2 != null: finishes a column after the host's second pass.
-void launch_givens(GState* G, int j, const double* raw, const double* raw2, const double* nrm, hipStream_t st);
+// Column j: raw = first-pass projections <V_i, z> (i <= j) and raw[j+1] = |z|^2;
+// |z1|^2 after the update is the sum of npart[0..nb) (the partials of
+// launch_axpy_reduce in norm mode with out = null, nb = axpy_norm_blocks(L)).
+// raw2 == null: first pass (may set status 2); raw2 != null: finishes a column
+// after the host's second pass.
+void launch_givens(GState* G, int j, const double* raw, const double* raw2, const double* npart, int nb,
+                   hipStream_t st);
+int axpy_norm_blocks(int64_t L);
 // x += sum_i coef[i] V_i
 template <typename R>
 void launch_lincomb(int64_t L, int nv, const R* V, int64_t ldv, const double* coef, R* x, hipStream_t st);

@@ -357,7 +357,6 @@ static imx_status arnoldi_cycle(imx_solver* s, R* V, const R* WJ, int m, double 
     GState* dn = s->hgs + 1;
     double* raw1 = s->dsc + imx_solver::S_RAW1;
     double* raw2 = s->dsc + imx_solver::S_RAW2;
-    double* nrm = s->dsc + imx_solver::S_NRM;
     std::memset(up, 0, sizeof(GState));
     up->g[0] = beta;
     up->sv[0] = 1.0 / beta;
@@ -375,9 +374,9 @@ static imx_status arnoldi_cycle(imx_solver* s, R* V, const R* WJ, int m, double 
         const int nd = raw2p ? j + 1 : j + 2;   // the second pass needs no |z|^2
         timed(s, IMX_K_DOTS, (nd + 1) * vb, [&] { launch_dots<R>(L, nd, V, L, Vn, WJ, s->partial, raw, s->st, c); });
         timed(s, IMX_K_ORTHO, (j + 4) * vb, [&] {
-            launch_axpy_reduce<R>(L, j + 1, V, L, raw, G->sv, Vn, Vn, WJ, 1, s->partial, nrm, s->st, c);
+            launch_axpy_reduce<R>(L, j + 1, V, L, raw, G->sv, Vn, Vn, WJ, 1, s->partial, nullptr, s->st, c);
         });
-        launch_givens(G, j, raw1, raw2p, nrm, s->st);
+        launch_givens(G, j, raw1, raw2p, s->partial, axpy_norm_blocks(L), s->st);
     };
     constexpr int CHUNK = 8;
     int j = 0;

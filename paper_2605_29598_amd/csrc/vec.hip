@@ -93,22 +93,30 @@ static unsigned stream_grid(int64_t L) {
 }
 
 // ------------------------------------------------------- multi-dot products
-// partial[b][v0 + i] = sum over the block's entries of WJ * V_i * z
-template <typename R, int CH>
+// partial[b][v] = sum over workgroup b's entries of WJ * V_v * z. The vectors
+// split into NG chunks over the wavefronts of one workgroup (4 / NG wavefronts
+// per chunk, at most CH running sums per lane, so the lanes keep full
+// occupancy): every chunk walks the same entries at the same time, so z and the
+// weights come from HBM once and from the compute unit's caches for the other
+// chunks.
+template <typename R, int NG, int CH>
 __global__ void __launch_bounds__(TPB)
-k_dots(int64_t L, int per, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z,
-       const R* __restrict__ WJ, double* __restrict__ partial, int nvtot, const int* __restrict__ ctrl) {
+k_dots(int64_t L, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z, const R* __restrict__ WJ,
+       double* __restrict__ partial, int nvtot, const int* __restrict__ ctrl) {
     if (ctrl && *ctrl != 0) return;
-    // chunk blockIdx.x of the vectors, V_{v0} .. V_{v0 + nv - 1}, over entry range blockIdx.y
-    const int v0 = blockIdx.x * per, nv = nvtot - v0 < per ? nvtot - v0 : per;
+    constexpr int WPG = TPB / 64 / NG;   // wavefronts per chunk
     using VT = typename Vec16<R>::T;
     constexpr int W = Vec16<R>::W;
-    __shared__ double red[(TPB / 64 + 1) * CH];
+    __shared__ double red[TPB / 64][CH];
+    const int ln = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int gi = wid % NG, sub = wid / NG;
+    const int per = (nvtot + NG - 1) / NG, v0 = gi * per;
+    const int nv = nvtot - v0 < per ? nvtot - v0 : per;
     double acc[CH];
 #pragma unroll
     for (int i = 0; i < CH; ++i) acc[i] = 0;
-    const int64_t nvec = L / W;   // ldv and L are multiples of W (checked by the launcher)
-    for (int64_t x = blockIdx.y * (int64_t)TPB + threadIdx.x; x < nvec; x += (int64_t)gridDim.y * TPB) {
+    const int64_t nvec = L / W;   // ldv and L are multiples of W
+    for (int64_t x = (blockIdx.x * (int64_t)WPG + sub) * 64 + ln; x < nvec; x += (int64_t)gridDim.x * WPG * 64) {
         const VT zz = ((const VT*)z)[x], ww = ((const VT*)WJ)[x];
         double wz[W];
 #pragma unroll
@@ -121,24 +129,36 @@ k_dots(int64_t L, int per, const R* __restrict__ V, int64_t ldv, const R* __rest
                 for (int k = 0; k < W; ++k) acc[i] += wz[k] * (double)lane<VT, R>(v, k);
             }
     }
-    block_sum<CH>(acc, red);
-    if (threadIdx.x < nv) partial[(size_t)blockIdx.y * nvtot + v0 + threadIdx.x] = red[TPB / 64 * CH + threadIdx.x];
+#pragma unroll
+    for (int i = 0; i < CH; ++i)
+        for (int off = 32; off > 0; off >>= 1) acc[i] += __shfl_xor(acc[i], off, 64);
+    if (ln == 0)
+#pragma unroll
+        for (int i = 0; i < CH; ++i) red[wid][i] = acc[i];
+    __syncthreads();
+    if (threadIdx.x < nvtot) {
+        const int g = threadIdx.x / per, i = threadIdx.x - g * per;
+        double sum = 0;
+        for (int k = 0; k < WPG; ++k) sum += red[k * NG + g][i];
+        partial[(size_t)blockIdx.x * nvtot + threadIdx.x] = sum;
+    }
 }
 
 template <typename R>
 void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R* WJ, double* partial,
                  double* out, hipStream_t st, const int* ctrl) {
-    // fewer, longer-running workgroups (1024 measured best against 512..4096 on
-    // the 3 M-entry channel basis): the block reduction of up to 16 sums is
-    // amortised over more entries per lane
-    const unsigned g = stream_grid(L) > 1024 ? 1024 : stream_grid(L);
-    // at most 8 running sums per lane (36 VGPRs, full occupancy; measured
-    // faster than 4, 6 and 16 on the channel basis); longer bases are split
-    // into chunks that each re-read z and the weights
-    const int nch = (nv + 7) / 8, per = (nv + nch - 1) / nch;
-    // the chunks of one entry range are consecutive workgroups (grid x), so z
-    // and the weights are re-read close together in time
-    hipLaunchKernelGGL((k_dots<R, 8>), dim3(nch, g), dim3(TPB), 0, st, L, per, V, ldv, z, WJ, partial, nv, ctrl);
+    // grid measured on the 3 M-entry channel basis: 1024 workgroups while a
+    // chunk has 2 or 4 wavefronts, 2048 with one wavefront per chunk
+    const unsigned gmax = nv <= 16 ? 1024 : 2048;
+    const unsigned g = stream_grid(L) > gmax ? gmax : stream_grid(L);
+    if (nv <= 8)
+        hipLaunchKernelGGL((k_dots<R, 1, 8>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl);
+    else if (nv <= 16)
+        hipLaunchKernelGGL((k_dots<R, 2, 8>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl);
+    else if (nv <= 32)
+        hipLaunchKernelGGL((k_dots<R, 4, 8>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl);
+    else   // nv <= MAXV = 33
+        hipLaunchKernelGGL((k_dots<R, 4, 9>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl);
     final_sum(partial, (int)g, nv, out, st, ctrl);
 }
 template void launch_dots<double>(int64_t, int, const double*, int64_t, const double*, const double*, double*,
@@ -246,6 +266,8 @@ k_axpy_norm(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const doubl
     if (threadIdx.x == 0) partial[blockIdx.x] = red[TPB / 64];
 }
 
+int axpy_norm_blocks(int64_t L) { return (int)stream_grid(L); }
+
 template <typename R>
 void launch_axpy_reduce(int64_t L, int nv, const R* V, int64_t ldv, const double* raw, const double* s,
                         const R* z, R* z1, const R* WJ, int mode_norm, double* partial, double* out,
@@ -261,7 +283,7 @@ void launch_axpy_reduce(int64_t L, int nv, const R* V, int64_t ldv, const double
         else
             hipLaunchKernelGGL((k_axpy_norm<R, 32>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
                                partial, ctrl);
-        final_sum(partial, (int)g, 1, out, st, ctrl);
+        if (out) final_sum(partial, (int)g, 1, out, st, ctrl);
         return;
     }
     if (nv <= 8)
@@ -284,56 +306,82 @@ template void launch_axpy_reduce<float>(int64_t, int, const float*, int64_t, con
 
 // ------------------------------------------------- Arnoldi step on the device
 // Column j of the Hessenberg matrix from the Gram-Schmidt projections, the
-// Givens rotations and the residual estimate (Saad, Alg. 6.9), by one thread:
-// the Krylov loop then needs no host round trip per iteration.
-__global__ void k_givens(GState* __restrict__ G, int j, const double* __restrict__ raw,
-                         const double* __restrict__ raw2, const double* __restrict__ nrm) {
-    if (threadIdx.x != 0) return;
-    if (raw2 == nullptr) {
-        if (G->status != 0) return;
+// Givens rotations and the residual estimate (Saad, Alg. 6.9): the Krylov loop
+// then needs no host round trip per iteration. One workgroup: it sums the
+// update's partial norms (same fixed order as the final sums), loads the
+// column and the earlier rotations into LDS in parallel, one lane applies the
+// recurrence, and the column is written back in parallel.
+__global__ void __launch_bounds__(TPB)
+k_givens(GState* __restrict__ G, int j, const double* __restrict__ raw, const double* __restrict__ raw2,
+         const double* __restrict__ npart, int nb) {
+    const int t = threadIdx.x;
+    const int st0 = G->status;
+    if (raw2 == nullptr ? st0 != 0 : st0 != 2) return;
+    __shared__ double red[TPB];
+    __shared__ double col[GM + 1], cs[GM], sn[GM];
+    __shared__ int keep;
+    double sum = 0;
+    for (int b = t; b < nb; b += TPB) sum += npart[b];
+    red[t] = sum;
+    if (t <= j) {
+        double h = G->sv[t] * raw[t];
+        if (raw2) h += G->sv[t] * raw2[t];
+        col[t] = h;
+    }
+    if (t < j) {
+        cs[t] = G->cs[t];
+        sn[t] = G->sn[t];
+    }
+    __syncthreads();
+    for (int off = TPB / 2; off > 0; off >>= 1) {
+        if (t < off) red[t] += red[t + off];
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double nrm = red[0];
         // severe cancellation in the single classical Gram-Schmidt pass: the
         // host runs a second pass and finishes the column
-        if (nrm[0] < 1e-6 * raw[j + 1]) {
+        if (raw2 == nullptr && nrm < 1e-6 * raw[j + 1]) {
             G->status = 2;
-            return;
+            keep = 0;
+        } else {
+            keep = 1;
+            if (raw2) G->status = 0;
+            const double hnext = sqrt(nrm);
+            col[j + 1] = hnext;
+            for (int i = 0; i < j; ++i) {
+                const double a = col[i], b = col[i + 1];
+                col[i] = cs[i] * a + sn[i] * b;
+                col[i + 1] = -sn[i] * a + cs[i] * b;
+            }
+            const double den = hypot(col[j], col[j + 1]);
+            const double c = col[j] / den, s = col[j + 1] / den;
+            G->cs[j] = c;
+            G->sn[j] = s;
+            col[j] = den;
+            col[j + 1] = 0.0;
+            const double gj = G->g[j];
+            G->g[j + 1] = -s * gj;
+            G->g[j] = c * gj;
+            G->k = j + 1;
+            const int its = G->its + 1;
+            G->its = its;
+            if (!isfinite(hnext)) {
+                G->status = 3;
+            } else if (hnext == 0.0 || its >= G->maxit || (!G->fixed && fabs(-s * gj) <= G->tolb)) {
+                G->status = 1;
+            } else {
+                G->sv[j + 1] = 1.0 / hnext;
+                G->svf[j + 1] = (float)(1.0 / hnext);
+            }
         }
-    } else {
-        if (G->status != 2) return;
-        G->status = 0;
     }
-    double* H = G->H;
-    for (int i = 0; i <= j; ++i) {
-        double h = G->sv[i] * raw[i];
-        if (raw2) h += G->sv[i] * raw2[i];
-        H[i * GM + j] = h;
-    }
-    const double hnext = sqrt(nrm[0]);
-    H[(j + 1) * GM + j] = hnext;
-    for (int i = 0; i < j; ++i) {
-        const double t = G->cs[i] * H[i * GM + j] + G->sn[i] * H[(i + 1) * GM + j];
-        H[(i + 1) * GM + j] = -G->sn[i] * H[i * GM + j] + G->cs[i] * H[(i + 1) * GM + j];
-        H[i * GM + j] = t;
-    }
-    const double den = hypot(H[j * GM + j], H[(j + 1) * GM + j]);
-    G->cs[j] = H[j * GM + j] / den;
-    G->sn[j] = H[(j + 1) * GM + j] / den;
-    H[j * GM + j] = den;
-    H[(j + 1) * GM + j] = 0.0;
-    G->g[j + 1] = -G->sn[j] * G->g[j];
-    G->g[j] = G->cs[j] * G->g[j];
-    G->k = j + 1;
-    G->its += 1;
-    if (!isfinite(hnext)) {
-        G->status = 3;
-    } else if (hnext == 0.0 || G->its >= G->maxit || (!G->fixed && fabs(G->g[j + 1]) <= G->tolb)) {
-        G->status = 1;
-    } else {
-        G->sv[j + 1] = 1.0 / hnext;
-        G->svf[j + 1] = (float)G->sv[j + 1];
-    }
+    __syncthreads();
+    if (keep && t <= j + 1) G->H[t * GM + j] = col[t];
 }
-void launch_givens(GState* G, int j, const double* raw, const double* raw2, const double* nrm, hipStream_t st) {
-    hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, G, j, raw, raw2, nrm);
+void launch_givens(GState* G, int j, const double* raw, const double* raw2, const double* npart, int nb,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(TPB), 0, st, G, j, raw, raw2, npart, nb);
 }
 
 // ----------------------------------------------------------- linear combination
