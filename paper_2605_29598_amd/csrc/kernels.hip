@@ -159,6 +159,16 @@ constexpr int threads_of(int N) { return ((epb_of(N) * N * N * N + 63) / 64) * 6
 constexpr int epb_mv(int N) { return epb_of(N); }
 constexpr int threads_mv(int N) { return ((epb_mv(N) * N * N * N + 63) / 64) * 64; }
 
+// Element slot of a lane within its workgroup. With Np = 64 one wavefront
+// holds exactly one element: the slot is then taken from the first lane, which
+// tells the compiler that it is wave-uniform, so per-element values (index,
+// neighbour lists, edge lengths) live in scalar registers.
+template <int NP>
+__device__ __forceinline__ int elem_slot(int tid) {
+    if constexpr (NP == 64) return __builtin_amdgcn_readfirstlane(tid >> 6);
+    else return tid / NP;
+}
+
 // Consecutive workgroups are dispatched round-robin over the 8 XCDs; give
 // every XCD a contiguous run of logical blocks so that neighbouring elements
 // meet in the same L2.
@@ -408,7 +418,7 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
     constexpr int UN = (L_FAST > L_SLOW ? L_FAST : L_SLOW) > L_VOL ? (L_FAST > L_SLOW ? L_FAST : L_SLOW) : L_VOL;
     __shared__ R s_q[EPB][5][NP];
     __shared__ R s_u[EPB][UN];
-    const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
+    const int tid = threadIdx.x, le = elem_slot<NP>(tid), node = tid - le * NP;
     __shared__ Tab<N, R> T;
     load_tab<N, R>(Tg, &T);
     const int64_t slot = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
@@ -596,7 +606,7 @@ k_pass1(const int* __restrict__ elist, int64_t nel, const R* __restrict__ p, con
     __shared__ R s_w[EPB][3][NP];
     __shared__ R s_u[EPB][UN];
     __shared__ int s_kind[EPB][6], s_nbr[EPB][6];
-    const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
+    const int tid = threadIdx.x, le = elem_slot<NP>(tid), node = tid - le * NP;
     __shared__ Tab<N, R> T;
     load_tab<N, R>(Tg, &T);
     const int64_t slot = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
@@ -858,7 +868,7 @@ k_pass2(const int* __restrict__ elist, int64_t nel, const R* __restrict__ Gp, co
     constexpr int L_FACE = SLOW ? 5 * NF : 6 * NF;
     __shared__ R s_face[EPB][L_FACE];
     __shared__ R s_vol[EPB][3][NP];
-    const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
+    const int tid = threadIdx.x, le = elem_slot<NP>(tid), node = tid - le * NP;
     __shared__ Tab<N, R> T;
     load_tab<N, R>(Tg, &T);
     const int64_t slot = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
@@ -1035,7 +1045,7 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
     __shared__ R s_v[AFF ? EPB : 1][NP];   // affine: W detJ sc p for the volume term
     __shared__ Tab<N, R> T;
     load_tab<N, R>(Tg, &T);
-    const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
+    const int tid = threadIdx.x, le = elem_slot<NP>(tid), node = tid - le * NP;
     const int slot = (int)xcd_block(blockIdx.x, gridDim.x) * EPB + le;
     const bool act = le < EPB && slot < nel;
     const int e = act ? (elist ? elist[slot] : slot) : 0;
@@ -1227,7 +1237,7 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
     __shared__ R s_vol[EPB][3][NP];
     __shared__ Tab<N, R> T;
     load_tab<N, R>(Tg, &T);
-    const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
+    const int tid = threadIdx.x, le = elem_slot<NP>(tid), node = tid - le * NP;
     const int slot = (int)xcd_block(blockIdx.x, gridDim.x) * EPB + le;
     const bool act = le < EPB && slot < nel;
     const int e = act ? (elist ? elist[slot] : slot) : 0;
@@ -1413,7 +1423,7 @@ k_lambda(const int* __restrict__ elist, int64_t nel, const double* __restrict__ 
     constexpr int UN = L_FAST > L_SLOW ? L_FAST : L_SLOW;
     __shared__ R s_q[EPB][4][NP];
     __shared__ R s_u[EPB][UN];
-    const int tid = threadIdx.x, le = tid / NP, node = tid - le * NP;
+    const int tid = threadIdx.x, le = elem_slot<NP>(tid), node = tid - le * NP;
     __shared__ Tab<N, R> T;
     load_tab<N, R>(Tg, &T);
     const int64_t slot = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
