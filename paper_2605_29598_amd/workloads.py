@@ -76,7 +76,7 @@ class Workload:
     T0: float                # isothermal temperature or surface potential temperature
     N: float = 0.0
     U: float = 0.0
-    pert: str = "none"       # "gauss" (radius a_p) or "igw" (sin(pi z/H)/(1+(x-xc)^2/a_p^2))
+    pert: str = "none"       # "gauss" (radius a_p), "igw" (sin(pi z/H)/(1+(x-xc)^2/a_p^2)) or "bretherton"
     pert_amp: float = 0.0
     pert_a: float = 1.0
     pert_xc: float = 0.0
@@ -137,6 +137,28 @@ def orography(nx=64, ny=64, nz=24, degree=4, scheme=R2, refined=False):
         seed=3 if not refined else 4)
 
 
+def igw_slice(nx=300, nz=20, degree=4, scheme=R2, planetary=False, dT=0.01):
+    """Inertia-gravity waves of Sec. 4.1 in the vertical-slice form (one
+    periodic element in y, so d/dy = 0 while v stays prognostic): isothermal
+    T0 = 250 K hydrostatic rest state, Bretherton-transformed perturbation
+    T_b = dT exp(-(x - xc)^2 / a^2) sin(pi z / H) with p' = 0, f = 1.03126e-4,
+    periodic in x, walls at the bottom and the top, 300 x 20 elements at r = 4.
+    Reference channel: 6000 x 10 km, a = 100 km, dt = 0.5 s, 8 h. Planetary
+    scale: 60000 x 10 km, a = 1000 km, dt = 10 s, 96 h. The paper does not
+    state dT; 0.01 K is used."""
+    Lx = 60000e3 if planetary else 6000e3
+    a = 1000e3 if planetary else 100e3
+    dt = 10.0 if planetary else 0.5
+    hours = 96.0 if planetary else 8.0
+    return Workload(
+        name="igw_slice%s_%dx%d_r%d" % ("_planetary" if planetary else "", nx, nz, degree),
+        mesh=MeshSpec(Lx, Lx / nx, 10e3, nx, 1, nz, degree),
+        phys=PhysSpec(f=1.03126e-4),
+        num=NumSpec(dt=dt, scheme=scheme),
+        steps=int(round(hours * 3600.0 / dt)), background="isothermal", T0=250.0,
+        pert="bretherton", pert_amp=dT, pert_a=a, pert_xc=Lx / 2)
+
+
 # ------------------------------------------------------------- initial state
 def primitive_background(w: Workload, x, y, z):
     """rho, p of the hydrostatic background at points (x, y, z)."""
@@ -156,13 +178,19 @@ def primitive_background(w: Workload, x, y, z):
 def initial_state(w: Workload, coords):
     """Conserved variables [5][E][Np] at node coordinates coords [3][E][Np].
 
-    The potential-temperature perturbation keeps the pressure and recomputes
-    the density. The optional noise multiplies rho and rho*E by (1 + eps xi)
+    The potential-temperature perturbations keep the pressure and recompute
+    the density; the Bretherton perturbation of Sec. 4.1 adds the linear
+    density perturbation rho' = -exp(-delta z / 2) rho_s T_b / T0 at p' = 0. The optional noise multiplies rho and rho*E by (1 + eps xi)
     and adds eps*xi m/s to each velocity component (xi ~ U[-1, 1) drawn per
     field, element and node in that order from numpy default_rng(seed))."""
     x, y, z = coords
     rho, p = primitive_background(w, x, y, z)
-    if w.pert != "none":
+    if w.pert == "bretherton":
+        delta = GRAV / (RGAS * w.T0)
+        rho_s = P_REF / (RGAS * w.T0)
+        Tb = w.pert_amp * np.exp(-((x - w.pert_xc) / w.pert_a) ** 2) * np.sin(np.pi * z / w.mesh.Lz)
+        rho = rho - np.exp(-0.5 * delta * z) * rho_s * Tb / w.T0
+    elif w.pert != "none":
         if w.pert == "gauss":
             r2 = (x - w.pert_xc) ** 2 + (y - w.pert_yc) ** 2 + (z - w.pert_zc) ** 2
             dth = w.pert_amp * np.exp(-r2 / w.pert_a ** 2)
