@@ -91,6 +91,7 @@ SIGNATURES = {
     "imx_implicit_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(imx_solve_stats)]),
     "imx_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(imx_step_stats)]),
     "imx_total_mass": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
+    "imx_geo_imbalance": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
     "imx_solver_destroy": (None, [_vp]),
     "imx_solver_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
     "imx_solver_timing_report": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -277,6 +278,11 @@ class Solver:
         m = ctypes.c_double()
         check(lib().imx_total_mass(self.h, ctypes.byref(m)), "imx_total_mass")
         return m.value
+
+    def geo_imbalance(self):
+        e = ctypes.c_double()
+        check(lib().imx_geo_imbalance(self.h, ctypes.byref(e)), "imx_geo_imbalance")
+        return e.value
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

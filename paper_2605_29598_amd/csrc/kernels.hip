@@ -1543,6 +1543,73 @@ const void* tab_ptr<double>(const DevMesh& m) { return m.tab; }
 template <>
 const void* tab_ptr<float>(const DevMesh& m) { return m.tabf; }
 
+// =====================================================================
+// Geostrophic imbalance of the x momentum (planetary-scale wave test,
+// Sec. 4.1): per workgroup, sum of W detJ |(1/rho) dp/dx - f v| and of
+// W detJ; dp/dx is the derivative of the element's own pressure polynomial
+// at its nodes, sum_d (d xi_d / d x) sum_m l_m'(xi_i) p_m.
+// =====================================================================
+template <int N>
+__global__ void __launch_bounds__(threads_of(N))
+k_geo(int64_t nel, const double* __restrict__ q, Geom<double> g, const Tab<N, double>* __restrict__ Tg,
+      double gm1, double fcor, double* __restrict__ partial) {
+    using R = double;
+    constexpr int NP = N * N * N, EPB = epb_of(N), NW = threads_of(N) / 64;
+    __shared__ R s_p[EPB][NP];
+    __shared__ R s_red[NW][2];
+    __shared__ Tab<N, R> T;
+    load_tab<N, R>(Tg, &T);
+    const int tid = threadIdx.x, le = elem_slot<NP>(tid), node = tid - le * NP;
+    const size_t fs = (size_t)g.E * NP;
+    const int i = node % N, j = (node / N) % N, k = node / (N * N);
+    R acc0 = 0, acc1 = 0;
+    for (int64_t base = (int64_t)blockIdx.x * EPB; base < nel; base += (int64_t)gridDim.x * EPB) {
+        const int64_t e = base + le;
+        const bool act = le < EPB && e < nel;
+        R rho = 1, v = 0, wj = 0;
+        __syncthreads();   // the previous group's pressure has been read
+        if (act) {
+            const size_t o = (size_t)e * NP + node;
+            rho = q[o];
+            const R m0 = q[fs + o], m1 = q[2 * fs + o], m2 = q[3 * fs + o];
+            s_p[le][node] = gm1 * (q[4 * fs + o] - (R)0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho);
+            v = m1 / rho;
+            wj = g.WJ[o];
+        }
+        __syncthreads();
+        if (act) {
+            const R* P = &s_p[le][0];
+            R dxi[3] = {0, 0, 0};
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                dxi[0] += T.D[i][m] * P[m + N * (j + N * k)];
+                dxi[1] += T.D[j][m] * P[i + N * (m + N * k)];
+                dxi[2] += T.D[k][m] * P[i + N * (j + N * m)];
+            }
+            R dpdx = 0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) dpdx += metric<N, R>(g, e, node, d, 0, wj) * dxi[d];
+            dpdx /= wj;
+            acc0 += wj * fabs(dpdx / rho - (R)fcor * v);
+            acc1 += wj;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        acc0 += __shfl_xor(acc0, off, 64);
+        acc1 += __shfl_xor(acc1, off, 64);
+    }
+    if ((tid & 63) == 0) {
+        s_red[tid >> 6][0] = acc0;
+        s_red[tid >> 6][1] = acc1;
+    }
+    __syncthreads();
+    if (tid < 2) {
+        R t = 0;
+        for (int w = 0; w < NW; ++w) t += s_red[w][tid];
+        partial[(size_t)blockIdx.x * 2 + tid] = t;
+    }
+}
+
 // Launches kern over all elements, or (meshes with hanging faces) the
 // face-by-face instance over the elements owning a coarse hanging face and
 // the all-faces instance over the others.
@@ -1731,6 +1798,22 @@ void launch_lambda(const DevMesh& m, const HostTab&, const StageK& sk, const dou
                      (const Tab<NN, double>*)m.tab, sk)
     IMX_DISPATCH_N(m.n, CALL)
 #undef CALL
+}
+
+int launch_geo(const DevMesh& m, const double* q, double gm1, double fcor, double* partial, int max_blocks,
+               hipStream_t st) {
+    int nb = 0;
+#define CALL(NN)                                                                                          \
+    do {                                                                                                  \
+        const int64_t groups = (m.E + epb_of(NN) - 1) / epb_of(NN);                                      \
+        nb = (int)(groups < max_blocks ? groups : max_blocks);                                            \
+        if (nb < 1) nb = 1;                                                                               \
+        hipLaunchKernelGGL(k_geo<NN>, dim3((unsigned)nb), dim3(threads_of(NN)), 0, st, (int64_t)m.E, q,  \
+                           geom<double>(m), (const Tab<NN, double>*)m.tab, gm1, fcor, partial);          \
+    } while (0)
+    IMX_DISPATCH_N(m.n, CALL)
+#undef CALL
+    return nb;
 }
 
 }  // namespace imx

@@ -176,6 +176,11 @@ void launch_picard_var(int64_t L, const double* p0, const double* u0, const doub
                        hipStream_t st);
 // sum WJ rho (out[0]) and a non-finite flag over the state (out[1] = count)
 void launch_mass(int64_t L, const double* q, const double* WJ, double* partial, double* out, hipStream_t st);
+// Geostrophic imbalance partial sums: partial[b][0] = sum W detJ |(1/rho) dp/dx - f v|,
+// partial[b][1] = sum W detJ over the elements of workgroup b; returns the
+// number of workgroups (at most max_blocks).
+int launch_geo(const DevMesh& m, const double* q, double gm1, double fcor, double* partial, int max_blocks,
+               hipStream_t st);
 
 // conversions / vector helpers
 void launch_d2f(int64_t L, const double* in, float* out, hipStream_t st);

@@ -1041,6 +1041,17 @@ imx_status imx_total_mass(imx_solver* s, double* mass) {
     return IMX_OK;
 }
 
+imx_status imx_geo_imbalance(imx_solver* s, double* egeo) {
+    NEED_BOUND(s);
+    if (!egeo) return IMX_EINVAL;
+    double* bb = s->dsc + imx_solver::S_MISC;
+    const int nb = launch_geo(s->dm, s->y, s->phys.gamma - 1.0, s->phys.f, s->partial, RED_BLOCKS, s->st);
+    launch_final_sum(s->partial, nb, 2, bb, s->st);
+    CHK(sync_read(s, bb, 2));
+    *egeo = s->hsc[0] / s->hsc[1];
+    return IMX_OK;
+}
+
 imx_status imx_solver_timing(imx_solver* s, int enable) {
     NEED_BOUND(s);
     timing_flush(s);
