@@ -186,7 +186,7 @@ imx_status imx_implicit_solve(imx_solver* s, const double* rho_l_dev, const doub
 imx_status imx_step(imx_solver* s, int nsteps, imx_step_stats* stats);
 /* Total mass sum_K int_K rho (binary64); synchronises. */
 imx_status imx_total_mass(imx_solver* s, double* mass);
-/* Geostrophic imbalance of the bound state (eq. egeo, Sec. 4.1, planetary-
+/* Geostrophic imbalance of the bound state (eq. egeo, Sec. 4.2, planetary-
  * scale test): the domain mean int |(1/rho) dp/dx - f v| dV / int dV, with
  * dp/dx the derivative of each element's own pressure polynomial at its
  * nodes and the elements' Gauss-Legendre rule. On a vertical slice (one

@@ -52,7 +52,7 @@ def broken_x_derivative(mesh, f):
 
 def geostrophic_imbalance(mesh, q, f_cor, gamma):
     """Departure from geostrophic balance of the x momentum (eq. egeo,
-    Sec. 4.1, planetary-scale test): the domain mean of |(1/rho) dp/dx - f v|,
+    Sec. 4.2, planetary-scale test): the domain mean of |(1/rho) dp/dx - f v|,
     int |.| dV / int dV with the Gauss-Legendre rule of the elements. On a
     vertical slice (one element in y) this is the paper's area mean over
     x and z; dp/dx is the element-local derivative of the discrete pressure."""

@@ -1545,7 +1545,7 @@ const void* tab_ptr<float>(const DevMesh& m) { return m.tabf; }
 
 // =====================================================================
 // Geostrophic imbalance of the x momentum (planetary-scale wave test,
-// Sec. 4.1): per workgroup, sum of W detJ |(1/rho) dp/dx - f v| and of
+// Sec. 4.2): per workgroup, sum of W detJ |(1/rho) dp/dx - f v| and of
 // W detJ; dp/dx is the derivative of the element's own pressure polynomial
 // at its nodes, sum_d (d xi_d / d x) sum_m l_m'(xi_i) p_m.
 // =====================================================================

@@ -134,13 +134,12 @@ constexpr int MAXV = 33;   // restart length <= 32
 template <typename R>
 void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R* WJ, double* partial,
                  double* out, hipStream_t st, const int* ctrl = nullptr);
-// z1 = z - sum_i c_i V_i with c_i = raw[i]*s[i]^2 ; then out[i] = sum WJ V_i z1 (if dots) or
-// out[0] = sum WJ z1^2 (norm; with out = null the axpy_norm_blocks(L) partial
-// sums are left in partial for the caller)
+// z1 = z - sum_i c_i V_i with c_i = raw[i]*s[i]^2 (z and z1 may be the same
+// array); the partial sums of the squared M-norm sum WJ z1^2 are left in
+// partial[0 .. axpy_norm_blocks(L)) for launch_givens
 template <typename R>
-void launch_axpy_reduce(int64_t L, int nv, const R* V, int64_t ldv, const double* raw, const double* s,
-                        const R* z, R* z1, const R* WJ, int mode_norm, double* partial, double* out,
-                        hipStream_t st, const int* ctrl = nullptr);
+void launch_axpy_norm(int64_t L, int nv, const R* V, int64_t ldv, const double* raw, const double* s, const R* z,
+                      R* z1, const R* WJ, double* partial, hipStream_t st, const int* ctrl = nullptr);
 
 // State of one restarted-GMRES cycle kept on the device (restart length <= GM).
 constexpr int GM = 32;
@@ -158,7 +157,7 @@ struct GState {
 };
 // Column j: raw = first-pass projections <V_i, z> (i <= j) and raw[j+1] = |z|^2;
 // |z1|^2 after the update is the sum of npart[0..nb) (the partials of
-// launch_axpy_reduce in norm mode with out = null, nb = axpy_norm_blocks(L)).
+// launch_axpy_norm, nb = axpy_norm_blocks(L)).
 // raw2 == null: first pass (may set status 2); raw2 != null: finishes a column
 // after the host's second pass.
 void launch_givens(GState* G, int j, const double* raw, const double* raw2, const double* npart, int nb,

@@ -95,7 +95,7 @@ struct imx_solver {
     double t_ms[IMX_K_COUNT] = {}, t_bytes[IMX_K_COUNT] = {};
     int64_t t_count[IMX_K_COUNT] = {};
     // device scalar slots (offsets into dsc)
-    enum { S_RAW1 = 0, S_RAW2 = 64, S_NRM = 128, S_SV = 192, S_COEF = 256, S_MISC = 320, S_N = 384 };
+    enum { S_RAW1 = 0, S_RAW2 = 64, S_COEF = 256, S_MISC = 320, S_N = 384 };
 };
 
 namespace imx {
@@ -374,7 +374,7 @@ static imx_status arnoldi_cycle(imx_solver* s, R* V, const R* WJ, int m, double 
         const int nd = raw2p ? j + 1 : j + 2;   // the second pass needs no |z|^2
         timed(s, IMX_K_DOTS, (nd + 1) * vb, [&] { launch_dots<R>(L, nd, V, L, Vn, WJ, s->partial, raw, s->st, c); });
         timed(s, IMX_K_ORTHO, (j + 4) * vb, [&] {
-            launch_axpy_reduce<R>(L, j + 1, V, L, raw, G->sv, Vn, Vn, WJ, 1, s->partial, nullptr, s->st, c);
+            launch_axpy_norm<R>(L, j + 1, V, L, raw, G->sv, Vn, Vn, WJ, s->partial, s->st, c);
         });
         launch_givens(G, j, raw1, raw2p, s->partial, axpy_norm_blocks(L), s->st);
     };

@@ -166,62 +166,7 @@ template void launch_dots<double>(int64_t, int, const double*, int64_t, const do
 template void launch_dots<float>(int64_t, int, const float*, int64_t, const float*, const float*, double*, double*,
                                  hipStream_t, const int*);
 
-// --------------------------------------------- Gram-Schmidt update (+ reduce)
-// z1 = z - sum_i raw[i] s[i]^2 V_i; then dots of z1 with all V_i (mode 0) or
-// its squared M-norm (mode 1). z and z1 may be the same array.
-template <typename R, int CH>
-__global__ void __launch_bounds__(TPB)
-k_axpy_red(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const double* __restrict__ raw,
-           const double* __restrict__ s, const R* z, R* z1, const R* __restrict__ WJ, int mode_norm,
-           double* __restrict__ partial) {
-    using VT = typename Vec16<R>::T;
-    constexpr int W = Vec16<R>::W;
-    __shared__ double red[(TPB / 64 + 1) * CH];
-    __shared__ double cf[CH];
-    if (threadIdx.x < CH) cf[threadIdx.x] = threadIdx.x < nv ? raw[threadIdx.x] * s[threadIdx.x] * s[threadIdx.x] : 0.0;
-    __syncthreads();
-    double acc[CH];
-#pragma unroll
-    for (int i = 0; i < CH; ++i) acc[i] = 0;
-    const int64_t nvec = L / W;
-    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < nvec; x += (int64_t)gridDim.x * TPB) {
-        VT v[CH];
-        const VT zin = ((const VT*)z)[x];
-        double zz[W];
-#pragma unroll
-        for (int k = 0; k < W; ++k) zz[k] = (double)lane<VT, R>(zin, k);
-#pragma unroll
-        for (int i = 0; i < CH; ++i)
-            if (i < nv) {
-                v[i] = ((const VT*)(V + (int64_t)i * ldv))[x];
-#pragma unroll
-                for (int k = 0; k < W; ++k) zz[k] -= cf[i] * (double)lane<VT, R>(v[i], k);
-            }
-        VT zo;
-#pragma unroll
-        for (int k = 0; k < W; ++k) set_lane<VT, R>(zo, k, (R)zz[k]);
-        ((VT*)z1)[x] = zo;
-        const VT ww = ((const VT*)WJ)[x];
-        if (mode_norm) {
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-                const double zr = (double)lane<VT, R>(zo, k);
-                acc[0] += (double)lane<VT, R>(ww, k) * zr * zr;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < CH; ++i)
-                if (i < nv)
-#pragma unroll
-                    for (int k = 0; k < W; ++k)
-                        acc[i] += (double)lane<VT, R>(ww, k) * (double)lane<VT, R>(zo, k) * (double)lane<VT, R>(v[i], k);
-        }
-    }
-    block_sum<CH>(acc, red);
-    const int nout = mode_norm ? 1 : nv;
-    if (threadIdx.x < nout) partial[(size_t)blockIdx.x * nout + threadIdx.x] = red[TPB / 64 * CH + threadIdx.x];
-}
-
+// --------------------------------------------------- Gram-Schmidt update
 // z1 = z - sum_i raw[i] s[i]^2 V_i and its squared M-norm (no basis vector
 // kept live: one running value per lane)
 template <typename R, int CH>
@@ -269,40 +214,23 @@ k_axpy_norm(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const doubl
 int axpy_norm_blocks(int64_t L) { return (int)stream_grid(L); }
 
 template <typename R>
-void launch_axpy_reduce(int64_t L, int nv, const R* V, int64_t ldv, const double* raw, const double* s,
-                        const R* z, R* z1, const R* WJ, int mode_norm, double* partial, double* out,
-                        hipStream_t st, const int* ctrl) {
+void launch_axpy_norm(int64_t L, int nv, const R* V, int64_t ldv, const double* raw, const double* s, const R* z,
+                      R* z1, const R* WJ, double* partial, hipStream_t st, const int* ctrl) {
     const unsigned g = stream_grid(L);
-    if (mode_norm) {
-        if (nv <= 8)
-            hipLaunchKernelGGL((k_axpy_norm<R, 8>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
-                               partial, ctrl);
-        else if (nv <= 16)
-            hipLaunchKernelGGL((k_axpy_norm<R, 16>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
-                               partial, ctrl);
-        else
-            hipLaunchKernelGGL((k_axpy_norm<R, 32>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
-                               partial, ctrl);
-        if (out) final_sum(partial, (int)g, 1, out, st, ctrl);
-        return;
-    }
     if (nv <= 8)
-        hipLaunchKernelGGL((k_axpy_red<R, 8>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ, mode_norm,
-                           partial);
+        hipLaunchKernelGGL((k_axpy_norm<R, 8>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
+                           partial, ctrl);
     else if (nv <= 16)
-        hipLaunchKernelGGL((k_axpy_red<R, 16>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
-                           mode_norm, partial);
+        hipLaunchKernelGGL((k_axpy_norm<R, 16>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
+                           partial, ctrl);
     else
-        hipLaunchKernelGGL((k_axpy_red<R, 32>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
-                           mode_norm, partial);
-    final_sum(partial, (int)g, mode_norm ? 1 : nv, out, st);
+        hipLaunchKernelGGL((k_axpy_norm<R, 32>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
+                           partial, ctrl);
 }
-template void launch_axpy_reduce<double>(int64_t, int, const double*, int64_t, const double*, const double*,
-                                         const double*, double*, const double*, int, double*, double*,
-                                         hipStream_t, const int*);
-template void launch_axpy_reduce<float>(int64_t, int, const float*, int64_t, const double*, const double*,
-                                        const float*, float*, const float*, int, double*, double*, hipStream_t,
-                                        const int*);
+template void launch_axpy_norm<double>(int64_t, int, const double*, int64_t, const double*, const double*,
+                                       const double*, double*, const double*, double*, hipStream_t, const int*);
+template void launch_axpy_norm<float>(int64_t, int, const float*, int64_t, const double*, const double*,
+                                      const float*, float*, const float*, double*, hipStream_t, const int*);
 
 // ------------------------------------------------- Arnoldi step on the device
 // Column j of the Hessenberg matrix from the Gram-Schmidt projections, the

@@ -1,5 +1,5 @@
 """Long integrations of the vertical-slice inertia-gravity-wave tests of
-Sec. 4.1 on the library, with the geostrophic-imbalance measure (eq. egeo).
+Secs. 4.1 and 4.2 on the library, with the geostrophic-imbalance measure (eq. egeo).
 
     python -m paper_2605_29598_amd.experiments planetary --hours 96
     python -m paper_2605_29598_amd.experiments reference --hours 8

@@ -138,7 +138,7 @@ def orography(nx=64, ny=64, nz=24, degree=4, scheme=R2, refined=False):
 
 
 def igw_slice(nx=300, nz=20, degree=4, scheme=R2, planetary=False, dT=0.01):
-    """Inertia-gravity waves of Sec. 4.1 in the vertical-slice form (one
+    """Inertia-gravity waves of Secs. 4.1 and 4.2 in the vertical-slice form (one
     periodic element in y, so d/dy = 0 while v stays prognostic): isothermal
     T0 = 250 K hydrostatic rest state, Bretherton-transformed perturbation
     T_b = dT exp(-(x - xc)^2 / a^2) sin(pi z / H) with p' = 0, f = 1.03126e-4,

@@ -1,4 +1,4 @@
-"""GPU tests of the vertical-slice inertia-gravity-wave workloads (Sec. 4.1)
+"""GPU tests of the vertical-slice inertia-gravity-wave workloads (Secs. 4.1, 4.2)
 and of the geostrophic-imbalance measure (eq. egeo).
 
 * E_geo of the library against the oracle's on random states, on slice,

@@ -1,4 +1,4 @@
-"""Pins of the oracle's geostrophic-imbalance measure (eq. egeo, Sec. 4.1,
+"""Pins of the oracle's geostrophic-imbalance measure (eq. egeo, Sec. 4.2,
 planetary-scale test) against closed forms.
 
 * p linear in x, constant rho, v linear in z with the sign change of
