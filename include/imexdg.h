@@ -80,11 +80,18 @@ typedef struct {
 /* Physical constants (Sec. 2, Sec. 4) and the optional Rayleigh sponge of
  * Sec. 4.3: lambda(z) = sponge_lambda sin^2(pi/2 (z - zB)/(zT - zB)) for
  * z >= zB, relaxing the momentum towards rho * sponge_u in the explicit
- * (non-stiff) part; sponge_lambda = 0 switches it off. */
+ * (non-stiff) part; sponge_lambda = 0 switches it off.
+ * slice != 0 selects the vertical-slice equations (Sec. 2, eq.
+ * vertical_slice: d/dy = 0, v prognostic) on a mesh with one periodic
+ * element in y, no refinement and flat ground: every step ends with the L2
+ * projection of the state onto fields constant in y (each y-line of nodes
+ * replaced by its Gauss-weighted mean; element integrals and the mass are
+ * unchanged). imx_solver_create fails with IMX_EINVAL on another mesh. */
 typedef struct {
     double gamma, R, g, f;
     double sponge_zB, sponge_zT, sponge_lambda;
     double sponge_u[3];
+    int slice;
 } imx_phys;
 
 /* Solver settings. GMRES(gmres_restart) on the M-preconditioned pressure

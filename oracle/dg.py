@@ -42,6 +42,10 @@ class Phys:
     sponge_zT: float = 1.0
     sponge_lam: float = 0.0
     sponge_u: tuple = (0.0, 0.0, 0.0)
+    # vertical-slice model (Sec. 2, eq. vertical_slice): d/dy = 0 with v
+    # prognostic, on a mesh with one periodic element in y; every step ends
+    # with the projection onto fields constant in y (slice_project)
+    slice: int = 0
 
 
 @dataclass
@@ -514,7 +518,22 @@ def ark2_step(mesh: Mesh, phys: Phys, num: Numerics, y):
         Ys.append(Yl)
         T.append(explicit_residual(mesh, phys, Yl))
     ynew = y + dt * sum(B_W[l] * (T[l][0] + T[l][1]) for l in range(3)) / Mw
+    if phys.slice:
+        ynew = slice_project(mesh, ynew)
     return ynew, stats
+
+
+def slice_project(mesh: Mesh, q):
+    """L2 projection of nodal fields (..., E, Np) onto the functions that are
+    constant in y within each element: the y-lines of nodes are replaced by
+    their Gauss-weighted mean sum_j w_j f_j / sum_j w_j, which is the exact
+    integral mean of the degree-r polynomial in y (so element integrals, and
+    the mass, are unchanged). On a slice mesh this imposes d/dy = 0 of the
+    vertical-slice equations on the discrete state."""
+    n, w = mesh.n, mesh.basis.w
+    g = q.reshape(q.shape[:-1] + (n, n, n))                    # [..., k, j, i]
+    m = np.einsum('...kji,j->...ki', g, w) / w.sum()
+    return np.broadcast_to(m[..., :, None, :], g.shape).reshape(q.shape).copy()
 
 
 def total_mass(mesh: Mesh, q):

@@ -1610,6 +1610,32 @@ k_geo(int64_t nel, const double* __restrict__ q, Geom<double> g, const Tab<N, do
     }
 }
 
+// =====================================================================
+// Vertical-slice model (Sec. 2, eq. vertical_slice): L2 projection onto
+// fields constant in y within each element. One lane per y-line of nodes
+// (field, element, k, i): the line becomes sum_j w_j f_j / sum_j w_j, the
+// exact element mean in y of the degree-r polynomial.
+// =====================================================================
+template <int N>
+__global__ void __launch_bounds__(256)
+k_slice_project(int64_t nlines, double* __restrict__ q, const Tab<N, double>* __restrict__ Tg) {
+    constexpr int NP = N * N * N;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < nlines; t += (int64_t)gridDim.x * 256) {
+        const int64_t fe = t / (N * N);          // field * E + element
+        const int ki = (int)(t - fe * (N * N)), k = ki / N, i = ki - k * N;
+        double* base = q + fe * NP + i + N * N * k;
+        double s = 0, ws = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            s += Tg->w[j] * base[N * j];
+            ws += Tg->w[j];
+        }
+        const double m = s / ws;
+#pragma unroll
+        for (int j = 0; j < N; ++j) base[N * j] = m;
+    }
+}
+
 // Launches kern over all elements, or (meshes with hanging faces) the
 // face-by-face instance over the elements owning a coarse hanging face and
 // the all-faces instance over the others.
@@ -1796,6 +1822,19 @@ void launch_lambda(const DevMesh& m, const HostTab&, const StageK& sk, const dou
 #define CALL(NN)                                                                                    \
     launch_split<NN>(m, k_lambda<NN, false>, k_lambda<NN, true>, st, pk, uk, rho, G0h, Gp, geom<double>(m), \
                      (const Tab<NN, double>*)m.tab, sk)
+    IMX_DISPATCH_N(m.n, CALL)
+#undef CALL
+}
+
+void launch_slice_project(const DevMesh& m, double* q, hipStream_t st) {
+#define CALL(NN)                                                                                         \
+    do {                                                                                                 \
+        const int64_t nl = 5 * m.E * NN * NN;                                                            \
+        int64_t g = (nl + 255) / 256;                                                                    \
+        if (g > 8192) g = 8192;                                                                          \
+        hipLaunchKernelGGL(k_slice_project<NN>, dim3((unsigned)g), dim3(256), 0, st, nl, q,               \
+                           (const Tab<NN, double>*)m.tab);                                              \
+    } while (0)
     IMX_DISPATCH_N(m.n, CALL)
 #undef CALL
 }

@@ -130,16 +130,27 @@ constexpr int RED_BLOCKS = 4096;
 constexpr int MAXV = 33;   // restart length <= 32
 // Krylov vectors are stored with L rounded up to a multiple of 4 (padding is
 // zero and carries zero weight), so the streaming kernels use 16-byte lanes.
+// Source of the weights W detJ of the Krylov inner products: the stored
+// array WJ, or on affine meshes the tensor weight of the node times the
+// element's det J (per-element constants, 8 per element, det J at index 6),
+// which saves one vector read per launch. Entries at and beyond nreal (the
+// padding of the basis) weigh 0.
+struct WSrc {
+    const double* W3 = nullptr;   // null: read the stored array
+    const double* eg = nullptr;
+    int E = 0, np = 0;
+};
 // out[i] = sum WJ * V_i * z  (i < nv), V_i = V + i*ldv, all length L (R = double or float)
 template <typename R>
 void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R* WJ, double* partial,
-                 double* out, hipStream_t st, const int* ctrl = nullptr);
+                 double* out, hipStream_t st, const int* ctrl = nullptr, WSrc ws = WSrc());
 // z1 = z - sum_i c_i V_i with c_i = raw[i]*s[i]^2 (z and z1 may be the same
 // array); the partial sums of the squared M-norm sum WJ z1^2 are left in
 // partial[0 .. axpy_norm_blocks(L)) for launch_givens
 template <typename R>
 void launch_axpy_norm(int64_t L, int nv, const R* V, int64_t ldv, const double* raw, const double* s, const R* z,
-                      R* z1, const R* WJ, double* partial, hipStream_t st, const int* ctrl = nullptr);
+                      R* z1, const R* WJ, double* partial, hipStream_t st, const int* ctrl = nullptr,
+                      WSrc ws = WSrc());
 
 // State of one restarted-GMRES cycle kept on the device (restart length <= GM).
 constexpr int GM = 32;
@@ -180,6 +191,9 @@ void launch_mass(int64_t L, const double* q, const double* WJ, double* partial, 
 // number of workgroups (at most max_blocks).
 int launch_geo(const DevMesh& m, const double* q, double gm1, double fcor, double* partial, int max_blocks,
                hipStream_t st);
+// Vertical-slice model: each y-line of nodes of the 5 fields of q [5][E][Np]
+// replaced by its Gauss-weighted mean (in place)
+void launch_slice_project(const DevMesh& m, double* q, hipStream_t st);
 
 // conversions / vector helpers
 void launch_d2f(int64_t L, const double* in, float* out, hipStream_t st);

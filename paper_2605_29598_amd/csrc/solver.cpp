@@ -82,6 +82,8 @@ struct imx_solver {
     float *rhof = nullptr, *pkf = nullptr, *WJf = nullptr, *Gf = nullptr, *nSf = nullptr, *xf = nullptr;
     double* cr = nullptr;    // 1 / (WJ rho_l) of the current stage
     float* crf = nullptr;
+    double* w3 = nullptr;    // tensor weights w_i w_j w_k of the nodes (Np)
+    WSrc wsrc;               // affine meshes: Krylov weights from w3 and det J instead of WJ
     GState* gst = nullptr;   // device state of the running Krylov cycle
     GState* hgs = nullptr;   // pinned host copies: [0] upload, [1] download
     float* svf = nullptr;   // binary32 copies of the Krylov scales
@@ -143,6 +145,7 @@ static size_t layout(imx_solver* s, char* base) {
     dm.tabf = D(tab_bytes(m.n, 1) / 8 + 1);
     dm.WJ = D(s->Lp);
     dm.eg = D(E * 8);
+    s->w3 = D(Np);
     if (m.deformed) {
         dm.G = D(5 * L);
         dm.nS = D((size_t)E * 10 * Nf);
@@ -372,9 +375,11 @@ static imx_status arnoldi_cycle(imx_solver* s, R* V, const R* WJ, int m, double 
         R* Vn = V + (size_t)(j + 1) * L;
         double* raw = raw2p ? raw2 : raw1;
         const int nd = raw2p ? j + 1 : j + 2;   // the second pass needs no |z|^2
-        timed(s, IMX_K_DOTS, (nd + 1) * vb, [&] { launch_dots<R>(L, nd, V, L, Vn, WJ, s->partial, raw, s->st, c); });
-        timed(s, IMX_K_ORTHO, (j + 4) * vb, [&] {
-            launch_axpy_norm<R>(L, j + 1, V, L, raw, G->sv, Vn, Vn, WJ, s->partial, s->st, c);
+        const double wb = s->wsrc.W3 ? 0.0 : vb;   // the weight vector, unless taken from the tables
+        timed(s, IMX_K_DOTS, nd * vb + wb,
+              [&] { launch_dots<R>(L, nd, V, L, Vn, WJ, s->partial, raw, s->st, c, s->wsrc); });
+        timed(s, IMX_K_ORTHO, (j + 3) * vb + wb, [&] {
+            launch_axpy_norm<R>(L, j + 1, V, L, raw, G->sv, Vn, Vn, WJ, s->partial, s->st, c, s->wsrc);
         });
         launch_givens(G, j, raw1, raw2p, s->partial, axpy_norm_blocks(L), s->st);
     };
@@ -657,6 +662,8 @@ static imx_status one_step(imx_solver* s, imx_step_stats* acc) {
     }
     timed(s, IMX_K_STAGE, (5 + 27 + 5) * (double)L * 8.0,
           [&] { launch_final_update(L, s->y, s->fN, s->fS, TAB.b, dt, s->y, s->st); });
+    if (s->phys.slice)
+        timed(s, IMX_K_STAGE, 10 * (double)L * 8.0, [&] { launch_slice_project(s->dm, s->y, s->st); });
     double* bb = s->dsc + imx_solver::S_MISC;
     timed(s, IMX_K_REDUCE, 6 * (double)L * 8.0, [&] { launch_mass(L, s->y, s->dm.WJ, s->partial, bb, s->st); });
     CHK(sync_read(s, bb, 2));
@@ -731,6 +738,14 @@ imx_status imx_solver_create(const imx_mesh* mesh, const imx_phys* phys, const i
         return IMX_EINVAL;
     }
     CHK(validate_num(*num));
+    if (phys->slice) {
+        const imx_mesh_desc& d = mesh->m.desc;
+        if (d.ny != 1 || !d.periodic_y || mesh->m.nh != 0 || mesh->m.deformed) {
+            set_error("imx_solver_create: the slice model needs one periodic element in y, no refinement and flat "
+                      "ground");
+            return IMX_EINVAL;
+        }
+    }
     imx_solver* s = new (std::nothrow) imx_solver;
     if (!s) return IMX_ENOMEM;
     s->mesh = &mesh->m;
@@ -844,6 +859,22 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
         q[7] = 1.0 / q[6];
     }
     CHK(up(s->dm.eg, eg.data(), eg.size() * sizeof(double)));
+    {
+        // the same products as the host geometry's W detJ = (w_i w_j w_k) det J
+        const int n = m.n;
+        std::vector<double> w3((size_t)s->Np);
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) w3[i + n * (j + n * k)] = s->tab.w[i] * s->tab.w[j] * s->tab.w[k];
+        CHK(up(s->w3, w3.data(), w3.size() * sizeof(double)));
+        s->wsrc = WSrc();
+        if (!m.deformed) {
+            s->wsrc.W3 = s->w3;
+            s->wsrc.eg = s->dm.eg;
+            s->wsrc.E = (int)s->E;
+            s->wsrc.np = s->Np;
+        }
+    }
     std::vector<char> tabimg(tab_bytes(m.n, 0)), tabimgf(tab_bytes(m.n, 1));
     fill_tab(s->tab, 0, tabimg.data());
     fill_tab(s->tab, 1, tabimgf.data());

@@ -92,6 +92,50 @@ static unsigned stream_grid(int64_t L) {
     return (unsigned)g;
 }
 
+// W detJ from the tables (affine meshes) for the entries a lane visits: the
+// element e and node n of its first entry are advanced by the grid stride
+// (de elements and dn nodes) instead of dividing every index by Np. The
+// binary32 weights are the rounded binary64 products, as in the stored array.
+struct TabWalk {
+    int e, n, de, dn;
+    __device__ __forceinline__ TabWalk(const WSrc& ws, int64_t idx0, int64_t stride) {
+        e = (int)(idx0 / ws.np);
+        n = (int)(idx0 - (int64_t)e * ws.np);
+        de = (int)(stride / ws.np);
+        dn = (int)(stride - (int64_t)de * ws.np);
+    }
+    __device__ __forceinline__ void advance(int np) {
+        n += dn;
+        e += de;
+        if (n >= np) {
+            n -= np;
+            ++e;
+        }
+    }
+};
+
+// the W lanes' weights of 16-byte lane x (TABW: from the tables)
+template <typename R, typename VT, int W, bool TABW>
+__device__ __forceinline__ void lane_weights(const R* WJ, const WSrc& ws, const TabWalk& tw, int64_t x, double* wv) {
+    if constexpr (TABW) {
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            int e = tw.e, n = tw.n + k;
+            if (n >= ws.np) {   // Np > W: at most one wrap
+                n -= ws.np;
+                ++e;
+            }
+            const int ec = e < ws.E ? e : ws.E - 1;   // padding entries: load in bounds, weigh 0
+            const double v = (double)(R)(ws.W3[n] * ws.eg[8 * (int64_t)ec + 6]);
+            wv[k] = e < ws.E ? v : 0.0;
+        }
+    } else {
+        const VT ww = ((const VT*)WJ)[x];
+#pragma unroll
+        for (int k = 0; k < W; ++k) wv[k] = (double)lane<VT, R>(ww, k);
+    }
+}
+
 // ------------------------------------------------------- multi-dot products
 // partial[b][v] = sum over workgroup b's entries of WJ * V_v * z. The vectors
 // split into NG chunks over the wavefronts of one workgroup (4 / NG wavefronts
@@ -99,10 +143,10 @@ static unsigned stream_grid(int64_t L) {
 // occupancy): every chunk walks the same entries at the same time, so z and the
 // weights come from HBM once and from the compute unit's caches for the other
 // chunks.
-template <typename R, int NG, int CH>
+template <typename R, int NG, int CH, bool TABW>
 __global__ void __launch_bounds__(TPB)
 k_dots(int64_t L, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z, const R* __restrict__ WJ,
-       double* __restrict__ partial, int nvtot, const int* __restrict__ ctrl) {
+       double* __restrict__ partial, int nvtot, const int* __restrict__ ctrl, WSrc ws) {
     if (ctrl && *ctrl != 0) return;
     constexpr int WPG = TPB / 64 / NG;   // wavefronts per chunk
     using VT = typename Vec16<R>::T;
@@ -116,11 +160,15 @@ k_dots(int64_t L, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z,
 #pragma unroll
     for (int i = 0; i < CH; ++i) acc[i] = 0;
     const int64_t nvec = L / W;   // ldv and L are multiples of W
-    for (int64_t x = (blockIdx.x * (int64_t)WPG + sub) * 64 + ln; x < nvec; x += (int64_t)gridDim.x * WPG * 64) {
-        const VT zz = ((const VT*)z)[x], ww = ((const VT*)WJ)[x];
+    const int64_t x0 = (blockIdx.x * (int64_t)WPG + sub) * 64 + ln, xs = (int64_t)gridDim.x * WPG * 64;
+    TabWalk tw(ws, TABW ? x0 * W : 0, TABW ? xs * W : 0);
+    for (int64_t x = x0; x < nvec; x += xs) {
+        const VT zz = ((const VT*)z)[x];
         double wz[W];
+        lane_weights<R, VT, W, TABW>(WJ, ws, tw, x, wz);
+        if constexpr (TABW) tw.advance(ws.np);
 #pragma unroll
-        for (int k = 0; k < W; ++k) wz[k] = (double)lane<VT, R>(ww, k) * (double)lane<VT, R>(zz, k);
+        for (int k = 0; k < W; ++k) wz[k] *= (double)lane<VT, R>(zz, k);
 #pragma unroll
         for (int i = 0; i < CH; ++i)
             if (i < nv) {
@@ -144,36 +192,49 @@ k_dots(int64_t L, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z,
     }
 }
 
+template <typename R, bool TABW>
+static void dots_launch(unsigned g, int nv, int64_t L, const R* V, int64_t ldv, const R* z, const R* WJ,
+                        double* partial, hipStream_t st, const int* ctrl, const WSrc& ws) {
+    if (nv <= 8)
+        hipLaunchKernelGGL((k_dots<R, 1, 8, TABW>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl,
+                           ws);
+    else if (nv <= 16)
+        hipLaunchKernelGGL((k_dots<R, 2, 8, TABW>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl,
+                           ws);
+    else if (nv <= 32)
+        hipLaunchKernelGGL((k_dots<R, 4, 8, TABW>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl,
+                           ws);
+    else   // nv <= MAXV = 33
+        hipLaunchKernelGGL((k_dots<R, 4, 9, TABW>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl,
+                           ws);
+}
+
 template <typename R>
 void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R* WJ, double* partial,
-                 double* out, hipStream_t st, const int* ctrl) {
+                 double* out, hipStream_t st, const int* ctrl, WSrc ws) {
     // grid measured on the 3 M-entry channel basis: 1024 workgroups while a
     // chunk has 2 or 4 wavefronts, 2048 with one wavefront per chunk
     const unsigned gmax = nv <= 16 ? 1024 : 2048;
     const unsigned g = stream_grid(L) > gmax ? gmax : stream_grid(L);
-    if (nv <= 8)
-        hipLaunchKernelGGL((k_dots<R, 1, 8>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl);
-    else if (nv <= 16)
-        hipLaunchKernelGGL((k_dots<R, 2, 8>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl);
-    else if (nv <= 32)
-        hipLaunchKernelGGL((k_dots<R, 4, 8>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl);
-    else   // nv <= MAXV = 33
-        hipLaunchKernelGGL((k_dots<R, 4, 9>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl);
+    if (ws.W3)
+        dots_launch<R, true>(g, nv, L, V, ldv, z, WJ, partial, st, ctrl, ws);
+    else
+        dots_launch<R, false>(g, nv, L, V, ldv, z, WJ, partial, st, ctrl, ws);
     final_sum(partial, (int)g, nv, out, st, ctrl);
 }
 template void launch_dots<double>(int64_t, int, const double*, int64_t, const double*, const double*, double*,
-                                  double*, hipStream_t, const int*);
+                                  double*, hipStream_t, const int*, WSrc);
 template void launch_dots<float>(int64_t, int, const float*, int64_t, const float*, const float*, double*, double*,
-                                 hipStream_t, const int*);
+                                 hipStream_t, const int*, WSrc);
 
 // --------------------------------------------------- Gram-Schmidt update
 // z1 = z - sum_i raw[i] s[i]^2 V_i and its squared M-norm (no basis vector
 // kept live: one running value per lane)
-template <typename R, int CH>
+template <typename R, int CH, bool TABW>
 __global__ void __launch_bounds__(TPB)
 k_axpy_norm(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const double* __restrict__ raw,
             const double* __restrict__ s, const R* z, R* z1, const R* __restrict__ WJ, double* __restrict__ partial,
-            const int* __restrict__ ctrl) {
+            const int* __restrict__ ctrl, WSrc ws) {
     if (ctrl && *ctrl != 0) return;
     using VT = typename Vec16<R>::T;
     constexpr int W = Vec16<R>::W;
@@ -183,7 +244,9 @@ k_axpy_norm(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const doubl
     __syncthreads();
     double acc[1] = {0.0};
     const int64_t nvec = L / W;
-    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < nvec; x += (int64_t)gridDim.x * TPB) {
+    const int64_t x0 = blockIdx.x * (int64_t)TPB + threadIdx.x, xs = (int64_t)gridDim.x * TPB;
+    TabWalk tw(ws, TABW ? x0 * W : 0, TABW ? xs * W : 0);
+    for (int64_t x = x0; x < nvec; x += xs) {
         const VT zin = ((const VT*)z)[x];
         double zz[W];
 #pragma unroll
@@ -200,11 +263,13 @@ k_axpy_norm(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const doubl
 #pragma unroll
         for (int k = 0; k < W; ++k) set_lane<VT, R>(zo, k, (R)zz[k]);
         ((VT*)z1)[x] = zo;
-        const VT ww = ((const VT*)WJ)[x];
+        double wv[W];
+        lane_weights<R, VT, W, TABW>(WJ, ws, tw, x, wv);
+        if constexpr (TABW) tw.advance(ws.np);
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             const double zr = (double)lane<VT, R>(zo, k);
-            acc[0] += (double)lane<VT, R>(ww, k) * zr * zr;
+            acc[0] += wv[k] * zr * zr;
         }
     }
     block_sum<1>(acc, red);
@@ -213,24 +278,34 @@ k_axpy_norm(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const doubl
 
 int axpy_norm_blocks(int64_t L) { return (int)stream_grid(L); }
 
+template <typename R, bool TABW>
+static void axpy_norm_launch(unsigned g, int64_t L, int nv, const R* V, int64_t ldv, const double* raw,
+                             const double* s, const R* z, R* z1, const R* WJ, double* partial, hipStream_t st,
+                             const int* ctrl, const WSrc& ws) {
+    if (nv <= 8)
+        hipLaunchKernelGGL((k_axpy_norm<R, 8, TABW>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
+                           partial, ctrl, ws);
+    else if (nv <= 16)
+        hipLaunchKernelGGL((k_axpy_norm<R, 16, TABW>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
+                           partial, ctrl, ws);
+    else
+        hipLaunchKernelGGL((k_axpy_norm<R, 32, TABW>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
+                           partial, ctrl, ws);
+}
+
 template <typename R>
 void launch_axpy_norm(int64_t L, int nv, const R* V, int64_t ldv, const double* raw, const double* s, const R* z,
-                      R* z1, const R* WJ, double* partial, hipStream_t st, const int* ctrl) {
+                      R* z1, const R* WJ, double* partial, hipStream_t st, const int* ctrl, WSrc ws) {
     const unsigned g = stream_grid(L);
-    if (nv <= 8)
-        hipLaunchKernelGGL((k_axpy_norm<R, 8>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
-                           partial, ctrl);
-    else if (nv <= 16)
-        hipLaunchKernelGGL((k_axpy_norm<R, 16>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
-                           partial, ctrl);
+    if (ws.W3)
+        axpy_norm_launch<R, true>(g, L, nv, V, ldv, raw, s, z, z1, WJ, partial, st, ctrl, ws);
     else
-        hipLaunchKernelGGL((k_axpy_norm<R, 32>), dim3(g), dim3(TPB), 0, st, L, nv, V, ldv, raw, s, z, z1, WJ,
-                           partial, ctrl);
+        axpy_norm_launch<R, false>(g, L, nv, V, ldv, raw, s, z, z1, WJ, partial, st, ctrl, ws);
 }
 template void launch_axpy_norm<double>(int64_t, int, const double*, int64_t, const double*, const double*,
-                                       const double*, double*, const double*, double*, hipStream_t, const int*);
+                                       const double*, double*, const double*, double*, hipStream_t, const int*, WSrc);
 template void launch_axpy_norm<float>(int64_t, int, const float*, int64_t, const double*, const double*,
-                                      const float*, float*, const float*, double*, hipStream_t, const int*);
+                                      const float*, float*, const float*, double*, hipStream_t, const int*, WSrc);
 
 // ------------------------------------------------- Arnoldi step on the device
 // Column j of the Hessenberg matrix from the Gram-Schmidt projections, the

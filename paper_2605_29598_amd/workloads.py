@@ -51,6 +51,7 @@ class PhysSpec:
     sponge_zT: float = 1.0
     sponge_lam: float = 0.0
     sponge_u: tuple = (0.0, 0.0, 0.0)
+    slice: int = 0           # vertical-slice equations (one periodic element in y)
 
 
 @dataclass
@@ -139,7 +140,8 @@ def orography(nx=64, ny=64, nz=24, degree=4, scheme=R2, refined=False):
 
 def igw_slice(nx=300, nz=20, degree=4, scheme=R2, planetary=False, dT=0.01):
     """Inertia-gravity waves of Secs. 4.1 and 4.2 in the vertical-slice form (one
-    periodic element in y, so d/dy = 0 while v stays prognostic): isothermal
+    periodic element in y and the slice model, so d/dy = 0 while v stays
+    prognostic): isothermal
     T0 = 250 K hydrostatic rest state, Bretherton-transformed perturbation
     T_b = dT exp(-(x - xc)^2 / a^2) sin(pi z / H) with p' = 0, f = 1.03126e-4,
     periodic in x, walls at the bottom and the top, 300 x 20 elements at r = 4.
@@ -153,7 +155,7 @@ def igw_slice(nx=300, nz=20, degree=4, scheme=R2, planetary=False, dT=0.01):
     return Workload(
         name="igw_slice%s_%dx%d_r%d" % ("_planetary" if planetary else "", nx, nz, degree),
         mesh=MeshSpec(Lx, Lx / nx, 10e3, nx, 1, nz, degree),
-        phys=PhysSpec(f=1.03126e-4),
+        phys=PhysSpec(f=1.03126e-4, slice=1),
         num=NumSpec(dt=dt, scheme=scheme),
         steps=int(round(hours * 3600.0 / dt)), background="isothermal", T0=250.0,
         pert="bretherton", pert_amp=dT, pert_a=a, pert_xc=Lx / 2)

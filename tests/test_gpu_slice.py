@@ -4,7 +4,8 @@ and of the geostrophic-imbalance measure (eq. egeo).
 * E_geo of the library against the oracle's on random states, on slice,
   terrain-following, hanging-face and ragged meshes (FP64 bar).
 * ARK2 steps of the reference and planetary-scale slices (one periodic
-  element in y, walls at the bottom and the top) against the oracle.
+  element in y, walls at the bottom and the top, the slice model's
+  projection onto y-constant fields after every step) against the oracle.
 * The hydrostatic rest state has no imbalance; after the first hour of the
   planetary-scale run (dT = 0.01 K) the imbalance is nonzero and below the
   1e-7 m s^-2 the paper reports for the whole run.
@@ -76,6 +77,10 @@ def test_slice_steps_match_oracle(planetary, scheme):
         assert np.abs(got[t] - y[t]).max() < 1e-12 * sc[t], (t, np.abs(got[t] - y[t]).max() / sc[t])
     # the perturbation has moved the state: the comparison is not of y0 with itself
     assert np.abs(y[3]).max() > 0
+    # slice model: the state after a step is constant along every y-line of nodes
+    n = w.mesh.degree + 1
+    g = got.reshape(5, om.E, n, n, n)
+    assert (g == g[:, :, :, :1, :]).all()
 
 
 def test_planetary_slice_first_hour_balance():

@@ -80,3 +80,18 @@ def test_invalid_meshes_rejected():
         B.Mesh(W.MeshSpec(4e3, 4e3, 2e3, 2, 2, 2, 5))
     with pytest.raises(B.IMXError):
         B.Mesh(W.MeshSpec(4e3, 4e3, 2e3, 0, 2, 2, 2))
+
+
+def test_slice_model_needs_a_slice_mesh():
+    """The vertical-slice model is refused on a mesh with two elements in y
+    (the check runs on the host before any device call)."""
+    B = _binding()
+    num = B.num_struct(W.NumSpec())
+    for spec in (W.MeshSpec(4e3, 4e3, 2e3, 2, 2, 2, 2),
+                 W.MeshSpec(4e3, 4e3, 2e3, 2, 1, 2, 2, periodic_y=0),
+                 W.MeshSpec(8e3, 8e3, 4e3, 3, 1, 2, 2, terrain=W.GAUSS, h0=300, a=2e3, xc=4e3, yc=4e3)):
+        m = B.Mesh(spec)
+        ph = B.phys_struct(W.PhysSpec(slice=1))
+        out = ctypes.c_void_p()
+        code = B.lib().imx_solver_create(m.h, ctypes.byref(ph), ctypes.byref(num), None, ctypes.byref(out))
+        assert code == B.IMX_EINVAL and b"slice" in B.lib().imx_last_error()

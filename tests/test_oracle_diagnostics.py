@@ -68,3 +68,30 @@ def test_sinusoid_converges():
     q = _state(np.full_like(x, rho0), np.zeros((3,) + x.shape), 1e5 + A * np.sin(k * x))
     exact = 2 * A * k / (math.pi * rho0)
     assert abs(geostrophic_imbalance(mesh, q, F, W.GAMMA) - exact) < 1e-5 * exact
+
+
+# ----------------------------------------------------- vertical-slice projection
+def test_slice_projection_closed_forms():
+    """The projection onto y-constant fields (vertical-slice model, Sec. 2):
+    a y-invariant field is unchanged up to rounding, the result is constant
+    along every y-line of nodes, a field polynomial in y of degree <= r is
+    replaced by its exact element mean in y, and the mass is unchanged."""
+    from oracle import dg
+    r = 4
+    Lx, Ly, Lz = 30e3, 20e3, 10e3
+    mesh = Mesh(MeshDesc(Lx, Ly, Lz, 3, 1, 2, r))
+    x, y, z = mesh.node_coords()
+    f0 = np.sin(x / 7e3) + z / Lz
+    q = np.stack([f0] * 5)
+    assert np.abs(dg.slice_project(mesh, q) - q).max() < 4e-16 * np.abs(q).max()
+    g = dg.slice_project(mesh, q + np.sin(y / 3e3)).reshape(5, mesh.E, r + 1, r + 1, r + 1)
+    assert (g == g[:, :, :, :1, :]).all()            # the same value on every y-line node
+    t = y / Ly                                       # one element in y: t in (0, 1)
+    fy = f0 * (1.0 + 3.0 * t ** 4 - 2.0 * t)         # degree 4 in y: mean factor 1 + 3/5 - 1
+    got = dg.slice_project(mesh, fy[None])[0]
+    assert np.abs(got - f0 * 0.6).max() < 1e-13 * np.abs(f0).max()
+    # rho: mass unchanged
+    rho = 1.0 + 0.3 * np.cos(2 * np.pi * t) * np.exp(-z / 5e3)
+    qq = W.conserved_from_primitive(rho, np.zeros((3,) + x.shape), 1e5 + 0 * x)
+    assert abs(dg.total_mass(mesh, dg.slice_project(mesh, qq)) - dg.total_mass(mesh, qq)) \
+        < 1e-14 * dg.total_mass(mesh, qq)
