@@ -8,7 +8,8 @@ Secs. 4.1 and 4.2 on the library, with the geostrophic-imbalance measure (eq. eg
 96 h and reports an imbalance below 1e-7 m s^-2). `reference`: 6000 x 10 km,
 a = 100 km, dt = 0.5 s, 8 h. Both on 300 x 20 elements at r = 4 with one
 periodic element in y. One JSON line per reporting interval (model time,
-imbalance, relative mass change, iterations and wall time per step) and a
+imbalance, relative mass change, largest velocity components, iterations
+and wall time per step) and a
 summary line at the end. A run can be continued from a saved state
 (--load / --save: a .npy file of the conserved state, the step count in a
 sidecar .json).
@@ -56,8 +57,11 @@ def run(kind, hours, every_hours, scheme, precision, load=None, save=None, out=s
         dt_wall = time.perf_counter() - t0
         wall += dt_wall
         done += n
+        q = sol.get_state().cpu().numpy()
         rec = {"t_h": (step0 + done) * w.num.dt / 3600.0, "egeo": sol.geo_imbalance(),
                "mass_rel": (sol.total_mass() - mass0) / mass0,
+               "max_abs_u": float(np.abs(q[1] / q[0]).max()), "max_abs_v": float(np.abs(q[2] / q[0]).max()),
+               "max_abs_w": float(np.abs(q[3] / q[0]).max()),
                "picard_per_step": st.picard_iters / n, "gmres_per_step": st.gmres_iters / n,
                "ms_per_step": 1e3 * dt_wall / n}
         series.append(rec)
