@@ -159,6 +159,18 @@ imx_status imx_solver_workspace_bytes(const imx_solver* s, size_t* bytes);
 imx_status imx_solver_bind_workspace(imx_solver* s, void* dev_ptr, size_t bytes);
 /* Changes dt / tolerances / scheme / precision of a bound solver. */
 imx_status imx_solver_set_numerics(imx_solver* s, const imx_numerics* num);
+/* Replay of the Krylov loop from HIP graphs (default off). Each chunk of up to
+ * 8 GMRES columns (matrix-vector product, Gram-Schmidt pass, Givens step per
+ * column; Sec. 3, the pressure system's GMRES) is a fixed launch sequence: it
+ * is captured once per solver and argument set on a private stream of the
+ * solver and then replayed on the solver's stream with one launch. Results
+ * are bitwise those of direct launches. enable = 0 launches every kernel
+ * directly and frees the captured graphs. Kernel timing (imx_solver_timing)
+ * always launches directly. For callers that drive many small solvers from
+ * few host threads; on a single MI355X the replay measured the same step
+ * times as direct launches (the time between dependent kernels is spent on
+ * the device, not in the launch calls). */
+imx_status imx_solver_set_graphs(imx_solver* s, int enable);
 
 /* Copies the conserved state [5][E][Np] (device) into / out of the solver. */
 imx_status imx_set_state(imx_solver* s, const double* q_dev);

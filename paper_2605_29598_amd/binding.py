@@ -92,6 +92,7 @@ SIGNATURES = {
     "imx_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(imx_step_stats)]),
     "imx_total_mass": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
     "imx_geo_imbalance": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
+    "imx_solver_set_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
     "imx_solver_destroy": (None, [_vp]),
     "imx_solver_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
     "imx_solver_timing_report": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -279,6 +280,9 @@ class Solver:
         m = ctypes.c_double()
         check(lib().imx_total_mass(self.h, ctypes.byref(m)), "imx_total_mass")
         return m.value
+
+    def set_graphs(self, enable):
+        check(lib().imx_solver_set_graphs(self.h, int(bool(enable))), "imx_solver_set_graphs")
 
     def geo_imbalance(self):
         e = ctypes.c_double()

@@ -34,6 +34,35 @@ void set_error(const std::string& msg) { g_err = msg; }
         if (s_ != IMX_OK) return s_;      \
     } while (0)
 
+// Key of a captured chunk of Krylov columns: everything its launches take by
+// value or point at, zero-filled first so that two keys compare bytewise.
+struct ChunkKey {
+    int prec;                  // 0: binary64 Krylov loop, 1: binary32 inner loop
+    int j0, jend, scheme;
+    const void *V, *WJ, *a, *b, *c;   // basis, weights, matvec stage buffers
+    double c_dt, beta, gamma, g, hfac, igm1, rot_si;
+};
+static ChunkKey chunk_key(int prec, const void* V, const void* WJ, const void* a, const void* b, const void* c,
+                          const StageK& k) {
+    ChunkKey key;
+    std::memset(&key, 0, sizeof(key));
+    key.prec = prec;
+    key.scheme = k.scheme;
+    key.V = V;
+    key.WJ = WJ;
+    key.a = a;
+    key.b = b;
+    key.c = c;
+    key.c_dt = k.c_dt;
+    key.beta = k.beta;
+    key.gamma = k.gamma;
+    key.g = k.g;
+    key.hfac = k.hfac;
+    key.igm1 = k.igm1;
+    key.rot_si = k.rot_si;
+    return key;
+}
+
 // Butcher tableaux of Sec. 3 (explicit / implicit), chi = 2 - sqrt(2), a32 = 1/2.
 struct Tableau {
     double a[3][3], at[3][3], b[3];
@@ -86,9 +115,12 @@ struct imx_solver {
     WSrc wsrc;               // affine meshes: Krylov weights from w3 and det J instead of WJ
     GState* gst = nullptr;   // device state of the running Krylov cycle
     GState* hgs = nullptr;   // pinned host copies: [0] upload, [1] download
-    float* svf = nullptr;   // binary32 copies of the Krylov scales
     // pinned host scalars
     double* hsc = nullptr;
+    // captured Krylov chunks (imx_solver_set_graphs): replayed on st, captured on cst
+    bool graphs = false;
+    hipStream_t cst = nullptr;
+    std::vector<std::pair<ChunkKey, hipGraphExec_t>> chunk_graphs;
     // kernel timing (imx_solver_timing)
     bool timing = false;
     struct TRec { int kind; hipEvent_t a, b; double bytes; };
@@ -193,7 +225,6 @@ static size_t layout(imx_solver* s, char* base) {
         s->pkf = F(L);
         s->xf = F(s->Lp);
         s->WJf = F(s->Lp);
-        s->svf = F(64);
         s->crf = F(L);
         dm.WJf = s->WJf;
         if (m.deformed) {
@@ -343,17 +374,58 @@ struct GmresOut {
     double relres = 0.0;
 };
 
+static void drop_chunk_graphs(imx_solver* s) {
+    for (auto& e : s->chunk_graphs) (void)hipGraphExecDestroy(e.second);
+    s->chunk_graphs.clear();
+}
+
+// The replayable graph of one chunk of Krylov columns: looked up by key, else
+// captured from `body` on the solver's capture stream (thread-local capture, so
+// other solvers' threads are not affected) and instantiated.
+template <typename F>
+static imx_status chunk_graph(imx_solver* s, const ChunkKey& key, F&& body, hipGraphExec_t& ex) {
+    for (auto& e : s->chunk_graphs)
+        if (std::memcmp(&e.first, &key, sizeof(ChunkKey)) == 0) {
+            ex = e.second;
+            return IMX_OK;
+        }
+    if (s->chunk_graphs.size() >= 128) drop_chunk_graphs(s);
+    if (!s->cst) HIPCHK(hipStreamCreateWithFlags(&s->cst, hipStreamNonBlocking));
+    hipStream_t run = s->st;
+    s->st = s->cst;
+    hipError_t e = hipStreamBeginCapture(s->cst, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) body();
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(s->cst, &g) : e;
+    s->st = run;
+    if (e2 != hipSuccess) {
+        set_error(std::string("Krylov chunk capture: ") + hipGetErrorString(e2));
+        return IMX_EHIP;
+    }
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        set_error(std::string("Krylov chunk instantiation: ") + hipGetErrorString(e));
+        return IMX_EHIP;
+    }
+    s->chunk_graphs.emplace_back(key, ex);
+    return IMX_OK;
+}
+
 // One cycle of GMRES(m) on the device (Saad, Alg. 6.9) from V_0 = r0 (unscaled,
 // |r0|_M = beta): for each column the matrix-vector product, one classical
 // Gram-Schmidt pass (projections and |z|^2 in one read of the basis, then the
-// update and |z1|^2), and the Givens step in a one-thread kernel. The host
-// queues the columns in chunks and reads the cycle state once per chunk;
-// kernels of a cycle that has stopped return at once. A column with severe
-// cancellation (|z1|^2 < 1e-6 |z|^2) stops the chunk and gets a second pass
-// from the host. `mv(j, x, xs_d, xs_f, out, ctrl)` queues out = A (xs x).
+// update and |z1|^2), and the Givens step in one workgroup. The host queues
+// the columns in chunks and reads the cycle state once per chunk; kernels of
+// a cycle that has stopped return at once. A column with severe cancellation
+// (|z1|^2 < 1e-6 |z|^2) stops the chunk and gets a second pass from the host.
+// `mv(j, x, xs_d, xs_f, out, ctrl)` queues out = A (xs x). With `key` (and
+// graphs on, kernel timing off) each chunk's launches are captured once into
+// a HIP graph and replayed: the chunk is a fixed launch sequence whose
+// arguments the key lists, and its kernels read the stop flag on the device.
 template <typename R, typename MV>
 static imx_status arnoldi_cycle(imx_solver* s, R* V, const R* WJ, int m, double beta, double tolb, int its0,
-                                int maxit, bool fixed, MV&& mv, const GState*& out) {
+                                int maxit, bool fixed, MV&& mv, const GState*& out, const ChunkKey* key = nullptr) {
     const int64_t L = s->Lp;
     GState* G = s->gst;
     GState* up = s->hgs;
@@ -387,9 +459,21 @@ static imx_status arnoldi_cycle(imx_solver* s, R* V, const R* WJ, int m, double 
     int j = 0;
     while (j < m) {
         const int jend = std::min(m, j + CHUNK);
-        for (int jj = j; jj < jend; ++jj) {
-            mv(jj, V + (size_t)jj * L, &G->sv[jj], &G->svf[jj], V + (size_t)(jj + 1) * L, ctrl);
-            column(jj, nullptr, ctrl);
+        auto chunk = [&] {
+            for (int jj = j; jj < jend; ++jj) {
+                mv(jj, V + (size_t)jj * L, &G->sv[jj], &G->svf[jj], V + (size_t)(jj + 1) * L, ctrl);
+                column(jj, nullptr, ctrl);
+            }
+        };
+        if (key && s->graphs && !s->timing) {
+            ChunkKey k = *key;
+            k.j0 = j;
+            k.jend = jend;
+            hipGraphExec_t ex = nullptr;
+            CHK(chunk_graph(s, k, chunk, ex));
+            HIPCHK(hipGraphLaunch(ex, s->st));
+        } else {
+            chunk();
         }
         HIPCHK(hipMemcpyAsync(dn, G, sizeof(GState), hipMemcpyDeviceToHost, s->st));
         HIPCHK(hipStreamSynchronize(s->st));
@@ -455,7 +539,8 @@ static imx_status gmres(imx_solver* s, const StageCtx& c, double* x, double bnor
         }
         if (beta == 0.0 || its >= maxit || (!fixed && beta <= tol * bnorm)) break;
         const GState* G = nullptr;
-        CHK(arnoldi_cycle<double>(s, V, s->dm.WJ, s->m, beta, tol * bnorm, its, maxit, fixed, mv, G));
+        const ChunkKey key = chunk_key(0, V, s->dm.WJ, s->cr, c.rho, c.pk, c.k);
+        CHK(arnoldi_cycle<double>(s, V, s->dm.WJ, s->m, beta, tol * bnorm, its, maxit, fixed, mv, G, &key));
         const int k = G->k;
         its = G->its;
         double cf[GM];
@@ -493,7 +578,8 @@ static imx_status inner_cycle_f32(imx_solver* s, const StageK& k, double beta, d
         });
     };
     const GState* G = nullptr;
-    CHK(arnoldi_cycle<float>(s, s->Vf, s->WJf, m, beta, tol * beta, 0, m, false, mv, G));
+    const ChunkKey key = chunk_key(1, s->Vf, s->WJf, s->crf, s->rhof, s->pkf, k);
+    CHK(arnoldi_cycle<float>(s, s->Vf, s->WJf, m, beta, tol * beta, 0, m, false, mv, G, &key));
     const int kk = G->k;
     double cf[GM];
     cycle_coefficients(*G, kk, cf);
@@ -797,6 +883,7 @@ imx_status imx_solver_workspace_bytes(const imx_solver* s, size_t* bytes) {
 
 imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
     if (!s || !dev) return IMX_EINVAL;
+    drop_chunk_graphs(s);   // captured against the previous workspace
     if (bytes < s->ws_bytes) {
         set_error("imx_solver_bind_workspace: workspace too small");
         return IMX_ENOMEM;
@@ -1083,6 +1170,13 @@ imx_status imx_geo_imbalance(imx_solver* s, double* egeo) {
     return IMX_OK;
 }
 
+imx_status imx_solver_set_graphs(imx_solver* s, int enable) {
+    if (!s) return IMX_EINVAL;
+    s->graphs = enable != 0;
+    if (!s->graphs) drop_chunk_graphs(s);
+    return IMX_OK;
+}
+
 imx_status imx_solver_timing(imx_solver* s, int enable) {
     NEED_BOUND(s);
     timing_flush(s);
@@ -1111,6 +1205,8 @@ void imx_solver_destroy(imx_solver* s) {
     if (!s) return;
     timing_flush(s);
     for (auto e : s->tpool) (void)hipEventDestroy(e);
+    drop_chunk_graphs(s);
+    if (s->cst) (void)hipStreamDestroy(s->cst);
     if (s->hsc) (void)hipHostFree(s->hsc);
     if (s->hgs) (void)hipHostFree(s->hgs);
     delete s;
