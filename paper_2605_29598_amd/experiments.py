@@ -79,9 +79,94 @@ def run(kind, hours, every_hours, scheme, precision, load=None, save=None, out=s
     return summary, series
 
 
+def _lagrange(nodes, t):
+    """l_i(t) for every node i and point t: array [len(t), n]."""
+    n = len(nodes)
+    out = np.ones((len(t), n))
+    for i in range(n):
+        for m in range(n):
+            if m != i:
+                out[:, i] *= (t - nodes[m]) / (nodes[i] - nodes[m])
+    return out
+
+
+def sample_slice(q, coords, spec, n, gamma, X, Z):
+    """w and p' = p - p_background of a slice state at points (X, Z): each
+    element's polynomial evaluated at the point (one periodic element in y,
+    elements ordered z fastest then x); the background is taken at the nodes,
+    so p' is the interpolant of the nodal perturbation."""
+    x = coords[0]
+    hx, hz = spec.Lx / spec.nx, spec.Lz / spec.nz
+    ix = np.minimum((X // hx).astype(int), spec.nx - 1)
+    iz = np.minimum((Z // hz).astype(int), spec.nz - 1)
+    e = iz + spec.nz * ix
+    nodes = x[0, :n] / hx                            # element 0 spans [0, hx] in x
+    lx = _lagrange(nodes, (X - ix * hx) / hx)
+    lz = _lagrange(nodes, (Z - iz * hz) / hz)
+    rho = q[0][e].reshape(len(X), n, n, n)[:, :, 0, :]   # [point][k][i], the j = 0 layer
+    mz = q[3][e].reshape(len(X), n, n, n)[:, :, 0, :]
+    mm = sum(q[c][e].reshape(len(X), n, n, n)[:, :, 0, :] ** 2 for c in (1, 2, 3))
+    E = q[4][e].reshape(len(X), n, n, n)[:, :, 0, :]
+    p = (gamma - 1.0) * (E - 0.5 * mm / rho)
+    # the isothermal background at the nodes, so that p' of the initial state is exactly 0
+    zn = coords[2][e].reshape(len(X), n, n, n)[:, :, 0, :]
+    pb = W.P_REF * np.exp(-W.GRAV / (W.RGAS * 250.0) * zn)
+    ev = lambda f: np.einsum("pki,pi,pk->p", f, lx, lz)
+    return ev(mz / rho), ev(p - pb)
+
+
+def convergence(hours, levels, scheme, nsx=1200, nsz=80, out=sys.stdout):
+    """Self-convergence of the Sec. 4.1 wave under the hyperbolic scaling of
+    the paper's convergence test: 150 x 10 elements, r = 4, dt = 1 s, mesh
+    width and dt halved per level; each level's w and p' sampled on a fixed
+    nsx x nsz grid and compared with the next finer level."""
+    import torch
+    from . import binding as B
+    X, Z = np.meshgrid((np.arange(nsx) + 0.5) * 6000e3 / nsx, (np.arange(nsz) + 0.5) * 10e3 / nsz, indexing="ij")
+    X, Z = X.ravel(), Z.ravel()
+    samples = []
+    for l in range(levels):
+        nx, nz, dt = 150 * 2 ** l, 10 * 2 ** l, 1.0 / 2 ** l
+        w = W.igw_slice(nx=nx, nz=nz, degree=4, scheme=scheme)
+        w.num.dt = dt
+        mesh = B.Mesh(w.mesh)
+        sol = B.Solver(mesh, w.phys, w.num)
+        coords = mesh.node_coords()
+        sol.set_state(W.initial_state(w, coords))
+        nsteps = int(round(hours * 3600.0 / dt))
+        chunk = max(1, min(nsteps, 2000))
+        done, t0, its = 0, time.perf_counter(), 0
+        while done < nsteps:
+            n = min(chunk, nsteps - done)
+            st = sol.step(n)
+            its += st.gmres_iters
+            done += n
+            print(json.dumps({"level": l, "steps": done, "of": nsteps}), file=out, flush=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        q = sol.get_state().cpu().numpy()
+        samples.append(sample_slice(q, coords, w.mesh, w.mesh.degree + 1, w.phys.gamma, X, Z))
+        print(json.dumps({"level": l, "elements": [nx, nz], "dt": dt, "steps": nsteps, "wall_s": wall,
+                          "ms_per_step": 1e3 * wall / nsteps, "gmres_per_step": its / nsteps,
+                          "dof_updates_per_s": 5 * mesh.E * mesh.Np * nsteps / wall}), file=out, flush=True)
+        del sol
+    rows = []
+    for l in range(levels - 1):
+        ew = samples[l][0] - samples[l + 1][0]
+        ep = samples[l][1] - samples[l + 1][1]
+        rows.append({"level": l, "l2_w": float(np.sqrt(np.mean(ew ** 2))), "linf_w": float(np.abs(ew).max()),
+                     "l2_p": float(np.sqrt(np.mean(ep ** 2))), "linf_p": float(np.abs(ep).max())})
+    for l in range(len(rows) - 1):
+        for k in ("l2_w", "linf_w", "l2_p", "linf_p"):
+            rows[l + 1]["eoc_" + k] = float(np.log2(rows[l][k] / rows[l + 1][k]))
+    print(json.dumps({"convergence": rows, "hours": hours, "scheme": "R%d" % scheme}), file=out, flush=True)
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("kind", choices=["planetary", "reference"])
+    ap.add_argument("kind", choices=["planetary", "reference", "convergence"])
+    ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--hours", type=float, default=None)
     ap.add_argument("--every-hours", type=float, default=None)
     ap.add_argument("--scheme", choices=["R1", "R2"], default="R2")
@@ -89,6 +174,9 @@ def main(argv=None):
     ap.add_argument("--load", default=None)
     ap.add_argument("--save", default=None)
     a = ap.parse_args(argv)
+    if a.kind == "convergence":
+        convergence(a.hours if a.hours is not None else 0.25, a.levels, W.R1 if a.scheme == "R1" else W.R2)
+        return
     hours = a.hours if a.hours is not None else (96.0 if a.kind == "planetary" else 8.0)
     every = a.every_hours if a.every_hours is not None else (1.0 if a.kind == "planetary" else 0.25)
     run(a.kind, hours, every, W.R1 if a.scheme == "R1" else W.R2, a.precision, a.load, a.save)
