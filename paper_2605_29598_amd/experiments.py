@@ -25,10 +25,12 @@ import numpy as np
 from . import workloads as W
 
 
-def run(kind, hours, every_hours, scheme, precision, load=None, save=None, out=sys.stdout):
+def run(kind, hours, every_hours, scheme, precision, load=None, save=None, dt=None, out=sys.stdout):
     import torch
     from . import binding as B
     w = W.igw_slice(planetary=(kind == "planetary"), scheme=scheme)
+    if dt is not None:
+        w.num.dt = dt
     mesh = B.Mesh(w.mesh)
     prec = B.IMX_MIXED if precision == "mixed" else B.IMX_FP64
     sol = B.Solver(mesh, w.phys, w.num, precision=prec)
@@ -134,7 +136,7 @@ def convergence(hours, levels, scheme, nsx=1200, nsz=80, out=sys.stdout):
         coords = mesh.node_coords()
         sol.set_state(W.initial_state(w, coords))
         nsteps = int(round(hours * 3600.0 / dt))
-        chunk = max(1, min(nsteps, 2000))
+        chunk = max(1, min(nsteps, 1000))
         done, t0, its = 0, time.perf_counter(), 0
         while done < nsteps:
             n = min(chunk, nsteps - done)
@@ -171,6 +173,7 @@ def main(argv=None):
     ap.add_argument("--every-hours", type=float, default=None)
     ap.add_argument("--scheme", choices=["R1", "R2"], default="R2")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--dt", type=float, default=None, help="time step in s instead of the workload's")
     ap.add_argument("--load", default=None)
     ap.add_argument("--save", default=None)
     a = ap.parse_args(argv)
@@ -179,7 +182,7 @@ def main(argv=None):
         return
     hours = a.hours if a.hours is not None else (96.0 if a.kind == "planetary" else 8.0)
     every = a.every_hours if a.every_hours is not None else (1.0 if a.kind == "planetary" else 0.25)
-    run(a.kind, hours, every, W.R1 if a.scheme == "R1" else W.R2, a.precision, a.load, a.save)
+    run(a.kind, hours, every, W.R1 if a.scheme == "R1" else W.R2, a.precision, a.load, a.save, a.dt)
 
 
 if __name__ == "__main__":
