@@ -55,6 +55,24 @@ __global__ void k_final_sum(const double* __restrict__ partial, int nb, int nv, 
     if (threadIdx.x == 0) out[v] = red[0];
 }
 
+// the same sums over partials stored [nv][nb] (contiguous per value)
+__global__ void k_final_sum_t(const double* __restrict__ partial, int nb, double* __restrict__ out,
+                              const int* __restrict__ ctrl) {
+    if (ctrl && *ctrl != 0) return;
+    __shared__ double red[TPB];
+    const int v = blockIdx.x;
+    const double* p = partial + (size_t)v * nb;
+    double s = 0;
+    for (int b = threadIdx.x; b < nb; b += TPB) s += p[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = TPB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[v] = red[0];
+}
+
 static void final_sum(const double* partial, int nb, int nv, double* out, hipStream_t st,
                       const int* ctrl = nullptr) {
     hipLaunchKernelGGL(k_final_sum, dim3(nv), dim3(TPB), 0, st, partial, nb, nv, out, ctrl);
@@ -137,7 +155,7 @@ __device__ __forceinline__ void lane_weights(const R* WJ, const WSrc& ws, const 
 }
 
 // ------------------------------------------------------- multi-dot products
-// partial[b][v] = sum over workgroup b's entries of WJ * V_v * z. The vectors
+// partial[v][b] = sum over workgroup b's entries of WJ * V_v * z. The vectors
 // split into NG chunks over the wavefronts of one workgroup (4 / NG wavefronts
 // per chunk, at most CH running sums per lane, so the lanes keep full
 // occupancy): every chunk walks the same entries at the same time, so z and the
@@ -188,7 +206,7 @@ k_dots(int64_t L, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z,
         const int g = threadIdx.x / per, i = threadIdx.x - g * per;
         double sum = 0;
         for (int k = 0; k < WPG; ++k) sum += red[k * NG + g][i];
-        partial[(size_t)blockIdx.x * nvtot + threadIdx.x] = sum;
+        partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = sum;   // [vector][workgroup]
     }
 }
 
@@ -220,7 +238,7 @@ void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R
         dots_launch<R, true>(g, nv, L, V, ldv, z, WJ, partial, st, ctrl, ws);
     else
         dots_launch<R, false>(g, nv, L, V, ldv, z, WJ, partial, st, ctrl, ws);
-    final_sum(partial, (int)g, nv, out, st, ctrl);
+    hipLaunchKernelGGL(k_final_sum_t, dim3(nv), dim3(TPB), 0, st, partial, (int)g, out, ctrl);
 }
 template void launch_dots<double>(int64_t, int, const double*, int64_t, const double*, const double*, double*,
                                   double*, hipStream_t, const int*, WSrc);
@@ -335,6 +353,17 @@ k_givens(GState* __restrict__ G, int j, const double* __restrict__ raw, const do
         cs[t] = G->cs[t];
         sn[t] = G->sn[t];
     }
+    // the scalars lane 0 needs after the reduction, loaded while it runs
+    double gj = 0, tolb = 0, zz = 0;
+    int its0 = 0, maxit = 0, fixed = 0;
+    if (t == 0) {
+        gj = G->g[j];
+        tolb = G->tolb;
+        its0 = G->its;
+        maxit = G->maxit;
+        fixed = G->fixed;
+        if (raw2 == nullptr) zz = raw[j + 1];
+    }
     __syncthreads();
     for (int off = TPB / 2; off > 0; off >>= 1) {
         if (t < off) red[t] += red[t + off];
@@ -344,34 +373,36 @@ k_givens(GState* __restrict__ G, int j, const double* __restrict__ raw, const do
         const double nrm = red[0];
         // severe cancellation in the single classical Gram-Schmidt pass: the
         // host runs a second pass and finishes the column
-        if (raw2 == nullptr && nrm < 1e-6 * raw[j + 1]) {
+        if (raw2 == nullptr && nrm < 1e-6 * zz) {
             G->status = 2;
             keep = 0;
         } else {
             keep = 1;
             if (raw2) G->status = 0;
             const double hnext = sqrt(nrm);
-            col[j + 1] = hnext;
+            // earlier rotations applied down the column; the entry below the
+            // current one stays in a register from one rotation to the next
+            double cur = col[0];
             for (int i = 0; i < j; ++i) {
-                const double a = col[i], b = col[i + 1];
+                const double a = cur, b = col[i + 1];
                 col[i] = cs[i] * a + sn[i] * b;
-                col[i + 1] = -sn[i] * a + cs[i] * b;
+                cur = -sn[i] * a + cs[i] * b;
             }
-            const double den = hypot(col[j], col[j + 1]);
-            const double c = col[j] / den, s = col[j + 1] / den;
+            const double hj = j > 0 ? cur : col[0];
+            const double den = hypot(hj, hnext);
+            const double c = hj / den, s = hnext / den;
             G->cs[j] = c;
             G->sn[j] = s;
             col[j] = den;
             col[j + 1] = 0.0;
-            const double gj = G->g[j];
             G->g[j + 1] = -s * gj;
             G->g[j] = c * gj;
             G->k = j + 1;
-            const int its = G->its + 1;
+            const int its = its0 + 1;
             G->its = its;
             if (!isfinite(hnext)) {
                 G->status = 3;
-            } else if (hnext == 0.0 || its >= G->maxit || (!G->fixed && fabs(-s * gj) <= G->tolb)) {
+            } else if (hnext == 0.0 || its >= maxit || (!fixed && fabs(-s * gj) <= tolb)) {
                 G->status = 1;
             } else {
                 G->sv[j + 1] = 1.0 / hnext;
