@@ -1636,19 +1636,42 @@ k_slice_project(int64_t nlines, double* __restrict__ q, const Tab<N, double>* __
     }
 }
 
+// The two element sets of a mesh with hanging faces write disjoint outputs:
+// the face-by-face launch over the elements owning a coarse hanging face runs
+// on the side stream, forked from and joined back into `st`, beside the
+// all-faces launch over the others. Measured worth it for the explicit
+// residual and the Picard refresh (face-by-face part of 70 us and more on the
+// refined orography box), not for the Schur passes (12 to 32 us, less than
+// the fork and join cost), which keep one stream (fork = false).
+template <typename FF, typename SF>
+static void fork_join(const DevMesh& m, hipStream_t st, FF&& fast, SF&& slow, bool fork = true) {
+    if (fork && m.ncoarse && m.side) {
+        (void)hipEventRecord(m.fork, st);
+        (void)hipStreamWaitEvent(m.side, m.fork, 0);
+        slow(m.side);
+        fast(st);
+        (void)hipEventRecord(m.join, m.side);
+        (void)hipStreamWaitEvent(st, m.join, 0);
+    } else {
+        fast(st);
+        if (m.ncoarse) slow(st);
+    }
+}
+
 // Launches kern over all elements, or (meshes with hanging faces) the
 // face-by-face instance over the elements owning a coarse hanging face and
 // the all-faces instance over the others.
-template <int N, typename KF, typename KS, typename... Args>
+template <int N, bool FORK, typename KF, typename KS, typename... Args>
 static void launch_split(const DevMesh& m, KF fast, KS slow, hipStream_t st, Args... args) {
     constexpr int EPB = epb_of(N);
-    auto go = [&](auto kern, const int* list, int64_t n) {
+    auto go = [&](auto kern, const int* list, int64_t n, hipStream_t s) {
         if (n <= 0) return;
         const int64_t nb = (n + EPB - 1) / EPB;
-        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(threads_of(N)), 0, st, list, n, args...);
+        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(threads_of(N)), 0, s, list, n, args...);
     };
-    go(fast, m.ncoarse ? m.reg_list : nullptr, m.E - m.ncoarse);
-    if (m.ncoarse) go(slow, m.crs_list, m.ncoarse);
+    fork_join(
+        m, st, [&](hipStream_t s) { go(fast, m.ncoarse ? m.reg_list : nullptr, m.E - m.ncoarse, s); },
+        [&](hipStream_t s) { go(slow, m.crs_list, m.ncoarse, s); }, FORK);
 }
 
 #define IMX_DISPATCH_N(n, CALL) \
@@ -1665,10 +1688,10 @@ void launch_explicit(const DevMesh& m, const HostTab&, const PhysK& ph, const R*
 #define CALL(NN)                                                                                            \
     do {                                                                                                    \
         if (m.deformed)                                                                                     \
-            launch_split<NN>(m, k_explicit<NN, R, false, false>, k_explicit<NN, R, true, false>, st, q, fNS, \
+            launch_split<NN, true>(m, k_explicit<NN, R, false, false>, k_explicit<NN, R, true, false>, st, q, fNS, \
                              fS, geom<R>(m), (const Tab<NN, R>*)tab_ptr<R>(m), ph, m.sponge);              \
         else                                                                                                \
-            launch_split<NN>(m, k_explicit<NN, R, false, true>, k_explicit<NN, R, true, true>, st, q, fNS,  \
+            launch_split<NN, true>(m, k_explicit<NN, R, false, true>, k_explicit<NN, R, true, true>, st, q, fNS,  \
                              fS, geom<R>(m), (const Tab<NN, R>*)tab_ptr<R>(m), ph, m.sponge);               \
     } while (0)
     IMX_DISPATCH_N(m.n, CALL)
@@ -1681,7 +1704,7 @@ template <typename R>
 void launch_pass1(const DevMesh& m, const HostTab&, const StageK& sk, const R* p, const R* pscale,
                   const R* Fh, const R* rho, const R* pk, const R* uk, R* w, R* FB, R* FBh, hipStream_t st) {
 #define CALL(NN)                                                                                         \
-    launch_split<NN>(m, k_pass1<NN, R, false>, k_pass1<NN, R, true>, st, p, pscale, Fh, rho, pk, uk, w, FB, \
+    launch_split<NN, false>(m, k_pass1<NN, R, false>, k_pass1<NN, R, true>, st, p, pscale, Fh, rho, pk, uk, w, FB, \
                      FBh, geom<R>(m), (const Tab<NN, R>*)tab_ptr<R>(m), sk, (const int*)nullptr)
     IMX_DISPATCH_N(m.n, CALL)
 #undef CALL
@@ -1702,14 +1725,21 @@ static void pass2_n(const DevMesh& m, const StageK& sk, const R* Gp, const R* p,
     const int64_t L = m.Lp;
     const int64_t nf = m.ncoarse ? m.E - m.ncoarse : m.E, ns = m.ncoarse;
     const int64_t bf = (nf + EPB - 1) / EPB, bs = (ns + EPB - 1) / EPB;
-    if (bf > 0)
-        hipLaunchKernelGGL((k_pass2<N, R, false>), dim3((unsigned)bf), dim3(threads_of(N)), 0, st,
-                           m.ncoarse ? m.reg_list : nullptr, nf, Gp, p, pscale, w, pk, rho, FB, FBh, out, (R)alpha,
-                           dual, geom<R>(m), T, sk, V, nv, L, partial, (const int*)nullptr);
-    if (bs > 0)
-        hipLaunchKernelGGL((k_pass2<N, R, true>), dim3((unsigned)bs), dim3(threads_of(N)), 0, st, m.crs_list, ns, Gp,
-                           p, pscale, w, pk, rho, FB, FBh, out, (R)alpha, dual, geom<R>(m), T, sk, V, nv, L,
-                           partial ? partial + (size_t)bf * (nv + 1) : nullptr, (const int*)nullptr);
+    fork_join(
+        m, st,
+        [&](hipStream_t s) {
+            if (bf > 0)
+                hipLaunchKernelGGL((k_pass2<N, R, false>), dim3((unsigned)bf), dim3(threads_of(N)), 0, s,
+                                   m.ncoarse ? m.reg_list : nullptr, nf, Gp, p, pscale, w, pk, rho, FB, FBh, out,
+                                   (R)alpha, dual, geom<R>(m), T, sk, V, nv, L, partial, (const int*)nullptr);
+        },
+        [&](hipStream_t s) {
+            if (bs > 0)
+                hipLaunchKernelGGL((k_pass2<N, R, true>), dim3((unsigned)bs), dim3(threads_of(N)), 0, s, m.crs_list,
+                                   ns, Gp, p, pscale, w, pk, rho, FB, FBh, out, (R)alpha, dual, geom<R>(m), T, sk, V,
+                                   nv, L, partial ? partial + (size_t)bf * (nv + 1) : nullptr, (const int*)nullptr);
+        },
+        false);
     if (V) launch_final_sum(partial, (int)(bf + bs), nv + 1, dots, st);
 }
 
@@ -1739,23 +1769,37 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
     const int64_t bf = (nf + EPBM - 1) / EPBM, bs = (ns + EPB - 1) / EPB;
     const int* fl = m.ncoarse ? m.reg_list : nullptr;
     if (!out) {
-        if (bf > 0)
-            hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, st, fl, (int)nf, x,
-                               xs, cr, pk, w, FB, geom<R>(m), T, sk, ctrl);
-        if (bs > 0)
-            hipLaunchKernelGGL((k_pass1<N, R, true>), dim3((unsigned)bs), dim3(threads_of(N)), 0, st, m.crs_list, ns,
-                               x, xs, (const R*)nullptr, rho, pk, (const R*)nullptr, w, FB, FBh, geom<R>(m), T, sk,
-                               ctrl);
+        fork_join(
+            m, st,
+            [&](hipStream_t s) {
+                if (bf > 0)
+                    hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
+                                       (int)nf, x, xs, cr, pk, w, FB, geom<R>(m), T, sk, ctrl);
+            },
+            [&](hipStream_t s) {
+                if (bs > 0)
+                    hipLaunchKernelGGL((k_pass1<N, R, true>), dim3((unsigned)bs), dim3(threads_of(N)), 0, s,
+                                       m.crs_list, ns, x, xs, (const R*)nullptr, rho, pk, (const R*)nullptr, w, FB,
+                                       FBh, geom<R>(m), T, sk, ctrl);
+            },
+            false);
     } else {
-        if (bf > 0)
-            hipLaunchKernelGGL((k_mv2<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, st, fl, (int)nf, x,
-                               xs, (const R*)w, pk, rho, (const R*)FB, (const R*)FBh, out, dual, geom<R>(m), T, sk,
-                               ctrl);
-        if (bs > 0)
-            hipLaunchKernelGGL((k_pass2<N, R, true>), dim3((unsigned)bs), dim3(threads_of(N)), 0, st, m.crs_list, ns,
-                               (const R*)nullptr, x, xs, (const R*)w, pk, rho, (const R*)FB, (const R*)FBh, out,
-                               (R)-1.0, dual, geom<R>(m), T, sk, (const R*)nullptr, 0, (int64_t)0,
-                               (double*)nullptr, ctrl);
+        fork_join(
+            m, st,
+            [&](hipStream_t s) {
+                if (bf > 0)
+                    hipLaunchKernelGGL((k_mv2<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
+                                       (int)nf, x, xs, (const R*)w, pk, rho, (const R*)FB, (const R*)FBh, out, dual,
+                                       geom<R>(m), T, sk, ctrl);
+            },
+            [&](hipStream_t s) {
+                if (bs > 0)
+                    hipLaunchKernelGGL((k_pass2<N, R, true>), dim3((unsigned)bs), dim3(threads_of(N)), 0, s,
+                                       m.crs_list, ns, (const R*)nullptr, x, xs, (const R*)w, pk, rho, (const R*)FB,
+                                       (const R*)FBh, out, (R)-1.0, dual, geom<R>(m), T, sk, (const R*)nullptr, 0,
+                                       (int64_t)0, (double*)nullptr, ctrl);
+            },
+            false);
     }
 }
 
@@ -1820,7 +1864,7 @@ size_t pass2_partial_count(const DevMesh& m) {
 void launch_lambda(const DevMesh& m, const HostTab&, const StageK& sk, const double* pk, const double* uk,
                    const double* rho, const double* G0h, double* Gp, hipStream_t st) {
 #define CALL(NN)                                                                                    \
-    launch_split<NN>(m, k_lambda<NN, false>, k_lambda<NN, true>, st, pk, uk, rho, G0h, Gp, geom<double>(m), \
+    launch_split<NN, true>(m, k_lambda<NN, false>, k_lambda<NN, true>, st, pk, uk, rho, G0h, Gp, geom<double>(m), \
                      (const Tab<NN, double>*)m.tab, sk)
     IMX_DISPATCH_N(m.n, CALL)
 #undef CALL

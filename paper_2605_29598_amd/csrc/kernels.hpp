@@ -21,8 +21,8 @@ struct DevMesh {
     const double* h = nullptr;      // [E*3]
     const double* hinv = nullptr;   // [E*3] 1 / h
     const double* WJ = nullptr;     // [E*Np]
-    const double* G = nullptr;      // [9][E][Np]
-    const double* nS = nullptr;     // [E][6][3][Nf]
+    const double* G = nullptr;      // [5][E][Np] terrain-following meshes: W cof(J) (0,0) (1,1) (2,0) (2,1) (2,2)
+    const double* nS = nullptr;     // [E][10][Nf] terrain-following meshes: n dS, normal component on x/y faces
     const double* sponge = nullptr; // [E*Np] or null
     const float* WJf = nullptr;
     const float* Gf = nullptr;
@@ -36,6 +36,10 @@ struct DevMesh {
     const int* crs_list = nullptr;  // [ncoarse]
     const void* tab = nullptr;      // basis tables (binary64), device
     const void* tabf = nullptr;     // basis tables (binary32), device
+    // meshes with hanging faces: the face-by-face kernels of crs_list run on
+    // `side` beside the all-faces kernels of reg_list (fork and join events)
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 struct PhysK {

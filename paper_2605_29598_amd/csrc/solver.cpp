@@ -120,6 +120,8 @@ struct imx_solver {
     // captured Krylov chunks (imx_solver_set_graphs): replayed on st, captured on cst
     bool graphs = false;
     hipStream_t cst = nullptr;
+    hipStream_t side = nullptr;           // meshes with hanging faces: see DevMesh::side
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::vector<std::pair<ChunkKey, hipGraphExec_t>> chunk_graphs;
     // kernel timing (imx_solver_timing)
     bool timing = false;
@@ -894,6 +896,17 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
     }
     s->ws = (char*)dev;
     layout(s, s->ws);
+    if (s->dm.ncoarse) {
+        // side stream for the elements owning a coarse hanging face (default priority)
+        if (!s->side) {
+            HIPCHK(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
+        }
+        s->dm.side = s->side;
+        s->dm.fork = s->ev_fork;
+        s->dm.join = s->ev_join;
+    }
     // zero first: the padding of the Krylov-stride vectors (and WJ) stays zero
     HIPCHK(hipMemsetAsync(s->ws, 0, s->ws_bytes, s->st));
     const Mesh& m = *s->mesh;
@@ -1207,6 +1220,12 @@ void imx_solver_destroy(imx_solver* s) {
     for (auto e : s->tpool) (void)hipEventDestroy(e);
     drop_chunk_graphs(s);
     if (s->cst) (void)hipStreamDestroy(s->cst);
+    if (s->side) {
+        (void)hipStreamSynchronize(s->side);
+        (void)hipStreamDestroy(s->side);
+        (void)hipEventDestroy(s->ev_fork);
+        (void)hipEventDestroy(s->ev_join);
+    }
     if (s->hsc) (void)hipHostFree(s->hsc);
     if (s->hgs) (void)hipHostFree(s->hgs);
     delete s;

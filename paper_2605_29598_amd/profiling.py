@@ -18,6 +18,7 @@ import hashlib
 import json
 import os
 import re
+import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -81,7 +82,61 @@ def summarize(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes):
     }
 
 
+WORKLOADS = {
+    "igw_channel_120x40x10_r3": lambda W: W.igw_channel(),
+    "orography_64x64x24_r4": lambda W: W.orography(),
+    "orography_amr_32x32x12_r4": lambda W: W.orography(32, 32, 12, 4, refined=True),
+}
+
+
+def operators(name, reps=20, seed=1):
+    """Per-launch time and algorithmic bandwidth of the explicit residual and
+    the two Schur passes (R2) on a full workload, from the solver's HIP-event
+    timers: `reps` Schur applies and `reps` // 4 explicit residuals on seeded
+    inputs, after a warm-up."""
+    import numpy as np
+    import torch
+    from . import binding as B
+    from . import workloads as W
+    w = WORKLOADS[name](W)
+    mesh = B.Mesh(w.mesh)
+    sol = B.Solver(mesh, w.phys, w.num)
+    rng = np.random.default_rng(seed)
+    shp = (mesh.E, mesh.Np)
+    sol.implicit_setup(1 + 0.1 * rng.uniform(size=shp), 1e5 * (1 + 0.1 * rng.uniform(size=shp)),
+                       rng.uniform(-1, 1, size=(3,) + shp))
+    p = torch.from_numpy(1e5 * (1 + 0.1 * rng.uniform(size=shp))).cuda()
+    q = torch.from_numpy(W.initial_state(w, mesh.node_coords())).cuda()
+    for _ in range(3):
+        sol.schur_apply(p)
+        sol.explicit_residual(q)
+    torch.cuda.synchronize()
+    sol.timing(True)
+    for _ in range(reps):
+        sol.schur_apply(p)
+    for _ in range(max(1, reps // 4)):
+        sol.explicit_residual(q)
+    torch.cuda.synchronize()
+    rep = sol.timing_report()
+    out = {"workload": name, "elements": mesh.E, "nodes_per_element": mesh.Np, "deformed": bool(mesh.deformed),
+           "coarse_hanging_faces": mesh.n_hanging, "kernels": {}}
+    for k in ("pass1", "pass2", "explicit"):
+        ms, by, n = rep[k]
+        us = 1e3 * ms / n
+        out["kernels"][k] = {"launches": n, "avg_launch_us": us, "algorithmic_MB_per_launch": by / n / 1e6,
+                             "GB_per_s": by / ms / 1e6, "frac_of_hbm_peak": by / ms / 1e6 / 8000.0}
+    return out
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "operators":
+        ap = argparse.ArgumentParser(description="operator timings on a full workload")
+        ap.add_argument("mode")
+        ap.add_argument("--workload", choices=list(WORKLOADS), required=True)
+        ap.add_argument("--reps", type=int, default=20)
+        a = ap.parse_args()
+        print(json.dumps(operators(a.workload, a.reps)))
+        return
     ap = argparse.ArgumentParser()
     for a in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--out"):
         ap.add_argument(a, required=True)
