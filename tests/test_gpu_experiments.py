@@ -1,0 +1,35 @@
+"""The slice runner end to end on the GPU at tiny model times: the reference
+channel and the planetary slice advance, report a finite imbalance and
+conserve mass, and the convergence study returns finite level differences
+that shrink under refinement."""
+import io
+import json
+
+import numpy as np
+import pytest
+
+from paper_2605_29598_amd import experiments as X
+from paper_2605_29598_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("kind", ["reference", "planetary"])
+def test_runner_short_run(kind):
+    buf = io.StringIO()
+    hours = 0.01 if kind == "reference" else 0.05
+    summary, series = X.run(kind, hours, hours / 2, W.R2, "fp64", out=buf)
+    assert summary["steps"] == int(round(hours * 3600 / (0.5 if kind == "reference" else 10.0)))
+    assert len(series) == 3 and all(np.isfinite(r["egeo"]) for r in series)
+    assert series[0]["egeo"] < 1e-13 < series[-1]["egeo"]
+    assert abs(series[-1]["mass_rel"]) < 1e-13
+    lines = [json.loads(l) for l in buf.getvalue().splitlines()]
+    assert "summary" in lines[-1]
+
+
+def test_convergence_study_shrinks():
+    buf = io.StringIO()
+    rows = X.convergence(hours=1.0 / 120, levels=3, scheme=W.R2, nsx=300, nsz=20, out=buf)
+    assert len(rows) == 2
+    for k in ("l2_w", "l2_p"):
+        assert 0 < rows[1][k] < rows[0][k], (k, rows)
