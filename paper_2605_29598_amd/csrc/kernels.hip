@@ -1164,7 +1164,9 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
             __syncthreads();
         }
     }
-    // w = (I + beta J)^{-1} A^{-1} (-B p) [R2] or A^{-1}(-B p) [R1]
+    // w = (I + beta J)^{-1} A^{-1} (-B p) [R2] or A^{-1}(-B p) [R1]; stored as
+    // (rho h)^k w, the flux the second pass differentiates (so that it needs no
+    // p^k), and kept plain in LDS for this element's face traces
     if (act) {
         const R cdt = (R)sk.c_dt, beta = (R)sk.beta;
         R v[3];
@@ -1181,9 +1183,10 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
             wv[1] = v[1];
             wv[2] = v[2];
         }
+        const R rh = (R)sk.hfac * s_pk[le][node];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            w[(size_t)(c * fs + o)] = wv[c];
+            w[(size_t)(c * fs + o)] = rh * wv[c];
             s_w[le][c][node] = wv[c];
         }
     }
@@ -1227,7 +1230,7 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
 template <int N, typename R, bool AFF, int SCH>
 __global__ void __launch_bounds__(threads_mv(N))
 k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
-      const R* __restrict__ w, const R* __restrict__ pk, const R* __restrict__ rho, const R* __restrict__ FB,
+      const R* __restrict__ hw, const R* __restrict__ rlh, const R* __restrict__ FB,
       const R* __restrict__ FBh, R* __restrict__ out, int dual, Geom<R> g, const Tab<N, R>* __restrict__ Tg,
       StageK sk, const int* __restrict__ ctrl) {
     if (ctrl && *ctrl != 0) return;
@@ -1243,14 +1246,13 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
     const int e = act ? (elist ? elist[slot] : slot) : 0;
     const unsigned fs = (unsigned)g.E * NP, o = (unsigned)e * NP + node;
     R* U = &s_face[le][0];
-    R wv[3] = {0, 0, 0}, rh = 0, rl = 0, pv = 0;
+    R hv[3] = {0, 0, 0}, rl = 0, pv = 0;   // (rho h)^k w, rho_l / (rho h)^k
     ElemGeo<N, R, AFF> eg;
     if (act) {
         eg.load(g.eg, e);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) wv[c] = w[(size_t)(c * fs + o)];
-        rh = (R)sk.hfac * pk[o];
-        if constexpr (SCH == 2) rl = rho[o];
+        for (int c = 0; c < 3; ++c) hv[c] = hw[(size_t)(c * fs + o)];
+        if constexpr (SCH == 2) rl = rlh[o];
         pv = (pscale ? pscale[0] : (R)1) * p[o];
         // {(rho h)^k w} . n dS from the two sides' face buffers
 #pragma unroll
@@ -1276,14 +1278,14 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
             // the LDS copy of the tables is not visible before the first barrier
             const R wj = Tg->W3[node] * eg.dJ;
 #pragma unroll
-            for (int dd = 0; dd < 3; ++dd) s_vol[le][dd][node] = rh * ((wj * eg.hi(dd)) * wv[dd]);
+            for (int dd = 0; dd < 3; ++dd) s_vol[le][dd][node] = (wj * eg.hi(dd)) * hv[dd];
         } else {
 #pragma unroll
             for (int dd = 0; dd < 3; ++dd) {
                 R v = 0;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) v += G_gc<R>(g, fs, dd, c, o) * wv[c];
-                s_vol[le][dd][node] = rh * v;
+                for (int c = 0; c < 3; ++c) v += G_gc<R>(g, fs, dd, c, o) * hv[c];
+                s_vol[le][dd][node] = v;
             }
         }
     }
@@ -1301,7 +1303,7 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
     const R cdt = (R)sk.c_dt;
     R res = -(pv * (R)sk.igm1);
     res -= cdt * acc * iwj;
-    if constexpr (SCH == 2) res -= cdt * (R)sk.g * rl * wv[2];
+    if constexpr (SCH == 2) res -= cdt * (R)sk.g * rl * hv[2];   // rho_l w_z
     // z = -res = M^{-1} S (sc x); the dual form is S (sc x) = -res W detJ
     if (dual) {
         const R wj = AFF ? T.W3[node] * eg.dJ : g.WJ[o];
@@ -1346,8 +1348,8 @@ struct Wave4 {
 
 template <typename R, int SCH>
 __global__ void __launch_bounds__(256)
-k_mv2w(int nel, const R* __restrict__ p, const R* __restrict__ pscale, const R* __restrict__ w,
-       const R* __restrict__ pk, const R* __restrict__ rho, const R* __restrict__ FB, R* __restrict__ out, int dual,
+k_mv2w(int nel, const R* __restrict__ p, const R* __restrict__ pscale, const R* __restrict__ hw,
+       const R* __restrict__ rlh, const R* __restrict__ FB, R* __restrict__ out, int dual,
        Geom<R> g, const Tab<4, R>* __restrict__ Tg, StageK sk, const int* __restrict__ ctrl) {
     if (ctrl && *ctrl != 0) return;
     constexpr int NP = 64, NF = 16;
@@ -1358,12 +1360,11 @@ k_mv2w(int nel, const R* __restrict__ p, const R* __restrict__ pscale, const R* 
     if (e >= nel) return;
     const Wave4<R> W(threadIdx.x & 63);
     const unsigned fs = (unsigned)g.E * NP, o = (unsigned)e * NP + W.lane;
-    R wv[3];
+    R hv[3];   // (rho h)^k w
 #pragma unroll
-    for (int c = 0; c < 3; ++c) wv[c] = w[(size_t)(c * fs + o)];
-    const R rh = (R)sk.hfac * pk[o];
-    R rl = 0;
-    if constexpr (SCH == 2) rl = rho[o];
+    for (int c = 0; c < 3; ++c) hv[c] = hw[(size_t)(c * fs + o)];
+    R rl = 0;   // rho_l / (rho h)^k
+    if constexpr (SCH == 2) rl = rlh[o];
     const R pv = (pscale ? pscale[0] : (R)1) * p[o];
     const double* q8 = g.eg + (size_t)e * 8;
     const R hi[3] = {(R)q8[3], (R)q8[4], (R)q8[5]};
@@ -1386,7 +1387,7 @@ k_mv2w(int nel, const R* __restrict__ p, const R* __restrict__ pscale, const R* 
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         R gq[4];
-        W.line(rh * ((wj * hi[d]) * wv[d]), d, gq);
+        W.line((wj * hi[d]) * hv[d], d, gq);
 #pragma unroll
         for (int q = 0; q < 4; ++q) dv += T.D[q][W.ind[d]] * gq[q];
     }
@@ -1395,7 +1396,7 @@ k_mv2w(int nel, const R* __restrict__ p, const R* __restrict__ pscale, const R* 
     const R cdt = (R)sk.c_dt;
     R res = -(pv * (R)sk.igm1);
     res -= cdt * acc * iwj;
-    if constexpr (SCH == 2) res -= cdt * (R)sk.g * rl * wv[2];
+    if constexpr (SCH == 2) res -= cdt * (R)sk.g * rl * hv[2];   // rho_l w_z
     out[o] = dual ? -res * wj : -res;
 }
 
@@ -1762,7 +1763,8 @@ template void launch_pass2<float>(const DevMesh&, const HostTab&, const StageK&,
 
 template <typename R, int N, bool AFF, int SCH>
 static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
-                 const R* pk, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st, const int* ctrl) {
+                 const R* pk, const R* rlh, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st,
+                 const int* ctrl) {
     constexpr int EPB = epb_of(N), EPBM = epb_mv(N);
     const Tab<N, R>* T = (const Tab<N, R>*)tab_ptr<R>(m);
     const int64_t nf = m.ncoarse ? m.E - m.ncoarse : m.E, ns = m.ncoarse;
@@ -1789,7 +1791,7 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
             [&](hipStream_t s) {
                 if (bf > 0)
                     hipLaunchKernelGGL((k_mv2<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
-                                       (int)nf, x, xs, (const R*)w, pk, rho, (const R*)FB, (const R*)FBh, out, dual,
+                                       (int)nf, x, xs, (const R*)w, rlh, (const R*)FB, (const R*)FBh, out, dual,
                                        geom<R>(m), T, sk, ctrl);
             },
             [&](hipStream_t s) {
@@ -1804,30 +1806,31 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
 }
 
 template <typename R, int SCH>
-static void mv2w(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* rho, const R* pk, const R* w,
+static void mv2w(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* rlh, const R* hw,
                  const R* FB, R* out, int dual, hipStream_t st, const int* ctrl) {
     const Tab<4, R>* T = (const Tab<4, R>*)tab_ptr<R>(m);
     const unsigned nb = (unsigned)((m.E + 3) / 4);
-    hipLaunchKernelGGL((k_mv2w<R, SCH>), dim3(nb), dim3(256), 0, st, (int)m.E, x, xs, w, pk, rho, FB, out, dual,
+    hipLaunchKernelGGL((k_mv2w<R, SCH>), dim3(nb), dim3(256), 0, st, (int)m.E, x, xs, hw, rlh, FB, out, dual,
                        geom<R>(m), T, sk, ctrl);
 }
 
 template <typename R>
 static void mv_dispatch(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
-                        const R* pk, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st, const int* ctrl) {
+                        const R* pk, const R* rlh, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st,
+                        const int* ctrl) {
     if (out && m.n == 4 && !m.deformed && m.nh == 0) {
-        if (sk.scheme == 2) mv2w<R, 2>(m, sk, x, xs, rho, pk, w, FB, out, dual, st, ctrl);
-        else mv2w<R, 1>(m, sk, x, xs, rho, pk, w, FB, out, dual, st, ctrl);
+        if (sk.scheme == 2) mv2w<R, 2>(m, sk, x, xs, rlh, w, FB, out, dual, st, ctrl);
+        else mv2w<R, 1>(m, sk, x, xs, rlh, w, FB, out, dual, st, ctrl);
         return;
     }
 #define MV(NN)                                                                                            \
     do {                                                                                                  \
         if (!m.deformed) {                                                                                \
-            if (sk.scheme == 2) mv_n<R, NN, true, 2>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);  \
-            else mv_n<R, NN, true, 1>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);                 \
+            if (sk.scheme == 2) mv_n<R, NN, true, 2>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);  \
+            else mv_n<R, NN, true, 1>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);                 \
         } else {                                                                                          \
-            if (sk.scheme == 2) mv_n<R, NN, false, 2>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl); \
-            else mv_n<R, NN, false, 1>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);                \
+            if (sk.scheme == 2) mv_n<R, NN, false, 2>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl); \
+            else mv_n<R, NN, false, 1>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);                \
         }                                                                                                 \
     } while (0)
     IMX_DISPATCH_N(m.n, MV)
@@ -1837,23 +1840,24 @@ static void mv_dispatch(const DevMesh& m, const StageK& sk, const R* x, const R*
 template <typename R>
 void launch_mv1(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
                 const R* pk, R* w, R* FB, R* FBh, hipStream_t st, const int* ctrl) {
-    mv_dispatch<R>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, nullptr, 0, st, ctrl);
+    mv_dispatch<R>(m, sk, x, xs, cr, rho, pk, (const R*)nullptr, w, FB, FBh, nullptr, 0, st, ctrl);
 }
 template <typename R>
 void launch_mv2(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* w, const R* pk,
-                const R* rho, const R* FB, const R* FBh, R* out, int dual, hipStream_t st, const int* ctrl) {
-    mv_dispatch<R>(m, sk, x, xs, (const R*)nullptr, rho, pk, (R*)w, (R*)FB, (R*)FBh, out, dual, st, ctrl);
+                const R* rho, const R* rlh, const R* FB, const R* FBh, R* out, int dual, hipStream_t st,
+                const int* ctrl) {
+    mv_dispatch<R>(m, sk, x, xs, (const R*)nullptr, rho, pk, rlh, (R*)w, (R*)FB, (R*)FBh, out, dual, st, ctrl);
 }
 template void launch_mv1<double>(const DevMesh&, const StageK&, const double*, const double*, const double*,
                                  const double*, const double*, double*, double*, double*, hipStream_t, const int*);
 template void launch_mv1<float>(const DevMesh&, const StageK&, const float*, const float*, const float*,
                                 const float*, const float*, float*, float*, float*, hipStream_t, const int*);
 template void launch_mv2<double>(const DevMesh&, const StageK&, const double*, const double*, const double*,
-                                 const double*, const double*, const double*, const double*, double*, int,
-                                 hipStream_t, const int*);
+                                 const double*, const double*, const double*, const double*, const double*, double*,
+                                 int, hipStream_t, const int*);
 template void launch_mv2<float>(const DevMesh&, const StageK&, const float*, const float*, const float*,
-                                const float*, const float*, const float*, const float*, float*, int, hipStream_t,
-                                const int*);
+                                const float*, const float*, const float*, const float*, const float*, float*, int,
+                                hipStream_t, const int*);
 
 size_t pass2_partial_count(const DevMesh& m) {
     const int e = m.n == 2 ? 16 : (m.n == 3 ? 9 : (m.n == 4 ? 4 : 2));
