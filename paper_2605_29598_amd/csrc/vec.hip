@@ -154,6 +154,16 @@ __device__ __forceinline__ void lane_weights(const R* WJ, const WSrc& ws, const 
     }
 }
 
+// The lane's byte offset from a wave-uniform address, made opaque in every
+// iteration of a walk (an empty statement that emits no instruction): the
+// compiler cannot then hoist "vector + lane" out of the loop as a 64-bit
+// per-lane address per vector, and every load takes the scalar-base form
+// (one 32-bit offset register shared by all the vectors a lane reads).
+__device__ __forceinline__ uint32_t lane_offset(uint32_t off) {
+    asm volatile("" : "+v"(off));
+    return off;
+}
+
 // ------------------------------------------------------- multi-dot products
 // partial[v][b] = sum over workgroup b's entries of WJ * V_v * z. The vectors
 // split into NG chunks over the wavefronts of one workgroup (4 / NG wavefronts
@@ -170,30 +180,50 @@ k_dots(int64_t L, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z,
     using VT = typename Vec16<R>::T;
     constexpr int W = Vec16<R>::W;
     __shared__ double red[TPB / 64][CH];
-    const int ln = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // the wavefront index is uniform: the chunk, its vectors and the walk's
+    // base offset live in scalar registers
+    const int ln = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gi = wid % NG, sub = wid / NG;
     const int per = (nvtot + NG - 1) / NG, v0 = gi * per;
     const int nv = nvtot - v0 < per ? nvtot - v0 : per;
     double acc[CH];
 #pragma unroll
     for (int i = 0; i < CH; ++i) acc[i] = 0;
+    // every running sum loads unconditionally (a guarded load would wait for
+    // each vector in turn); sums past the chunk's last vector repeat that
+    // vector's address and are never written out
+    const char* vp[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+        int vi = v0 + (i < nv ? i : nv - 1);
+        vi = vi < nvtot ? (vi < 0 ? 0 : vi) : nvtot - 1;
+        vp[i] = (const char*)(V + (int64_t)vi * ldv);
+    }
     const int64_t nvec = L / W;   // ldv and L are multiples of W
-    const int64_t x0 = (blockIdx.x * (int64_t)WPG + sub) * 64 + ln, xs = (int64_t)gridDim.x * WPG * 64;
-    TabWalk tw(ws, TABW ? x0 * W : 0, TABW ? xs * W : 0);
-    for (int64_t x = x0; x < nvec; x += xs) {
-        const VT zz = ((const VT*)z)[x];
-        double wz[W];
-        lane_weights<R, VT, W, TABW>(WJ, ws, tw, x, wz);
+    // a wavefront walks 64 consecutive 16-byte lanes from a uniform base b:
+    // each address is a scalar base plus the lane's 32-bit offset
+    const int64_t b0 = (blockIdx.x * (int64_t)WPG + sub) * 64, xs = (int64_t)gridDim.x * WPG * 64;
+    const uint32_t lo0 = (uint32_t)ln * (uint32_t)sizeof(VT);
+    TabWalk tw(ws, TABW ? (b0 + ln) * W : 0, TABW ? xs * W : 0);
+    for (int64_t b = b0; b < nvec; b += xs) {
+        const int64_t x = b + ln;
+        if (x < nvec) {
+            const int64_t bo = b * (int64_t)sizeof(VT);
+            const uint32_t lo = lane_offset(lo0);
+            VT v[CH];
+#pragma unroll
+            for (int i = 0; i < CH; ++i) v[i] = *(const VT*)(vp[i] + bo + lo);
+            const VT zz = *(const VT*)((const char*)z + bo + lo);
+            double wz[W];
+            lane_weights<R, VT, W, TABW>(WJ, ws, tw, x, wz);
+#pragma unroll
+            for (int k = 0; k < W; ++k) wz[k] *= (double)lane<VT, R>(zz, k);
+#pragma unroll
+            for (int i = 0; i < CH; ++i)
+#pragma unroll
+                for (int k = 0; k < W; ++k) acc[i] += wz[k] * (double)lane<VT, R>(v[i], k);
+        }
         if constexpr (TABW) tw.advance(ws.np);
-#pragma unroll
-        for (int k = 0; k < W; ++k) wz[k] *= (double)lane<VT, R>(zz, k);
-#pragma unroll
-        for (int i = 0; i < CH; ++i)
-            if (i < nv) {
-                const VT v = ((const VT*)(V + (int64_t)(v0 + i) * ldv))[x];
-#pragma unroll
-                for (int k = 0; k < W; ++k) acc[i] += wz[k] * (double)lane<VT, R>(v, k);
-            }
     }
 #pragma unroll
     for (int i = 0; i < CH; ++i)
@@ -210,29 +240,47 @@ k_dots(int64_t L, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z,
     }
 }
 
+// one running sum per vector of a chunk: the chunk length (nv / NG rounded up)
+// is the template's CH, so that no load repeats an address except in the
+// last chunk
 template <typename R, bool TABW>
 static void dots_launch(unsigned g, int nv, int64_t L, const R* V, int64_t ldv, const R* z, const R* WJ,
                         double* partial, hipStream_t st, const int* ctrl, const WSrc& ws) {
-    if (nv <= 8)
-        hipLaunchKernelGGL((k_dots<R, 1, 8, TABW>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl,
-                           ws);
+#define IMX_DOTS(NG, CH) \
+    hipLaunchKernelGGL((k_dots<R, NG, CH, TABW>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl, ws)
+    if (nv <= 2)
+        IMX_DOTS(1, 2);
+    else if (nv <= 4)
+        IMX_DOTS(1, 4);
+    else if (nv <= 8)
+        IMX_DOTS(1, 8);
+    else if (nv <= 10)
+        IMX_DOTS(2, 5);
+    else if (nv <= 12)
+        IMX_DOTS(2, 6);
+    else if (nv <= 14)
+        IMX_DOTS(2, 7);
     else if (nv <= 16)
-        hipLaunchKernelGGL((k_dots<R, 2, 8, TABW>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl,
-                           ws);
+        IMX_DOTS(2, 8);
+    else if (nv <= 20)
+        IMX_DOTS(4, 5);
+    else if (nv <= 24)
+        IMX_DOTS(4, 6);
+    else if (nv <= 28)
+        IMX_DOTS(4, 7);
     else if (nv <= 32)
-        hipLaunchKernelGGL((k_dots<R, 4, 8, TABW>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl,
-                           ws);
+        IMX_DOTS(4, 8);
     else   // nv <= MAXV = 33
-        hipLaunchKernelGGL((k_dots<R, 4, 9, TABW>), dim3(g), dim3(TPB), 0, st, L, V, ldv, z, WJ, partial, nv, ctrl,
-                           ws);
+        IMX_DOTS(4, 9);
+#undef IMX_DOTS
 }
 
 template <typename R>
 void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R* WJ, double* partial,
                  double* out, hipStream_t st, const int* ctrl, WSrc ws) {
-    // grid measured on the 3 M-entry channel basis: 1024 workgroups while a
-    // chunk has 2 or 4 wavefronts, 2048 with one wavefront per chunk
-    const unsigned gmax = nv <= 16 ? 1024 : 2048;
+    // grid measured on the 3 M-entry channel basis: 512 workgroups (two per
+    // compute unit) for every vector count; 256, 384, 1024 and 2048 were slower
+    const unsigned gmax = 512;
     const unsigned g = stream_grid(L) > gmax ? gmax : stream_grid(L);
     if (ws.W3)
         dots_launch<R, true>(g, nv, L, V, ldv, z, WJ, partial, st, ctrl, ws);
