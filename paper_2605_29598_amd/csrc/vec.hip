@@ -55,16 +55,34 @@ __global__ void k_final_sum(const double* __restrict__ partial, int nb, int nv, 
     if (threadIdx.x == 0) out[v] = red[0];
 }
 
+// p[b] summed over b = t, t + TPB, ... < nb in that order, with eight loads in
+// flight (a plain loop waits for each load before the next)
+__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int t, int nb) {
+    double sum = 0;
+    int b = t;
+    for (; b + 7 * TPB < nb; b += 8 * TPB) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = p[b + k * TPB];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sum += v[k];
+    }
+    for (; b + TPB < nb; b += 2 * TPB) {
+        const double v0 = p[b], v1 = p[b + TPB];
+        sum += v0;
+        sum += v1;
+    }
+    if (b < nb) sum += p[b];
+    return sum;
+}
+
 // the same sums over partials stored [nv][nb] (contiguous per value)
 __global__ void k_final_sum_t(const double* __restrict__ partial, int nb, double* __restrict__ out,
                               const int* __restrict__ ctrl) {
     if (ctrl && *ctrl != 0) return;
     __shared__ double red[TPB];
     const int v = blockIdx.x;
-    const double* p = partial + (size_t)v * nb;
-    double s = 0;
-    for (int b = threadIdx.x; b < nb; b += TPB) s += p[b];
-    red[threadIdx.x] = s;
+    red[threadIdx.x] = strided_sum(partial + (size_t)v * nb, threadIdx.x, nb);
     __syncthreads();
     for (int off = TPB / 2; off > 0; off >>= 1) {
         if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
@@ -389,19 +407,19 @@ k_givens(GState* __restrict__ G, int j, const double* __restrict__ raw, const do
     __shared__ double red[TPB];
     __shared__ double col[GM + 1], cs[GM], sn[GM];
     __shared__ int keep;
-    double sum = 0;
-    for (int b = t; b < nb; b += TPB) sum += npart[b];
-    red[t] = sum;
+    // every global load is issued before the first LDS write and before any
+    // sum needs its value: the column, the earlier rotations, the scalars lane
+    // 0 needs after the reduction, and the partial norms eight at a time (the
+    // additions keep the order b = t, t + TPB, ...)
+    double h = 0, csv = 0, snv = 0;
     if (t <= j) {
-        double h = G->sv[t] * raw[t];
+        h = G->sv[t] * raw[t];
         if (raw2) h += G->sv[t] * raw2[t];
-        col[t] = h;
     }
     if (t < j) {
-        cs[t] = G->cs[t];
-        sn[t] = G->sn[t];
+        csv = G->cs[t];
+        snv = G->sn[t];
     }
-    // the scalars lane 0 needs after the reduction, loaded while it runs
     double gj = 0, tolb = 0, zz = 0;
     int its0 = 0, maxit = 0, fixed = 0;
     if (t == 0) {
@@ -411,6 +429,12 @@ k_givens(GState* __restrict__ G, int j, const double* __restrict__ raw, const do
         maxit = G->maxit;
         fixed = G->fixed;
         if (raw2 == nullptr) zz = raw[j + 1];
+    }
+    red[t] = strided_sum(npart, t, nb);
+    if (t <= j) col[t] = h;
+    if (t < j) {
+        cs[t] = csv;
+        sn[t] = snv;
     }
     __syncthreads();
     for (int off = TPB / 2; off > 0; off >>= 1) {
