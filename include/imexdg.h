@@ -78,9 +78,16 @@ typedef struct {
 } imx_mesh_desc;
 
 /* Physical constants (Sec. 2, Sec. 4) and the optional Rayleigh sponge of
- * Sec. 4.3: lambda(z) = sponge_lambda sin^2(pi/2 (z - zB)/(zT - zB)) for
- * z >= zB, relaxing the momentum towards rho * sponge_u in the explicit
- * (non-stiff) part; sponge_lambda = 0 switches it off.
+ * Sec. 4.3 (eq. damping), relaxing the momentum towards rho * sponge_u in the
+ * explicit (non-stiff) part; sponge_lambda = 0 switches it off. Its
+ * coefficient at a node is the largest of the top layer's
+ * lambda_z = sponge_lambda sin^2(pi/2 (z - zB)/(zT - zB)) for z >= zB and of
+ * the lateral layers' profiles of the same form over the first and the last
+ * sponge_xw of [0, Lx] and sponge_yw of [0, Ly] (0 = no lateral layer),
+ * rising from 0 at a layer's inner edge to sponge_lambda at the domain
+ * boundary (Lx, Ly: the mesh's extents). imx_solver_create fails with
+ * IMX_EINVAL if a width is negative or the two layers of a direction
+ * overlap.
  * slice != 0 selects the vertical-slice equations (Sec. 2, eq.
  * vertical_slice: d/dy = 0, v prognostic) on a mesh with one periodic
  * element in y, no refinement and flat ground: every step ends with the L2
@@ -91,6 +98,7 @@ typedef struct {
     double gamma, R, g, f;
     double sponge_zB, sponge_zT, sponge_lambda;
     double sponge_u[3];
+    double sponge_xw, sponge_yw;
     int slice;
 } imx_phys;
 

@@ -42,6 +42,11 @@ class Phys:
     sponge_zT: float = 1.0
     sponge_lam: float = 0.0
     sponge_u: tuple = (0.0, 0.0, 0.0)
+    # lateral layers of the same sin^2 form over the first and last sponge_xw
+    # of [0, Lx] and sponge_yw of [0, Ly] (0 = none); where layers overlap the
+    # largest coefficient applies
+    sponge_xw: float = 0.0
+    sponge_yw: float = 0.0
     # vertical-slice model (Sec. 2, eq. vertical_slice): d/dy = 0 with v
     # prognostic, on a mesh with one periodic element in y; every step ends
     # with the projection onto fields constant in y (slice_project)
@@ -180,12 +185,24 @@ def primitives(q, gamma):
     return rho, m, E, u, kin, p
 
 
-def sponge_coefficient(phys: Phys, z):
+def sponge_coefficient(phys: Phys, xyz, Lx, Ly):
+    """Rayleigh damping coefficient of eq. damping (Sec. 4.3) at points
+    xyz (..., 3): the top layer lam sin^2(pi/2 (z - zB)/(zT - zB)) for z >= zB
+    and, in the lateral buffer regions of widths sponge_xw and sponge_yw at
+    both ends of [0, Lx] and [0, Ly], the same profile of the depth into the
+    layer (0 at its inner edge, 1 at the boundary); the largest applies."""
+    z = xyz[..., 2]
     if phys.sponge_lam == 0.0:
         return np.zeros_like(z)
     s = np.clip((z - phys.sponge_zB) / (phys.sponge_zT - phys.sponge_zB), 0.0, None)
-    lam = phys.sponge_lam * np.sin(0.5 * np.pi * s) ** 2
-    return np.where(z >= phys.sponge_zB, lam, 0.0)
+    lam = np.where(z >= phys.sponge_zB, phys.sponge_lam * np.sin(0.5 * np.pi * s) ** 2, 0.0)
+    for d, (w, ext) in enumerate(((phys.sponge_xw, Lx), (phys.sponge_yw, Ly))):
+        if w <= 0.0:
+            continue
+        x = xyz[..., d]
+        depth = np.where(x < w, (w - x) / w, np.where(x > ext - w, (x - (ext - w)) / w, 0.0))
+        lam = np.maximum(lam, np.where(depth > 0.0, phys.sponge_lam * np.sin(0.5 * np.pi * depth) ** 2, 0.0))
+    return lam
 
 
 # --------------------------------------------------------- explicit residual
@@ -217,7 +234,7 @@ def explicit_residual(mesh: Mesh, phys: Phys, q):
     TS[3] -= WJ * rho * phys.g
     TS[4] -= WJ * rho * phys.g * u[2]
     if phys.sponge_lam != 0.0:
-        lam = sponge_coefficient(phys, mesh.xq[..., 2])
+        lam = sponge_coefficient(phys, mesh.xq, mesh.desc.Lx, mesh.desc.Ly)
         for c in range(3):
             TNS[1 + c] -= WJ * lam * (m[c] - rho * phys.sponge_u[c])
 

@@ -36,7 +36,8 @@ class imx_mesh_desc(ctypes.Structure):
 class imx_phys(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("R", ctypes.c_double), ("g", ctypes.c_double), ("f", ctypes.c_double),
                 ("sponge_zB", ctypes.c_double), ("sponge_zT", ctypes.c_double), ("sponge_lambda", ctypes.c_double),
-                ("sponge_u", ctypes.c_double * 3), ("slice", ctypes.c_int)]
+                ("sponge_u", ctypes.c_double * 3), ("sponge_xw", ctypes.c_double), ("sponge_yw", ctypes.c_double),
+                ("slice", ctypes.c_int)]
 
 
 class imx_numerics(ctypes.Structure):
@@ -182,7 +183,7 @@ class Mesh:
 
 def phys_struct(p: W.PhysSpec):
     return imx_phys(p.gamma, p.R, p.g, p.f, p.sponge_zB, p.sponge_zT, p.sponge_lam, (ctypes.c_double * 3)(*p.sponge_u),
-                    int(p.slice))
+                    p.sponge_xw, p.sponge_yw, int(p.slice))
 
 
 def num_struct(n: W.NumSpec, precision=IMX_FP64, inner_tol=1e-3):

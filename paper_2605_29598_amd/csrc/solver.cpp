@@ -834,6 +834,14 @@ imx_status imx_solver_create(const imx_mesh* mesh, const imx_phys* phys, const i
         return IMX_EINVAL;
     }
     CHK(validate_num(*num));
+    {
+        const imx_mesh_desc& d = mesh->m.desc;
+        if (!(phys->sponge_xw >= 0.0) || !(phys->sponge_yw >= 0.0) || 2.0 * phys->sponge_xw > d.Lx ||
+            2.0 * phys->sponge_yw > d.Ly) {
+            set_error("imx_solver_create: lateral sponge widths must be >= 0 and at most half the domain");
+            return IMX_EINVAL;
+        }
+    }
     if (phys->slice) {
         const imx_mesh_desc& d = mesh->m.desc;
         if (d.ny != 1 || !d.periodic_y || mesh->m.nh != 0 || mesh->m.deformed) {
@@ -1035,15 +1043,25 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
     }
     std::vector<double> spl;
     if (s->dm.sponge) {
-        // lambda(z) of the Rayleigh sponge at every node
+        // Rayleigh sponge coefficient at every node: the largest of the top
+        // layer's and the lateral layers' sin^2 profiles
         spl.resize(s->L);
         const double zB = s->phys.sponge_zB, zT = s->phys.sponge_zT, lam = s->phys.sponge_lambda;
+        const double ext[2] = {m.desc.Lx, m.desc.Ly}, wid[2] = {s->phys.sponge_xw, s->phys.sponge_yw};
+        auto profile = [lam](double t) {   // t in [0, 1]: depth into the layer
+            const double sn = std::sin(0.5 * M_PI * t);
+            return lam * sn * sn;
+        };
         for (int64_t i = 0; i < s->L; ++i) {
             const double zz = m.xyz[2 * s->L + i];
-            double v = 0.0;
-            if (zz >= zB) {
-                const double sn = std::sin(0.5 * M_PI * (zz - zB) / (zT - zB));
-                v = lam * sn * sn;
+            double v = zz >= zB ? profile((zz - zB) / (zT - zB)) : 0.0;
+            for (int d = 0; d < 2; ++d) {
+                if (wid[d] <= 0.0) continue;
+                const double x = m.xyz[d * s->L + i];
+                double t = 0.0;
+                if (x < wid[d]) t = (wid[d] - x) / wid[d];
+                else if (x > ext[d] - wid[d]) t = (x - (ext[d] - wid[d])) / wid[d];
+                if (t > 0.0) v = std::max(v, profile(t));
             }
             spl[i] = v;
         }

@@ -1,8 +1,11 @@
 """Long integrations of the vertical-slice inertia-gravity-wave tests of
-Secs. 4.1 and 4.2 on the library, with the geostrophic-imbalance measure (eq. egeo).
+Secs. 4.1 and 4.2 on the library, with the geostrophic-imbalance measure (eq. egeo),
+and of the benchmark flow over the bell mountain of Sec. 4.3.
 
     python -m paper_2605_29598_amd.experiments planetary --hours 96
     python -m paper_2605_29598_amd.experiments reference --hours 8
+    python -m paper_2605_29598_amd.experiments hill|hill_rotating --hours 8
+    python -m paper_2605_29598_amd.experiments column --dt 8 --hours 0.5
 
 `planetary`: 60000 x 10 km channel, a = 1000 km, dt = 10 s (the paper runs
 96 h and reports an imbalance below 1e-7 m s^-2). `reference`: 6000 x 10 km,
@@ -79,6 +82,97 @@ def run(kind, hours, every_hours, scheme, precision, load=None, save=None, dt=No
                "ms_per_step": 1e3 * wall / done if done else None, "wall_s": wall}
     print(json.dumps({"summary": summary}), file=out, flush=True)
     return summary, series
+
+
+def run_hill(rotating, hours, every_hours, scheme=W.R2, out=sys.stdout):
+    """The benchmark flow over the bell mountain of Sec. 4.3 (`hill_benchmark`):
+    one JSON line per interval with the relative mass change, max|w| and the
+    ranges the paper contours at 8 h: u - U and v on the nodes within 200 m of
+    z = 800 m, v on the nodes within 500 m of the sections y = 18 km and
+    y = 22 km; iterations and wall time per step; a summary line at the end."""
+    import torch
+    from . import binding as B
+    w = W.hill_benchmark(rotating=rotating, scheme=scheme)
+    mesh = B.Mesh(w.mesh)
+    sol = B.Solver(mesh, w.phys, w.num)
+    xyz = mesh.node_coords()
+    q0 = W.initial_state(w, xyz)
+    sol.set_state(q0)
+    mass0 = float((mesh.mass_diag() * q0[0]).sum())
+    x, y, z = xyz
+    near800 = np.abs(z - 800.0) <= 200.0
+    y18 = np.abs(y - 18e3) <= 500.0
+    y22 = np.abs(y - 22e3) <= 500.0
+    dofs = 5 * mesh.E * mesh.Np
+    nsteps = int(round(hours * 3600.0 / w.num.dt))
+    every = max(1, int(round(every_hours * 3600.0 / w.num.dt)))
+    done, wall, rec = 0, 0.0, {}
+
+    def rng(a):
+        return [float(a.min()), float(a.max())]
+
+    while done < nsteps:
+        n = min(every, nsteps - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = sol.step(n)
+        torch.cuda.synchronize()
+        dt_wall = time.perf_counter() - t0
+        wall += dt_wall
+        done += n
+        q = sol.get_state().cpu().numpy()
+        u, v, ww = q[1] / q[0], q[2] / q[0], q[3] / q[0]
+        rec = {"t_h": done * w.num.dt / 3600.0, "mass_rel": (sol.total_mass() - mass0) / mass0,
+               "max_abs_w": float(np.abs(ww).max()), "u_minus_U_z800": rng(u[near800] - w.U),
+               "v_z800": rng(v[near800]), "v_y18": rng(v[y18]), "v_y22": rng(v[y22]),
+               "picard_per_step": st.picard_iters / n, "gmres_per_step": st.gmres_iters / n,
+               "ms_per_step": 1e3 * dt_wall / n}
+        print(json.dumps(rec), file=out, flush=True)
+    summary = {"workload": w.name, "scheme": "R%d" % scheme, "hours": done * w.num.dt / 3600.0, "steps": done,
+               "dt": w.num.dt, "dof_updates_per_s": dofs * done / wall if wall > 0 else None,
+               "ms_per_step": 1e3 * wall / done if done else None, "wall_s": wall, "final": rec}
+    print(json.dumps({"summary": summary}), file=out, flush=True)
+    return summary
+
+
+def run_column(dt, hours, every_hours, nz=8, background="stratified", out=sys.stdout):
+    """A resting atmosphere in one periodic 4 x 4 km column of the benchmark
+    hill's height (16 km, slip walls at the bottom and the top, r = 4, nz
+    elements), no wind, no rotation, no sponge: the largest vertical velocity
+    and its height per interval. The rest state is not a discrete steady
+    state, so a small w appears at once; whether it stays bounded or grows
+    shows the stability of the stage solves and of the step at this dt."""
+    import torch
+    from . import binding as B
+    w = W.hill_benchmark(rotating=False)
+    w.mesh = W.MeshSpec(4e3, 4e3, 16e3, 1, 1, nz, 4)
+    w.phys = W.PhysSpec()
+    w.num = W.NumSpec(dt=dt)
+    w.U = 0.0
+    if background == "isothermal":
+        w.background, w.T0 = "isothermal", 250.0
+    mesh = B.Mesh(w.mesh)
+    sol = B.Solver(mesh, w.phys, w.num)
+    xyz = mesh.node_coords()
+    sol.set_state(W.initial_state(w, xyz))
+    nsteps = int(round(hours * 3600.0 / dt))
+    every = max(1, int(round(every_hours * 3600.0 / dt)))
+    done, rows = 0, []
+    while done < nsteps:
+        n = min(every, nsteps - done)
+        try:
+            sol.step(n)
+        except B.IMXError as e:
+            rows.append({"t_s": done * dt, "error": str(e)})
+            print(json.dumps(rows[-1]), file=out, flush=True)
+            break
+        done += n
+        q = sol.get_state().cpu().numpy()
+        ww = np.abs(q[3] / q[0])
+        i = np.unravel_index(ww.argmax(), ww.shape)
+        rows.append({"t_s": done * dt, "max_abs_w": float(ww.max()), "z_of_max": float(xyz[2][i])})
+        print(json.dumps(rows[-1]), file=out, flush=True)
+    return rows
 
 
 def _lagrange(nodes, t):
@@ -167,7 +261,9 @@ def convergence(hours, levels, scheme, nsx=1200, nsz=80, out=sys.stdout):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("kind", choices=["planetary", "reference", "convergence"])
+    ap.add_argument("kind", choices=["planetary", "reference", "convergence", "hill", "hill_rotating", "column"])
+    ap.add_argument("--nz", type=int, default=8, help="column: elements in z")
+    ap.add_argument("--background", choices=["stratified", "isothermal"], default="stratified")
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--hours", type=float, default=None)
     ap.add_argument("--every-hours", type=float, default=None)
@@ -180,7 +276,16 @@ def main(argv=None):
     if a.kind == "convergence":
         convergence(a.hours if a.hours is not None else 0.25, a.levels, W.R1 if a.scheme == "R1" else W.R2)
         return
+    if a.kind == "column":
+        dt = a.dt if a.dt is not None else 8.0
+        run_column(dt, a.hours if a.hours is not None else 0.5, a.every_hours if a.every_hours is not None else 0.05,
+                   a.nz, a.background)
+        return
     hours = a.hours if a.hours is not None else (96.0 if a.kind == "planetary" else 8.0)
+    if a.kind.startswith("hill"):
+        run_hill(a.kind == "hill_rotating", hours, a.every_hours if a.every_hours is not None else 1.0,
+                 W.R1 if a.scheme == "R1" else W.R2)
+        return
     every = a.every_hours if a.every_hours is not None else (1.0 if a.kind == "planetary" else 0.25)
     run(a.kind, hours, every, W.R1 if a.scheme == "R1" else W.R2, a.precision, a.load, a.save, a.dt)
 

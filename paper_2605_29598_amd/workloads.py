@@ -51,6 +51,8 @@ class PhysSpec:
     sponge_zT: float = 1.0
     sponge_lam: float = 0.0
     sponge_u: tuple = (0.0, 0.0, 0.0)
+    sponge_xw: float = 0.0   # widths of the lateral sponge layers at both ends of x and y (0 = none)
+    sponge_yw: float = 0.0
     slice: int = 0           # vertical-slice equations (one periodic element in y)
 
 
@@ -136,6 +138,26 @@ def orography(nx=64, ny=64, nz=24, degree=4, scheme=R2, refined=False):
         num=NumSpec(dt=dt, scheme=scheme),
         steps=500, background="stratified", T0=293.15, N=0.01, U=10.0,
         seed=3 if not refined else 4)
+
+
+def hill_benchmark(rotating=True, nx=30, ny=20, nz=8, degree=4, scheme=R2):
+    """Benchmark flow over orography of Sec. 4.3: a 60 x 40 x 16 km Gal-Chen box
+    over the bell mountain h0 / (1 + r^2/a^2) (h0 = 400 m, a = 1 km, centre
+    (30, 20) km), periodic in x and y; stratified rest-frame background
+    theta_ref = 293.15 K, N = 0.01, uniform wind U = 10 m/s along x; Rayleigh
+    damping in the first and last 20 km of x, the first and last 10 km of y
+    and the top 6 km, lambda*dt = 1.2; 30 x 20 x 8 elements at r = 4
+    (500 m effective resolution), dt = 8 s, 8 h; f = 1e-4 (rotating run) or 0.
+    With periodic y the geostrophic pressure correction of the rotating run
+    cannot be represented and is left out, as for the orography box."""
+    dt = 8.0
+    return Workload(
+        name="hill_benchmark%s_%dx%dx%d_r%d" % ("_rotating" if rotating else "", nx, ny, nz, degree),
+        mesh=MeshSpec(60e3, 40e3, 16e3, nx, ny, nz, degree, terrain=BELL, h0=400.0, a=1e3, xc=30e3, yc=20e3),
+        phys=PhysSpec(f=1e-4 if rotating else 0.0, sponge_zB=10e3, sponge_zT=16e3, sponge_lam=1.2 / dt,
+                      sponge_u=(10.0, 0.0, 0.0), sponge_xw=20e3, sponge_yw=10e3),
+        num=NumSpec(dt=dt, scheme=scheme),
+        steps=int(round(8 * 3600 / dt)), background="stratified", T0=293.15, N=0.01, U=10.0, seed=6)
 
 
 def igw_slice(nx=300, nz=20, degree=4, scheme=R2, planetary=False, dT=0.01):

@@ -1,7 +1,7 @@
-"""The slice runner end to end on the GPU at tiny model times: the reference
-channel and the planetary slice advance, report a finite imbalance and
-conserve mass, and the convergence study returns finite level differences
-that shrink under refinement."""
+"""The experiment runners end to end on the GPU at tiny model times: the
+reference channel and the planetary slice advance, report a finite imbalance
+and conserve mass, the convergence study returns finite level differences
+that shrink under refinement, and the benchmark hill advances."""
 import io
 import json
 
@@ -33,3 +33,18 @@ def test_convergence_study_shrinks():
     assert len(rows) == 2
     for k in ("l2_w", "l2_p"):
         assert 0 < rows[1][k] < rows[0][k], (k, rows)
+
+
+@pytest.mark.parametrize("rotating", [False, True])
+def test_hill_runner_short_run(rotating):
+    """The Sec. 4.3 benchmark hill (lateral and top sponges, bell mountain)
+    advances five steps: mass conserved, vertical motion over the hill, one
+    summary line."""
+    buf = io.StringIO()
+    summary = X.run_hill(rotating, 5 * 8.0 / 3600.0, 2 * 8.0 / 3600.0, W.R2, out=buf)
+    assert summary["steps"] == 5
+    fin = summary["final"]
+    assert abs(fin["mass_rel"]) < 1e-13
+    assert 0 < fin["max_abs_w"] < 10 and all(np.isfinite(fin["u_minus_U_z800"]))
+    lines = [json.loads(l) for l in buf.getvalue().splitlines()]
+    assert len(lines) == 4 and "summary" in lines[-1]

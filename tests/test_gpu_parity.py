@@ -77,9 +77,13 @@ def _state(om, seed):
 
 
 @pytest.mark.parametrize("name", list(MESHES))
-def test_explicit_residual_parity(name):
+@pytest.mark.parametrize("lateral", [False, True])
+def test_explicit_residual_parity(name, lateral):
     spec = MESHES[name]
-    phys = W.PhysSpec(f=1.3e-3, sponge_zB=1e3, sponge_zT=4e3, sponge_lam=0.01, sponge_u=(3.0, -1.0, 0.0))
+    # lateral: Rayleigh layers over the first and last quarter of x and third of y as well
+    wx, wy = (spec.Lx / 4, spec.Ly / 3) if lateral else (0.0, 0.0)
+    phys = W.PhysSpec(f=1.3e-3, sponge_zB=1e3, sponge_zT=4e3, sponge_lam=0.01, sponge_u=(3.0, -1.0, 0.0),
+                      sponge_xw=wx, sponge_yw=wy)
     sol, om, oph, _ = _pair(spec, phys)
     q = _state(om, 11)
     TNS, TS = dg.explicit_residual(om, oph, q)

@@ -82,6 +82,19 @@ def test_invalid_meshes_rejected():
         B.Mesh(W.MeshSpec(4e3, 4e3, 2e3, 0, 2, 2, 2))
 
 
+def test_lateral_sponge_widths_validated():
+    """Negative lateral sponge widths and layers that would overlap across the
+    domain are refused before any device call."""
+    B = _binding()
+    num = B.num_struct(W.NumSpec())
+    m = B.Mesh(W.MeshSpec(4e3, 2e3, 2e3, 2, 2, 2, 2))
+    for xw, yw in ((-1.0, 0.0), (0.0, -1.0), (2.1e3, 0.0), (0.0, 1.1e3)):
+        ph = B.phys_struct(W.PhysSpec(sponge_lam=0.01, sponge_zB=1e3, sponge_zT=2e3, sponge_xw=xw, sponge_yw=yw))
+        out = ctypes.c_void_p()
+        code = B.lib().imx_solver_create(m.h, ctypes.byref(ph), ctypes.byref(num), None, ctypes.byref(out))
+        assert code == B.IMX_EINVAL and b"sponge" in B.lib().imx_last_error(), (xw, yw)
+
+
 def test_slice_model_needs_a_slice_mesh():
     """The vertical-slice model is refused on a mesh with two elements in y
     (the check runs on the host before any device call)."""

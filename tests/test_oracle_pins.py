@@ -103,6 +103,42 @@ def test_printed_courant_numbers():
             assert abs(Ca - rec["C_adv"]) < 10.0 ** -rec["digits"]
 
 
+def test_hill_benchmark_dof_count():
+    # the Sec. 4.3 benchmark workload has the printed element and DoF counts
+    w = W.hill_benchmark()
+    rec = json.load(open(GOLDEN))["dofs"][0]
+    assert w.mesh.nx * w.mesh.ny * w.mesh.nz == rec["cells"] and w.mesh.degree == rec["r"]
+    assert diagnostics.dofs_per_scalar(rec["cells"], w.mesh.degree) == rec["dofs"]
+
+
+def test_sponge_profile():
+    # eq. damping: lam sin^2(pi/2 t) with t the depth into a layer; the lateral
+    # layers of Sec. 4.3 use the same profile; overlapping layers take the
+    # largest value (not the sum)
+    ph = dg.Phys(sponge_zB=10e3, sponge_zT=16e3, sponge_lam=0.15, sponge_xw=20e3, sponge_yw=10e3)
+    Lx, Ly = 60e3, 40e3
+    cases = [((30e3, 20e3, 5e3), 0.0),        # interior
+             ((0.0, 20e3, 5e3), 0.15),        # boundary of the x layer
+             ((60e3, 20e3, 5e3), 0.15),
+             ((10e3, 20e3, 5e3), 0.075),      # half way into a layer: sin^2(pi/4) = 1/2
+             ((50e3, 20e3, 5e3), 0.075),
+             ((20e3, 20e3, 5e3), 0.0),        # inner edge
+             ((30e3, 5e3, 5e3), 0.075),       # y layer
+             ((30e3, 0.0, 5e3), 0.15),
+             ((30e3, 20e3, 13e3), 0.075),     # top layer
+             ((30e3, 20e3, 16e3), 0.15),
+             ((10e3, 5e3, 13e3), 0.075),      # corner of three layers: the largest, not the sum
+             ((5e3, 5e3, 5e3), 0.15 * math.sin(0.375 * math.pi) ** 2),   # x depth 3/4 beats y depth 1/2
+             ((30e3, 20e3, 9e3), 0.0)]
+    xyz = np.array([c[0] for c in cases])
+    got = dg.sponge_coefficient(ph, xyz, Lx, Ly)
+    for (pt, want), g in zip(cases, got):
+        assert abs(g - want) < 1e-15, (pt, g, want)
+    # without lateral widths only the top layer remains
+    ph0 = dg.Phys(sponge_zB=10e3, sponge_zT=16e3, sponge_lam=0.15)
+    assert dg.sponge_coefficient(ph0, np.array([[0.0, 0.0, 5e3]]), Lx, Ly)[0] == 0.0
+
+
 def test_config_dof_and_element_counts():
     # nested 2:1 refinement around the hill: 12288 - 144 + 1152 - 144 + 1152 cells
     w = W.orography(32, 32, 12, 1, refined=True)
