@@ -1028,11 +1028,16 @@ struct ElemGeo {
     __device__ __forceinline__ R hi(int d) const { return d == 0 ? hi0 : (d == 1 ? hi1 : hi2); }
 };
 
-template <int N, typename R, bool AFF, int SCH>
+// VQ (affine, r = 3, paired with k_mv2w): instead of the three components of
+// (rho h)^k w, w[0] receives the element's own part of pass 2, its volume
+// term c_dt (W detJ)^{-1} sum_d D_d^T (W detJ / h_d (rho h)^k w_d) minus, for R2,
+// the gravity term c_dt g rho_l w_z; pass 2 then adds only the face terms
+template <int N, typename R, bool AFF, int SCH, bool VQ = false>
 __global__ void __launch_bounds__(threads_mv(N))
 k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
       const R* __restrict__ cr, const R* __restrict__ pk, R* __restrict__ w, R* __restrict__ FB, Geom<R> g,
       const Tab<N, R>* __restrict__ Tg, StageK sk, const int* __restrict__ ctrl) {
+    static_assert(!VQ || (AFF && N == 4), "the own-element part of pass 2 is formed on affine r = 3 meshes");
     if (ctrl && *ctrl != 0) return;   // the Krylov cycle has stopped
     constexpr int NP = N * N * N, NF = N * N, EPB = epb_mv(N);
     constexpr int NR = (6 * NF + NP - 1) / NP;   // face points per lane
@@ -1167,6 +1172,7 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
     // w = (I + beta J)^{-1} A^{-1} (-B p) [R2] or A^{-1}(-B p) [R1]; stored as
     // (rho h)^k w, the flux the second pass differentiates (so that it needs no
     // p^k), and kept plain in LDS for this element's face traces
+    R hq[3] = {0, 0, 0}, wz = 0;   // (rho h)^k w, w_z
     if (act) {
         const R cdt = (R)sk.c_dt, beta = (R)sk.beta;
         R v[3];
@@ -1186,9 +1192,11 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
         const R rh = (R)sk.hfac * s_pk[le][node];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            w[(size_t)(c * fs + o)] = rh * wv[c];
+            hq[c] = rh * wv[c];
+            if constexpr (!VQ) w[(size_t)(c * fs + o)] = hq[c];
             s_w[le][c][node] = wv[c];
         }
+        wz = wv[2];
     }
     __syncthreads();
     // face buffer: (rho h)^k (w . n dS) on this element's side of each face
@@ -1223,6 +1231,35 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
                 fbv = hk * wn;
             }
             FB[(size_t)(unsigned)(e * 6 + f) * NF + pt] = fbv;
+        }
+    }
+    if constexpr (VQ) {
+        // the own-element part of pass 2 from the line products in LDS (s_w is
+        // free once every lane has read its traces)
+        __syncthreads();
+        const R wj = T.W3[node] * eg.dJ;
+        if (act) {
+            s_w[le][0][node] = (wj * eg.hi0) * hq[0];
+            s_w[le][1][node] = (wj * eg.hi1) * hq[1];
+            s_w[le][2][node] = (wj * eg.hi2) * hq[2];
+        }
+        __syncthreads();
+        if (act) {
+            const int i = node % N, j = (node / N) % N, k = node / (N * N);
+            R dv = 0;
+#pragma unroll
+            for (int q = 0; q < N; ++q) dv += T.D[q][i] * s_w[le][0][q + N * (j + N * k)];
+#pragma unroll
+            for (int q = 0; q < N; ++q) dv += T.D[q][j] * s_w[le][1][i + N * (q + N * k)];
+#pragma unroll
+            for (int q = 0; q < N; ++q) dv += T.D[q][k] * s_w[le][2][i + N * (j + N * q)];
+            const R cdt = (R)sk.c_dt;
+            R qv = cdt * dv * (T.iW3[node] * eg.idJ);
+            if constexpr (SCH == 2) {
+                const R rho_l = (R)1 / (crv * wj);   // cr = 1 / (W detJ rho_l)
+                qv -= cdt * (R)sk.g * (rho_l * wz);
+            }
+            w[o] = qv;
         }
     }
 }
@@ -1346,10 +1383,14 @@ struct Wave4 {
     }
 };
 
-template <typename R, int SCH>
+// Pass 2 at r = 3 on affine meshes without hanging faces, paired with the VQ
+// form of pass 1: qv holds the element's own volume and gravity part, so this
+// pass adds the pressure term and the face terms from the two sides' face
+// buffers.
+template <typename R>
 __global__ void __launch_bounds__(256)
-k_mv2w(int nel, const R* __restrict__ p, const R* __restrict__ pscale, const R* __restrict__ hw,
-       const R* __restrict__ rlh, const R* __restrict__ FB, R* __restrict__ out, int dual,
+k_mv2w(int nel, const R* __restrict__ p, const R* __restrict__ pscale, const R* __restrict__ qw,
+       const R* __restrict__ FB, R* __restrict__ out, int dual,
        Geom<R> g, const Tab<4, R>* __restrict__ Tg, StageK sk, const int* __restrict__ ctrl) {
     if (ctrl && *ctrl != 0) return;
     constexpr int NP = 64, NF = 16;
@@ -1359,15 +1400,10 @@ k_mv2w(int nel, const R* __restrict__ p, const R* __restrict__ pscale, const R* 
     const int e = __builtin_amdgcn_readfirstlane((int)xcd_block(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6));
     if (e >= nel) return;
     const Wave4<R> W(threadIdx.x & 63);
-    const unsigned fs = (unsigned)g.E * NP, o = (unsigned)e * NP + W.lane;
-    R hv[3];   // (rho h)^k w
-#pragma unroll
-    for (int c = 0; c < 3; ++c) hv[c] = hw[(size_t)(c * fs + o)];
-    R rl = 0;   // rho_l / (rho h)^k
-    if constexpr (SCH == 2) rl = rlh[o];
+    const unsigned o = (unsigned)e * NP + W.lane;
+    const R qv = qw[o];   // own volume and gravity part, from pass 1
     const R pv = (pscale ? pscale[0] : (R)1) * p[o];
     const double* q8 = g.eg + (size_t)e * 8;
-    const R hi[3] = {(R)q8[3], (R)q8[4], (R)q8[5]};
     const R dJ = (R)q8[6], idJ = (R)q8[7];
     R uf[6];
 #pragma unroll
@@ -1381,22 +1417,12 @@ k_mv2w(int nel, const R* __restrict__ p, const R* __restrict__ pscale, const R* 
     R acc = 0;
 #pragma unroll
     for (int f = 0; f < 6; ++f) acc += T.f[f & 1][W.ind[f >> 1]] * uf[f];
-    // volume: contravariant (rho h)^k w, differentiated along each direction
     const R wj = T.W3[W.lane] * dJ;
-    R dv = 0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        R gq[4];
-        W.line((wj * hi[d]) * hv[d], d, gq);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) dv += T.D[q][W.ind[d]] * gq[q];
-    }
-    acc -= dv;
     const R iwj = T.iW3[W.lane] * idJ;
     const R cdt = (R)sk.c_dt;
     R res = -(pv * (R)sk.igm1);
     res -= cdt * acc * iwj;
-    if constexpr (SCH == 2) res -= cdt * (R)sk.g * rl * hv[2];   // rho_l w_z
+    res += qv;
     out[o] = dual ? -res * wj : -res;
 }
 
@@ -1761,7 +1787,7 @@ template void launch_pass2<float>(const DevMesh&, const HostTab&, const StageK&,
                                   const float*, float*, double, int, hipStream_t, const float*, int, double*,
                                   double*);
 
-template <typename R, int N, bool AFF, int SCH>
+template <typename R, int N, bool AFF, int SCH, bool VQ = false>
 static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
                  const R* pk, const R* rlh, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st,
                  const int* ctrl) {
@@ -1775,7 +1801,7 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
             m, st,
             [&](hipStream_t s) {
                 if (bf > 0)
-                    hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
+                    hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH, VQ>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
                                        (int)nf, x, xs, cr, pk, w, FB, geom<R>(m), T, sk, ctrl);
             },
             [&](hipStream_t s) {
@@ -1805,22 +1831,25 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
     }
 }
 
-template <typename R, int SCH>
-static void mv2w(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* rlh, const R* hw,
-                 const R* FB, R* out, int dual, hipStream_t st, const int* ctrl) {
+template <typename R>
+static void mv2w(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* qw, const R* FB, R* out,
+                 int dual, hipStream_t st, const int* ctrl) {
     const Tab<4, R>* T = (const Tab<4, R>*)tab_ptr<R>(m);
     const unsigned nb = (unsigned)((m.E + 3) / 4);
-    hipLaunchKernelGGL((k_mv2w<R, SCH>), dim3(nb), dim3(256), 0, st, (int)m.E, x, xs, hw, rlh, FB, out, dual,
-                       geom<R>(m), T, sk, ctrl);
+    hipLaunchKernelGGL((k_mv2w<R>), dim3(nb), dim3(256), 0, st, (int)m.E, x, xs, qw, FB, out, dual, geom<R>(m),
+                       T, sk, ctrl);
 }
 
 template <typename R>
 static void mv_dispatch(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
                         const R* pk, const R* rlh, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st,
                         const int* ctrl) {
-    if (out && m.n == 4 && !m.deformed && m.nh == 0) {
-        if (sk.scheme == 2) mv2w<R, 2>(m, sk, x, xs, rlh, w, FB, out, dual, st, ctrl);
-        else mv2w<R, 1>(m, sk, x, xs, rlh, w, FB, out, dual, st, ctrl);
+    // r = 3, affine, no hanging faces: pass 1 forms the own-element part of
+    // pass 2 (one field in w) and the wavefront pass 2 adds the face terms
+    if (m.n == 4 && !m.deformed && m.nh == 0) {
+        if (out) mv2w<R>(m, sk, x, xs, w, FB, out, dual, st, ctrl);
+        else if (sk.scheme == 2) mv_n<R, 4, true, 2, true>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);
+        else mv_n<R, 4, true, 1, true>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);
         return;
     }
 #define MV(NN)                                                                                            \
