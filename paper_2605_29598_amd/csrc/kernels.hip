@@ -1028,16 +1028,16 @@ struct ElemGeo {
     __device__ __forceinline__ R hi(int d) const { return d == 0 ? hi0 : (d == 1 ? hi1 : hi2); }
 };
 
-// VQ (affine, r = 3, paired with k_mv2w): instead of the three components of
+// VQ (paired with the VQ form of pass 2): instead of the three components of
 // (rho h)^k w, w[0] receives the element's own part of pass 2, its volume
-// term c_dt (W detJ)^{-1} sum_d D_d^T (W detJ / h_d (rho h)^k w_d) minus, for R2,
-// the gravity term c_dt g rho_l w_z; pass 2 then adds only the face terms
+// term c_dt (W detJ)^{-1} sum_d D_d^T (contravariant (rho h)^k w)_d minus, for
+// R2, the gravity term c_dt g rho_l w_z; pass 2 then adds the pressure and
+// face terms. rho (rho_l) is read only for R2 on terrain-following meshes.
 template <int N, typename R, bool AFF, int SCH, bool VQ = false>
 __global__ void __launch_bounds__(threads_mv(N))
 k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
-      const R* __restrict__ cr, const R* __restrict__ pk, R* __restrict__ w, R* __restrict__ FB, Geom<R> g,
-      const Tab<N, R>* __restrict__ Tg, StageK sk, const int* __restrict__ ctrl) {
-    static_assert(!VQ || (AFF && N == 4), "the own-element part of pass 2 is formed on affine r = 3 meshes");
+      const R* __restrict__ cr, const R* __restrict__ pk, const R* __restrict__ rho, R* __restrict__ w,
+      R* __restrict__ FB, Geom<R> g, const Tab<N, R>* __restrict__ Tg, StageK sk, const int* __restrict__ ctrl) {
     if (ctrl && *ctrl != 0) return;   // the Krylov cycle has stopped
     constexpr int NP = N * N * N, NF = N * N, EPB = epb_mv(N);
     constexpr int NR = (6 * NF + NP - 1) / NP;   // face points per lane
@@ -1234,37 +1234,48 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
         }
     }
     if constexpr (VQ) {
-        // the own-element part of pass 2 from the line products in LDS (s_w is
-        // free once every lane has read its traces)
+        // the own-element part of pass 2 from the contravariant (rho h)^k w in
+        // LDS (s_w is free once every lane has read its traces)
         __syncthreads();
-        const R wj = T.W3[node] * eg.dJ;
         if (act) {
-            s_w[le][0][node] = (wj * eg.hi0) * hq[0];
-            s_w[le][1][node] = (wj * eg.hi1) * hq[1];
-            s_w[le][2][node] = (wj * eg.hi2) * hq[2];
+            if constexpr (AFF) {
+                const R wj = T.W3[node] * eg.dJ;
+                s_w[le][0][node] = (wj * eg.hi0) * hq[0];
+                s_w[le][1][node] = (wj * eg.hi1) * hq[1];
+                s_w[le][2][node] = (wj * eg.hi2) * hq[2];
+            } else {
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) {
+                    R v = 0;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) v += G_gc<R>(g, fs, dd, c, o) * hq[c];
+                    s_w[le][dd][node] = v;
+                }
+            }
         }
         __syncthreads();
         if (act) {
-            const int i = node % N, j = (node / N) % N, k = node / (N * N);
-            R dv = 0;
-#pragma unroll
-            for (int q = 0; q < N; ++q) dv += T.D[q][i] * s_w[le][0][q + N * (j + N * k)];
-#pragma unroll
-            for (int q = 0; q < N; ++q) dv += T.D[q][j] * s_w[le][1][i + N * (q + N * k)];
-#pragma unroll
-            for (int q = 0; q < N; ++q) dv += T.D[q][k] * s_w[le][2][i + N * (j + N * q)];
+            const R dv = div_T<N>(&s_w[le][0][0], T, node);
             const R cdt = (R)sk.c_dt;
-            R qv = cdt * dv * (T.iW3[node] * eg.idJ);
-            if constexpr (SCH == 2) {
-                const R rho_l = (R)1 / (crv * wj);   // cr = 1 / (W detJ rho_l)
-                qv -= cdt * (R)sk.g * (rho_l * wz);
+            R qv;
+            if constexpr (AFF) {
+                qv = cdt * dv * (T.iW3[node] * eg.idJ);
+                if constexpr (SCH == 2) {
+                    const R rho_l = (R)1 / (crv * (T.W3[node] * eg.dJ));   // cr = 1 / (W detJ rho_l)
+                    qv -= cdt * (R)sk.g * (rho_l * wz);
+                }
+            } else {
+                qv = cdt * dv * g.iWJ[o];
+                if constexpr (SCH == 2) qv -= cdt * (R)sk.g * (rho[o] * wz);
             }
             w[o] = qv;
         }
     }
 }
 
-template <int N, typename R, bool AFF, int SCH>
+// VQ: hw[0] holds the element's own volume and gravity part formed by the VQ
+// form of pass 1; only the pressure and face terms are added here.
+template <int N, typename R, bool AFF, int SCH, bool VQ = false>
 __global__ void __launch_bounds__(threads_mv(N))
 k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
       const R* __restrict__ hw, const R* __restrict__ rlh, const R* __restrict__ FB,
@@ -1283,13 +1294,17 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
     const int e = act ? (elist ? elist[slot] : slot) : 0;
     const unsigned fs = (unsigned)g.E * NP, o = (unsigned)e * NP + node;
     R* U = &s_face[le][0];
-    R hv[3] = {0, 0, 0}, rl = 0, pv = 0;   // (rho h)^k w, rho_l / (rho h)^k
+    R hv[3] = {0, 0, 0}, rl = 0, pv = 0, qv = 0;   // (rho h)^k w, rho_l / (rho h)^k, own part
     ElemGeo<N, R, AFF> eg;
     if (act) {
         eg.load(g.eg, e);
+        if constexpr (VQ) {
+            qv = hw[o];
+        } else {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) hv[c] = hw[(size_t)(c * fs + o)];
-        if constexpr (SCH == 2) rl = rlh[o];
+            for (int c = 0; c < 3; ++c) hv[c] = hw[(size_t)(c * fs + o)];
+            if constexpr (SCH == 2) rl = rlh[o];
+        }
         pv = (pscale ? pscale[0] : (R)1) * p[o];
         // {(rho h)^k w} . n dS from the two sides' face buffers
 #pragma unroll
@@ -1311,7 +1326,8 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
             U[f * NF + pt] = v;
         }
         // contravariant (rho h)^k w for the volume term
-        if constexpr (AFF) {
+        if constexpr (VQ) {
+        } else if constexpr (AFF) {
             // the LDS copy of the tables is not visible before the first barrier
             const R wj = Tg->W3[node] * eg.dJ;
 #pragma unroll
@@ -1335,12 +1351,13 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
         split_node<N>(f >> 1, node, m, pt);
         acc += T.f[f & 1][m] * U[f * NF + pt];
     }
-    acc -= div_T<N>(&s_vol[le][0][0], T, node);
+    if constexpr (!VQ) acc -= div_T<N>(&s_vol[le][0][0], T, node);
     const R iwj = AFF ? T.iW3[node] * eg.idJ : g.iWJ[o];
     const R cdt = (R)sk.c_dt;
     R res = -(pv * (R)sk.igm1);
     res -= cdt * acc * iwj;
-    if constexpr (SCH == 2) res -= cdt * (R)sk.g * rl * hv[2];   // rho_l w_z
+    if constexpr (VQ) res += qv;
+    else if constexpr (SCH == 2) res -= cdt * (R)sk.g * rl * hv[2];   // rho_l w_z
     // z = -res = M^{-1} S (sc x); the dual form is S (sc x) = -res W detJ
     if (dual) {
         const R wj = AFF ? T.W3[node] * eg.dJ : g.WJ[o];
@@ -1802,7 +1819,7 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
             [&](hipStream_t s) {
                 if (bf > 0)
                     hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH, VQ>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
-                                       (int)nf, x, xs, cr, pk, w, FB, geom<R>(m), T, sk, ctrl);
+                                       (int)nf, x, xs, cr, pk, rho, w, FB, geom<R>(m), T, sk, ctrl);
             },
             [&](hipStream_t s) {
                 if (bs > 0)
@@ -1816,7 +1833,7 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
             m, st,
             [&](hipStream_t s) {
                 if (bf > 0)
-                    hipLaunchKernelGGL((k_mv2<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
+                    hipLaunchKernelGGL((k_mv2<N, R, AFF, SCH, VQ>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
                                        (int)nf, x, xs, (const R*)w, rlh, (const R*)FB, (const R*)FBh, out, dual,
                                        geom<R>(m), T, sk, ctrl);
             },
@@ -1855,11 +1872,11 @@ static void mv_dispatch(const DevMesh& m, const StageK& sk, const R* x, const R*
 #define MV(NN)                                                                                            \
     do {                                                                                                  \
         if (!m.deformed) {                                                                                \
-            if (sk.scheme == 2) mv_n<R, NN, true, 2>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);  \
-            else mv_n<R, NN, true, 1>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);                 \
+            if (sk.scheme == 2) mv_n<R, NN, true, 2, true>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);  \
+            else mv_n<R, NN, true, 1, true>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);                 \
         } else {                                                                                          \
-            if (sk.scheme == 2) mv_n<R, NN, false, 2>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl); \
-            else mv_n<R, NN, false, 1>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);                \
+            if (sk.scheme == 2) mv_n<R, NN, false, 2, true>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl); \
+            else mv_n<R, NN, false, 1, true>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);                \
         }                                                                                                 \
     } while (0)
     IMX_DISPATCH_N(m.n, MV)

@@ -340,18 +340,16 @@ static double field_bytes(const imx_solver* s, double nfields, bool geometry) {
     return b;
 }
 
-// algorithmic nodal fields of the matrix-vector product's two passes. Pass 1
-// reads x and rho_l (as cr) and writes (rho h)^k w (3); pass 2 reads x, w (3),
-// p^k and, for R2, rho_l, and writes S x (the p^k read of pass 1 for the face
-// buffer and the face buffers themselves are not counted). On affine r = 3
-// meshes without hanging faces pass 1 also reads p^k and writes the element's
-// own part of pass 2 (1 field) in place of w, and pass 2 reads x and that
-// field and writes S x.
-static bool mv_own_part(const imx_solver* s) { return s->dm.n == 4 && !s->dm.deformed && s->dm.nh == 0; }
-static double mv1_fields(const imx_solver* s) { return mv_own_part(s) ? 4.0 : 5.0; }
-static double mv2_fields(const imx_solver* s, int scheme) {
-    return mv_own_part(s) ? 3.0 : 6.0 + (scheme == 2 ? 1.0 : 0.0);
+// algorithmic bytes of the matrix-vector product's two passes. Pass 1 reads
+// x, rho_l (as cr) and p^k (and rho_l itself for R2 on terrain-following
+// meshes) and the stored geometry, and writes the element's own part of
+// pass 2 (1 field: volume divergence of (rho h)^k w and the R2 gravity term);
+// pass 2 reads x and that field (and W detJ^{-1} on terrain-following meshes)
+// and writes S x. The face buffers are not counted.
+static double mv1_bytes(const imx_solver* s, int scheme) {
+    return field_bytes(s, 4.0 + (s->mesh->deformed && scheme == 2 ? 1.0 : 0.0), true);
 }
+static double mv2_bytes(const imx_solver* s) { return field_bytes(s, 3.0 + (s->mesh->deformed ? 1.0 : 0.0), false); }
 
 // ------------------------------------------------------------ stage context
 struct StageCtx {
@@ -379,10 +377,10 @@ static void residual(imx_solver* s, const StageCtx& c, const double* x, const do
 // solve (s->b): the Krylov loop's own matrix-vector kernels and one axpby
 // instead of the right-hand-side passes
 static void residual_b(imx_solver* s, const StageCtx& c, const double* x, double* out) {
-    timed(s, IMX_K_PASS1, field_bytes(s, mv1_fields(s), true), [&] {
+    timed(s, IMX_K_PASS1, mv1_bytes(s, c.k.scheme), [&] {
         launch_mv1<double>(s->dm, c.k, x, nullptr, s->cr, c.rho, c.pk, s->w, s->FB, s->FBh, s->st);
     });
-    timed(s, IMX_K_PASS2, field_bytes(s, mv2_fields(s, c.k.scheme), true), [&] {
+    timed(s, IMX_K_PASS2, mv2_bytes(s), [&] {
         launch_mv2<double>(s->dm, c.k, x, nullptr, s->w, c.pk, c.rho, s->rlh, s->FB, s->FBh, out, 0, s->st);
     });
     timed(s, IMX_K_STAGE, 3 * (double)s->L * 8.0, [&] { launch_axpby(s->L, 1.0, s->b, -1.0, out, out, s->st); });
@@ -544,10 +542,10 @@ static imx_status gmres(imx_solver* s, const StageCtx& c, double* x, double bnor
     double beta = std::sqrt(s->hsc[0]);
     int its = 0;
     auto mv = [&](int, const double* xj, const double* xs, const float*, double* o, const int* ctrl) {
-        timed(s, IMX_K_PASS1, field_bytes(s, mv1_fields(s), true), [&] {
+        timed(s, IMX_K_PASS1, mv1_bytes(s, c.k.scheme), [&] {
             launch_mv1<double>(s->dm, c.k, xj, xs, s->cr, c.rho, c.pk, s->w, s->FB, s->FBh, s->st, ctrl);
         });
-        timed(s, IMX_K_PASS2, field_bytes(s, mv2_fields(s, c.k.scheme), true), [&] {
+        timed(s, IMX_K_PASS2, mv2_bytes(s), [&] {
             launch_mv2<double>(s->dm, c.k, xj, xs, s->w, c.pk, c.rho, s->rlh, s->FB, s->FBh, o, 0, s->st, ctrl);
         });
     };
@@ -589,10 +587,10 @@ static imx_status inner_cycle_f32(imx_solver* s, const StageK& k, double beta, d
     const int m = std::min(s->m, maxit);
     double* coef = s->dsc + imx_solver::S_COEF;
     auto mv = [&](int, const float* xj, const double*, const float* xs, float* o, const int* ctrl) {
-        timed(s, IMX_K_PASS1, field_bytes(s, mv1_fields(s), true) / 2, [&] {
+        timed(s, IMX_K_PASS1, mv1_bytes(s, k.scheme) / 2, [&] {
             launch_mv1<float>(s->dm, k, xj, xs, s->crf, s->rhof, s->pkf, s->wf, s->FBf, s->FBhf, s->st, ctrl);
         });
-        timed(s, IMX_K_PASS2, field_bytes(s, mv2_fields(s, k.scheme), true) / 2, [&] {
+        timed(s, IMX_K_PASS2, mv2_bytes(s) / 2, [&] {
             launch_mv2<float>(s->dm, k, xj, xs, s->wf, s->pkf, s->rhof, s->rlhf, s->FBf, s->FBhf, o, 0, s->st, ctrl);
         });
     };
@@ -1158,10 +1156,10 @@ imx_status imx_schur_apply(imx_solver* s, const double* pin, double* out) {
     if (!pin || !out) return IMX_EINVAL;
     const double a_ll = TAB.at[1][1];
     StageK k = stage_k(s, a_ll);
-    timed(s, IMX_K_PASS1, field_bytes(s, mv1_fields(s), true), [&] {
+    timed(s, IMX_K_PASS1, mv1_bytes(s, k.scheme), [&] {
         launch_mv1<double>(s->dm, k, pin, nullptr, s->cr, s->rho, s->p, s->w, s->FB, s->FBh, s->st);
     });
-    timed(s, IMX_K_PASS2, field_bytes(s, mv2_fields(s, k.scheme), true), [&] {
+    timed(s, IMX_K_PASS2, mv2_bytes(s), [&] {
         launch_mv2<double>(s->dm, k, pin, nullptr, s->w, s->p, s->rho, s->rlh, s->FB, s->FBh, out, 1, s->st);
     });
     HIPCHK(hipGetLastError());
