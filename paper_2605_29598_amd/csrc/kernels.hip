@@ -1028,12 +1028,13 @@ struct ElemGeo {
     __device__ __forceinline__ R hi(int d) const { return d == 0 ? hi0 : (d == 1 ? hi1 : hi2); }
 };
 
-// VQ (paired with the VQ form of pass 2): instead of the three components of
-// (rho h)^k w, w[0] receives the element's own part of pass 2, its volume
-// term c_dt (W detJ)^{-1} sum_d D_d^T (contravariant (rho h)^k w)_d minus, for
-// R2, the gravity term c_dt g rho_l w_z; pass 2 then adds the pressure and
-// face terms. rho (rho_l) is read only for R2 on terrain-following meshes.
-template <int N, typename R, bool AFF, int SCH, bool VQ = false>
+// Schur pass 1 inside the Krylov loop. From w it writes the face buffer
+// (rho h)^k w . n dS and, in w[0], the element's own part of pass 2: its
+// volume term c_dt (W detJ)^{-1} sum_d D_d^T (contravariant (rho h)^k w)_d
+// minus, for R2, the gravity term c_dt g rho_l w_z; pass 2 then adds the
+// pressure and face terms. rho (rho_l) is read only for R2 on
+// terrain-following meshes.
+template <int N, typename R, bool AFF, int SCH>
 __global__ void __launch_bounds__(threads_mv(N))
 k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
       const R* __restrict__ cr, const R* __restrict__ pk, const R* __restrict__ rho, R* __restrict__ w,
@@ -1169,9 +1170,9 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
             __syncthreads();
         }
     }
-    // w = (I + beta J)^{-1} A^{-1} (-B p) [R2] or A^{-1}(-B p) [R1]; stored as
-    // (rho h)^k w, the flux the second pass differentiates (so that it needs no
-    // p^k), and kept plain in LDS for this element's face traces
+    // w = (I + beta J)^{-1} A^{-1} (-B p) [R2] or A^{-1}(-B p) [R1]: (rho h)^k w
+    // in registers for the own part of pass 2, w plain in LDS for this
+    // element's face traces
     R hq[3] = {0, 0, 0}, wz = 0;   // (rho h)^k w, w_z
     if (act) {
         const R cdt = (R)sk.c_dt, beta = (R)sk.beta;
@@ -1193,7 +1194,6 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             hq[c] = rh * wv[c];
-            if constexpr (!VQ) w[(size_t)(c * fs + o)] = hq[c];
             s_w[le][c][node] = wv[c];
         }
         wz = wv[2];
@@ -1233,7 +1233,7 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
             FB[(size_t)(unsigned)(e * 6 + f) * NF + pt] = fbv;
         }
     }
-    if constexpr (VQ) {
+    {
         // the own-element part of pass 2 from the contravariant (rho h)^k w in
         // LDS (s_w is free once every lane has read its traces)
         __syncthreads();
@@ -1273,38 +1273,31 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
     }
 }
 
-// VQ: hw[0] holds the element's own volume and gravity part formed by the VQ
-// form of pass 1; only the pressure and face terms are added here.
-template <int N, typename R, bool AFF, int SCH, bool VQ = false>
+// Schur pass 2 inside the Krylov loop: qw[0] holds the element's own volume
+// and gravity part formed by pass 1; the pressure and face terms are added.
+template <int N, typename R, bool AFF>
 __global__ void __launch_bounds__(threads_mv(N))
 k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
-      const R* __restrict__ hw, const R* __restrict__ rlh, const R* __restrict__ FB,
+      const R* __restrict__ qw, const R* __restrict__ FB,
       const R* __restrict__ FBh, R* __restrict__ out, int dual, Geom<R> g, const Tab<N, R>* __restrict__ Tg,
       StageK sk, const int* __restrict__ ctrl) {
     if (ctrl && *ctrl != 0) return;
     constexpr int NP = N * N * N, NF = N * N, EPB = epb_mv(N);
     constexpr int NR = (6 * NF + NP - 1) / NP;
     __shared__ R s_face[EPB][6 * NF];
-    __shared__ R s_vol[EPB][3][NP];
     __shared__ Tab<N, R> T;
     load_tab<N, R>(Tg, &T);
     const int tid = threadIdx.x, le = elem_slot<NP>(tid), node = tid - le * NP;
     const int slot = (int)xcd_block(blockIdx.x, gridDim.x) * EPB + le;
     const bool act = le < EPB && slot < nel;
     const int e = act ? (elist ? elist[slot] : slot) : 0;
-    const unsigned fs = (unsigned)g.E * NP, o = (unsigned)e * NP + node;
+    const unsigned o = (unsigned)e * NP + node;
     R* U = &s_face[le][0];
-    R hv[3] = {0, 0, 0}, rl = 0, pv = 0, qv = 0;   // (rho h)^k w, rho_l / (rho h)^k, own part
+    R pv = 0, qv = 0;   // scaled x, own part from pass 1
     ElemGeo<N, R, AFF> eg;
     if (act) {
         eg.load(g.eg, e);
-        if constexpr (VQ) {
-            qv = hw[o];
-        } else {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) hv[c] = hw[(size_t)(c * fs + o)];
-            if constexpr (SCH == 2) rl = rlh[o];
-        }
+        qv = qw[o];
         pv = (pscale ? pscale[0] : (R)1) * p[o];
         // {(rho h)^k w} . n dS from the two sides' face buffers
 #pragma unroll
@@ -1325,22 +1318,6 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
             }
             U[f * NF + pt] = v;
         }
-        // contravariant (rho h)^k w for the volume term
-        if constexpr (VQ) {
-        } else if constexpr (AFF) {
-            // the LDS copy of the tables is not visible before the first barrier
-            const R wj = Tg->W3[node] * eg.dJ;
-#pragma unroll
-            for (int dd = 0; dd < 3; ++dd) s_vol[le][dd][node] = (wj * eg.hi(dd)) * hv[dd];
-        } else {
-#pragma unroll
-            for (int dd = 0; dd < 3; ++dd) {
-                R v = 0;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) v += G_gc<R>(g, fs, dd, c, o) * hv[c];
-                s_vol[le][dd][node] = v;
-            }
-        }
     }
     __syncthreads();
     if (!act) return;
@@ -1351,13 +1328,11 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
         split_node<N>(f >> 1, node, m, pt);
         acc += T.f[f & 1][m] * U[f * NF + pt];
     }
-    if constexpr (!VQ) acc -= div_T<N>(&s_vol[le][0][0], T, node);
     const R iwj = AFF ? T.iW3[node] * eg.idJ : g.iWJ[o];
     const R cdt = (R)sk.c_dt;
     R res = -(pv * (R)sk.igm1);
     res -= cdt * acc * iwj;
-    if constexpr (VQ) res += qv;
-    else if constexpr (SCH == 2) res -= cdt * (R)sk.g * rl * hv[2];   // rho_l w_z
+    res += qv;
     // z = -res = M^{-1} S (sc x); the dual form is S (sc x) = -res W detJ
     if (dual) {
         const R wj = AFF ? T.W3[node] * eg.dJ : g.WJ[o];
@@ -1369,19 +1344,13 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
 
 // =====================================================================
 // Pass 2 for r = 3 on affine meshes without hanging faces: one wavefront per
-// element (64 lanes = 4^3 nodes). The values along a line of nodes (the 4
-// nodes that share the two other indices) that the volume term differentiates
-// are exchanged between lanes by cross-lane permutes, so the only LDS use is
-// the basis tables and the only barrier the one after loading them. (Pass 1 in
-// this form, with its traces also taken through permutes, measured slower than
-// the LDS form above: 87 against 69 us on the 48,000-element channel.)
+// element (64 lanes = 4^3 nodes). Pass 1 has formed the element's own volume
+// and gravity part, so this pass adds the pressure term and the face terms
+// from the two sides' face buffers; the only LDS use is the basis tables and
+// the only barrier the one after loading them. (Pass 1 in a wavefront form,
+// with its traces taken through cross-lane permutes, measured slower than the
+// LDS form above: 87 against 69 us on the 48,000-element channel.)
 // =====================================================================
-template <typename R>
-__device__ __forceinline__ R line_get(R v, int lane, int d, int q) {
-    const int sh = 2 * d;
-    return __shfl(v, (lane & ~(3 << sh)) | (q << sh), 64);
-}
-
 template <typename R>
 struct Wave4 {
     int lane, ind[3];   // node index along x, y, z
@@ -1394,16 +1363,8 @@ struct Wave4 {
     __device__ __forceinline__ int point(int d) const {
         return d == 0 ? ind[1] + 4 * ind[2] : (d == 1 ? ind[0] + 4 * ind[2] : ind[0] + 4 * ind[1]);
     }
-    __device__ __forceinline__ void line(R v, int d, R out[4]) const {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) out[q] = line_get(v, lane, d, q);
-    }
 };
 
-// Pass 2 at r = 3 on affine meshes without hanging faces, paired with the VQ
-// form of pass 1: qv holds the element's own volume and gravity part, so this
-// pass adds the pressure term and the face terms from the two sides' face
-// buffers.
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_mv2w(int nel, const R* __restrict__ p, const R* __restrict__ pscale, const R* __restrict__ qw,
@@ -1804,10 +1765,9 @@ template void launch_pass2<float>(const DevMesh&, const HostTab&, const StageK&,
                                   const float*, float*, double, int, hipStream_t, const float*, int, double*,
                                   double*);
 
-template <typename R, int N, bool AFF, int SCH, bool VQ = false>
+template <typename R, int N, bool AFF, int SCH>
 static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
-                 const R* pk, const R* rlh, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st,
-                 const int* ctrl) {
+                 const R* pk, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st, const int* ctrl) {
     constexpr int EPB = epb_of(N), EPBM = epb_mv(N);
     const Tab<N, R>* T = (const Tab<N, R>*)tab_ptr<R>(m);
     const int64_t nf = m.ncoarse ? m.E - m.ncoarse : m.E, ns = m.ncoarse;
@@ -1818,7 +1778,7 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
             m, st,
             [&](hipStream_t s) {
                 if (bf > 0)
-                    hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH, VQ>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
+                    hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
                                        (int)nf, x, xs, cr, pk, rho, w, FB, geom<R>(m), T, sk, ctrl);
             },
             [&](hipStream_t s) {
@@ -1833,8 +1793,8 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
             m, st,
             [&](hipStream_t s) {
                 if (bf > 0)
-                    hipLaunchKernelGGL((k_mv2<N, R, AFF, SCH, VQ>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
-                                       (int)nf, x, xs, (const R*)w, rlh, (const R*)FB, (const R*)FBh, out, dual,
+                    hipLaunchKernelGGL((k_mv2<N, R, AFF>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
+                                       (int)nf, x, xs, (const R*)w, (const R*)FB, (const R*)FBh, out, dual,
                                        geom<R>(m), T, sk, ctrl);
             },
             [&](hipStream_t s) {
@@ -1859,24 +1819,20 @@ static void mv2w(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
 
 template <typename R>
 static void mv_dispatch(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
-                        const R* pk, const R* rlh, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st,
-                        const int* ctrl) {
-    // r = 3, affine, no hanging faces: pass 1 forms the own-element part of
-    // pass 2 (one field in w) and the wavefront pass 2 adds the face terms
-    if (m.n == 4 && !m.deformed && m.nh == 0) {
-        if (out) mv2w<R>(m, sk, x, xs, w, FB, out, dual, st, ctrl);
-        else if (sk.scheme == 2) mv_n<R, 4, true, 2, true>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);
-        else mv_n<R, 4, true, 1, true>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);
+                        const R* pk, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st, const int* ctrl) {
+    // r = 3, affine, no hanging faces: pass 2 runs one element per wavefront
+    if (out && m.n == 4 && !m.deformed && m.nh == 0) {
+        mv2w<R>(m, sk, x, xs, w, FB, out, dual, st, ctrl);
         return;
     }
 #define MV(NN)                                                                                            \
     do {                                                                                                  \
         if (!m.deformed) {                                                                                \
-            if (sk.scheme == 2) mv_n<R, NN, true, 2, true>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);  \
-            else mv_n<R, NN, true, 1, true>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);                 \
+            if (sk.scheme == 2) mv_n<R, NN, true, 2>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);  \
+            else mv_n<R, NN, true, 1>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);                 \
         } else {                                                                                          \
-            if (sk.scheme == 2) mv_n<R, NN, false, 2, true>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl); \
-            else mv_n<R, NN, false, 1, true>(m, sk, x, xs, cr, rho, pk, rlh, w, FB, FBh, out, dual, st, ctrl);                \
+            if (sk.scheme == 2) mv_n<R, NN, false, 2>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl); \
+            else mv_n<R, NN, false, 1>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);                \
         }                                                                                                 \
     } while (0)
     IMX_DISPATCH_N(m.n, MV)
@@ -1886,24 +1842,23 @@ static void mv_dispatch(const DevMesh& m, const StageK& sk, const R* x, const R*
 template <typename R>
 void launch_mv1(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
                 const R* pk, R* w, R* FB, R* FBh, hipStream_t st, const int* ctrl) {
-    mv_dispatch<R>(m, sk, x, xs, cr, rho, pk, (const R*)nullptr, w, FB, FBh, nullptr, 0, st, ctrl);
+    mv_dispatch<R>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, nullptr, 0, st, ctrl);
 }
 template <typename R>
 void launch_mv2(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* w, const R* pk,
-                const R* rho, const R* rlh, const R* FB, const R* FBh, R* out, int dual, hipStream_t st,
-                const int* ctrl) {
-    mv_dispatch<R>(m, sk, x, xs, (const R*)nullptr, rho, pk, rlh, (R*)w, (R*)FB, (R*)FBh, out, dual, st, ctrl);
+                const R* rho, const R* FB, const R* FBh, R* out, int dual, hipStream_t st, const int* ctrl) {
+    mv_dispatch<R>(m, sk, x, xs, (const R*)nullptr, rho, pk, (R*)w, (R*)FB, (R*)FBh, out, dual, st, ctrl);
 }
 template void launch_mv1<double>(const DevMesh&, const StageK&, const double*, const double*, const double*,
                                  const double*, const double*, double*, double*, double*, hipStream_t, const int*);
 template void launch_mv1<float>(const DevMesh&, const StageK&, const float*, const float*, const float*,
                                 const float*, const float*, float*, float*, float*, hipStream_t, const int*);
 template void launch_mv2<double>(const DevMesh&, const StageK&, const double*, const double*, const double*,
-                                 const double*, const double*, const double*, const double*, const double*, double*,
-                                 int, hipStream_t, const int*);
+                                 const double*, const double*, const double*, const double*, double*, int,
+                                 hipStream_t, const int*);
 template void launch_mv2<float>(const DevMesh&, const StageK&, const float*, const float*, const float*,
-                                const float*, const float*, const float*, const float*, const float*, float*, int,
-                                hipStream_t, const int*);
+                                const float*, const float*, const float*, const float*, float*, int, hipStream_t,
+                                const int*);
 
 size_t pass2_partial_count(const DevMesh& m) {
     const int e = m.n == 2 ? 16 : (m.n == 3 ? 9 : (m.n == 4 ? 4 : 2));

@@ -95,10 +95,11 @@ void launch_pass2(const DevMesh& m, const HostTab& t, const StageK& sk, const R*
 size_t pass2_partial_count(const DevMesh& m);
 
 // Schur complement inside the Krylov loop (no right-hand side):
-// launch_mv1: w and face buffers of x scaled by *xs (xs may be null), cr = 1 / (WJ rho_l);
-// w is stored as (rho h)^k w on the elements without a coarse hanging face;
+// launch_mv1: face buffers of x scaled by *xs (xs may be null), cr = 1 / (WJ rho_l);
+// w[0] receives each element's own volume and gravity part of pass 2 (the
+// elements owning a coarse hanging face store (rho h)^k w, three fields);
 // launch_mv2: out = M^{-1} S (xs x) (dual = 0) or S (xs x) (dual = 1), after
-// launch_mv1; rlh = rho_l / (rho h)^k (launch_ratio; read by R2 only).
+// launch_mv1.
 // With ctrl != null every workgroup returns at once while *ctrl != 0 (a
 // Krylov cycle that has stopped on the device).
 template <typename R>
@@ -106,11 +107,8 @@ void launch_mv1(const DevMesh& m, const StageK& sk, const R* x, const R* xs, con
                 const R* pk, R* w, R* FB, R* FBh, hipStream_t st, const int* ctrl = nullptr);
 template <typename R>
 void launch_mv2(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* w, const R* pk,
-                const R* rho, const R* rlh, const R* FB, const R* FBh, R* out, int dual, hipStream_t st,
+                const R* rho, const R* FB, const R* FBh, R* out, int dual, hipStream_t st,
                 const int* ctrl = nullptr);
-// rlh = rho / (hfac pk) per node (rho_l / (rho h)^k), and its binary32 copy when rlhf != null
-void launch_ratio(int64_t L, const double* rho, const double* pk, double hfac, double* rlh, float* rlhf,
-                  hipStream_t st);
 // cr = 1 / (WJ rho), and its binary32 copy when crf != null
 void launch_stage_coef(int64_t L, const double* rho, const double* WJ, double* cr, float* crf, hipStream_t st);
 void launch_final_sum(const double* partial, int nb, int nv, double* out, hipStream_t st);

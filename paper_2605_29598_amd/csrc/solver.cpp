@@ -110,8 +110,6 @@ struct imx_solver {
     float *Vf = nullptr, *zf = nullptr, *z1f = nullptr, *wf = nullptr, *FBf = nullptr, *FBhf = nullptr;
     float *rhof = nullptr, *pkf = nullptr, *WJf = nullptr, *Gf = nullptr, *nSf = nullptr, *xf = nullptr;
     double* cr = nullptr;    // 1 / (WJ rho_l) of the current stage
-    double* rlh = nullptr;   // rho_l / (rho h)^k of the current Picard iterate (second Schur pass, R2)
-    float* rlhf = nullptr;
     float* crf = nullptr;
     double* w3 = nullptr;    // tensor weights w_i w_j w_k of the nodes (Np)
     WSrc wsrc;               // affine meshes: Krylov weights from w3 and det J instead of WJ
@@ -188,7 +186,6 @@ static size_t layout(imx_solver* s, char* base) {
         dm.iWJ = D(L);
     }
     s->cr = D(L);
-    s->rlh = D(L);
     if (s->phys.sponge_lambda != 0.0) dm.sponge = D(L);
     s->y = D(5 * L);
     s->ybak = D(5 * L);
@@ -226,7 +223,6 @@ static size_t layout(imx_solver* s, char* base) {
         s->wf = F(3 * L);
         s->FBf = F((size_t)E * 6 * Nf);
         s->FBhf = F(std::max<int64_t>(m.nh, 1) * 4 * Nf);
-        s->rlhf = F(L);
         s->rhof = F(L);
         s->pkf = F(L);
         s->xf = F(s->Lp);
@@ -381,7 +377,7 @@ static void residual_b(imx_solver* s, const StageCtx& c, const double* x, double
         launch_mv1<double>(s->dm, c.k, x, nullptr, s->cr, c.rho, c.pk, s->w, s->FB, s->FBh, s->st);
     });
     timed(s, IMX_K_PASS2, mv2_bytes(s), [&] {
-        launch_mv2<double>(s->dm, c.k, x, nullptr, s->w, c.pk, c.rho, s->rlh, s->FB, s->FBh, out, 0, s->st);
+        launch_mv2<double>(s->dm, c.k, x, nullptr, s->w, c.pk, c.rho, s->FB, s->FBh, out, 0, s->st);
     });
     timed(s, IMX_K_STAGE, 3 * (double)s->L * 8.0, [&] { launch_axpby(s->L, 1.0, s->b, -1.0, out, out, s->st); });
 }
@@ -546,7 +542,7 @@ static imx_status gmres(imx_solver* s, const StageCtx& c, double* x, double bnor
             launch_mv1<double>(s->dm, c.k, xj, xs, s->cr, c.rho, c.pk, s->w, s->FB, s->FBh, s->st, ctrl);
         });
         timed(s, IMX_K_PASS2, mv2_bytes(s), [&] {
-            launch_mv2<double>(s->dm, c.k, xj, xs, s->w, c.pk, c.rho, s->rlh, s->FB, s->FBh, o, 0, s->st, ctrl);
+            launch_mv2<double>(s->dm, c.k, xj, xs, s->w, c.pk, c.rho, s->FB, s->FBh, o, 0, s->st, ctrl);
         });
     };
     while (true) {
@@ -591,7 +587,7 @@ static imx_status inner_cycle_f32(imx_solver* s, const StageK& k, double beta, d
             launch_mv1<float>(s->dm, k, xj, xs, s->crf, s->rhof, s->pkf, s->wf, s->FBf, s->FBhf, s->st, ctrl);
         });
         timed(s, IMX_K_PASS2, mv2_bytes(s) / 2, [&] {
-            launch_mv2<float>(s->dm, k, xj, xs, s->wf, s->pkf, s->rhof, s->rlhf, s->FBf, s->FBhf, o, 0, s->st, ctrl);
+            launch_mv2<float>(s->dm, k, xj, xs, s->wf, s->pkf, s->rhof, s->FBf, s->FBhf, o, 0, s->st, ctrl);
         });
     };
     const GState* G = nullptr;
@@ -679,10 +675,6 @@ static imx_status stage_solve(imx_solver* s, double a_ll, const double* rho, con
         timed(s, IMX_K_LAMBDA, field_bytes(s, 8, true),
               [&] { launch_lambda(s->dm, s->tab, k, p, u, rho, G0h, s->Gp, s->st); });
         StageCtx c{k, Fh, s->Gp, p, u, rho};
-        if (k.scheme == 2)
-            timed(s, IMX_K_STAGE, 3 * (double)L * 8.0, [&] {
-                launch_ratio(L, rho, p, k.hfac, s->rlh, s->mixed ? s->rlhf : nullptr, s->st);
-            });
         HIPCHK(hipMemcpyAsync(pn, p, L * sizeof(double), hipMemcpyDeviceToDevice, s->st));
         GmresOut go;
         CHK(pressure_solve(s, c, pn, go));
@@ -1147,7 +1139,6 @@ imx_status imx_implicit_setup(imx_solver* s, const double* rho_l, const double* 
     launch_stage_coef(s->L, s->rho, s->dm.WJ, s->cr, s->mixed ? s->crf : nullptr, s->st);
     HIPCHK(hipMemcpyAsync(s->p, p_lag, L, hipMemcpyDeviceToDevice, s->st));
     HIPCHK(hipMemcpyAsync(s->u, u_lag, 3 * L, hipMemcpyDeviceToDevice, s->st));
-    launch_ratio(s->L, s->rho, s->p, stage_k(s, TAB.at[1][1]).hfac, s->rlh, s->mixed ? s->rlhf : nullptr, s->st);
     return IMX_OK;
 }
 
@@ -1160,7 +1151,7 @@ imx_status imx_schur_apply(imx_solver* s, const double* pin, double* out) {
         launch_mv1<double>(s->dm, k, pin, nullptr, s->cr, s->rho, s->p, s->w, s->FB, s->FBh, s->st);
     });
     timed(s, IMX_K_PASS2, mv2_bytes(s), [&] {
-        launch_mv2<double>(s->dm, k, pin, nullptr, s->w, s->p, s->rho, s->rlh, s->FB, s->FBh, out, 1, s->st);
+        launch_mv2<double>(s->dm, k, pin, nullptr, s->w, s->p, s->rho, s->FB, s->FBh, out, 1, s->st);
     });
     HIPCHK(hipGetLastError());
     return IMX_OK;

@@ -693,19 +693,6 @@ void launch_stage_coef(int64_t L, const double* rho, const double* WJ, double* c
 __global__ void k_d2f(int64_t L, const double* __restrict__ in, float* __restrict__ out) {
     for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) out[x] = (float)in[x];
 }
-__global__ void k_ratio(int64_t L, const double* __restrict__ rho, const double* __restrict__ pk, double hfac,
-                        double* __restrict__ out, float* __restrict__ outf) {
-    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < L; i += (int64_t)gridDim.x * TPB) {
-        const double v = rho[i] / (hfac * pk[i]);
-        out[i] = v;
-        if (outf) outf[i] = (float)v;
-    }
-}
-void launch_ratio(int64_t L, const double* rho, const double* pk, double hfac, double* rlh, float* rlhf,
-                  hipStream_t st) {
-    hipLaunchKernelGGL(k_ratio, dim3(grid_for(L)), dim3(TPB), 0, st, L, rho, pk, hfac, rlh, rlhf);
-}
-
 void launch_d2f(int64_t L, const double* in, float* out, hipStream_t st) {
     hipLaunchKernelGGL(k_d2f, dim3(grid_for(L)), dim3(TPB), 0, st, L, in, out);
 }
