@@ -128,7 +128,39 @@ def operators(name, reps=20, seed=1):
     return out
 
 
+def steps(name, nsteps=3, mixed=False):
+    """Whole ARK2 steps of a workload from its initial state: one untimed step,
+    then `nsteps` timed ones (wall clock around synchronised calls)."""
+    import time
+    import torch
+    from . import binding as B
+    from . import workloads as W
+    w = WORKLOADS[name](W)
+    mesh = B.Mesh(w.mesh)
+    sol = B.Solver(mesh, w.phys, w.num, precision=B.IMX_MIXED if mixed else B.IMX_FP64)
+    sol.set_state(W.initial_state(w, mesh.node_coords()))
+    sol.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = sol.step(nsteps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / nsteps
+    dofs = 5 * mesh.E * mesh.Np
+    return {"workload": name, "precision": "fp32_inner" if mixed else "fp64", "elements": mesh.E, "dofs": dofs,
+            "dt": w.num.dt, "ms_per_step": 1e3 * dt, "dof_updates_per_s": dofs / dt,
+            "gmres_per_step": st.gmres_iters / nsteps, "picard_per_step": st.picard_iters / nsteps}
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "steps":
+        ap = argparse.ArgumentParser(description="ARK2 step rate of a full workload")
+        ap.add_argument("mode")
+        ap.add_argument("--workload", choices=list(WORKLOADS), required=True)
+        ap.add_argument("--steps", type=int, default=3)
+        ap.add_argument("--mixed", action="store_true")
+        a = ap.parse_args()
+        print(json.dumps(steps(a.workload, a.steps, a.mixed)))
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "operators":
         ap = argparse.ArgumentParser(description="operator timings on a full workload")
         ap.add_argument("mode")
