@@ -48,3 +48,14 @@ def test_hill_runner_short_run(rotating):
     assert 0 < fin["max_abs_w"] < 10 and all(np.isfinite(fin["u_minus_U_z800"]))
     lines = [json.loads(l) for l in buf.getvalue().splitlines()]
     assert len(lines) == 4 and "summary" in lines[-1]
+
+
+def test_column_runner_short_run():
+    """The resting-column runner advances a few steps and reports the largest
+    vertical velocity and its height (small: the initial imbalance only)."""
+    buf = io.StringIO()
+    rows = X.run_column(8.0, 5 * 8.0 / 3600.0, 2 * 8.0 / 3600.0, out=buf)
+    assert [round(r["t_s"]) for r in rows] == [16, 32, 40]
+    for r in rows:
+        assert 0 < r["max_abs_w"] < 1e-3 and 0 < r["z_of_max"] < 16e3
+    assert len(buf.getvalue().splitlines()) == 3
