@@ -160,6 +160,25 @@ def hill_benchmark(rotating=True, nx=30, ny=20, nz=8, degree=4, scheme=R2):
         steps=int(round(8 * 3600 / dt)), background="stratified", T0=293.15, N=0.01, U=10.0, seed=6)
 
 
+def hill_large(rotating=True, nx=50, ny=50, nz=50, degree=4, scheme=R2):
+    """Larger-scale flow over the bell mountain of Sec. 4.3: a 240 x 240 x 30 km
+    Gal-Chen box over h0 / (1 + r^2/a^2) (h0 = 100 m, a = 10 km, centre
+    (120, 120) km), periodic in x and y; isothermal hydrostatic background
+    T = 250 K (N = g / sqrt(cp T) = 0.0196), uniform wind U = 10 m/s along x;
+    Rayleigh damping in the first and last 60 km of x and y and the top 14 km,
+    lambda*dt = 1.2; 50^3 elements at r = 4, dt = 4 s, 8 h; f = 1e-4 (rotating
+    run) or 0, the geostrophic pressure correction left out as for the
+    benchmark hill."""
+    dt = 4.0
+    return Workload(
+        name="hill_large%s_%dx%dx%d_r%d" % ("_rotating" if rotating else "", nx, ny, nz, degree),
+        mesh=MeshSpec(240e3, 240e3, 30e3, nx, ny, nz, degree, terrain=BELL, h0=100.0, a=10e3, xc=120e3, yc=120e3),
+        phys=PhysSpec(f=1e-4 if rotating else 0.0, sponge_zB=16e3, sponge_zT=30e3, sponge_lam=1.2 / dt,
+                      sponge_u=(10.0, 0.0, 0.0), sponge_xw=60e3, sponge_yw=60e3),
+        num=NumSpec(dt=dt, scheme=scheme),
+        steps=int(round(8 * 3600 / dt)), background="isothermal", T0=250.0, U=10.0, seed=7)
+
+
 def igw_slice(nx=300, nz=20, degree=4, scheme=R2, planetary=False, dT=0.01):
     """Inertia-gravity waves of Secs. 4.1 and 4.2 in the vertical-slice form (one
     periodic element in y and the slice model, so d/dy = 0 while v stays

@@ -111,6 +111,18 @@ def test_hill_benchmark_dof_count():
     assert diagnostics.dofs_per_scalar(rec["cells"], w.mesh.degree) == rec["dofs"]
 
 
+def test_hill_large_matches_printed_setup():
+    # the larger-scale hill workload has the mesh, degree, dt, temperature and
+    # wind of the printed Sec. 4.3 record (whose Courant numbers the test above
+    # recomputes)
+    rec = [r for r in json.load(open(GOLDEN))["courant"] if "240x240x30 km" in r["cite"]][0]
+    w = W.hill_large()
+    assert (w.mesh.Lx, w.mesh.Ly, w.mesh.Lz) == (rec["Lx"], rec["Ly"], rec["Lz"])
+    assert (w.mesh.nx, w.mesh.ny, w.mesh.nz, w.mesh.degree) == (rec["nx"], rec["ny"], rec["nz"], rec["r"])
+    assert (w.num.dt, w.T0, w.U) == (rec["dt"], rec["T0"], rec["U"])
+    assert abs(w.phys.sponge_lam * w.num.dt - 1.2) < 1e-15
+
+
 def test_sponge_profile():
     # eq. damping: lam sin^2(pi/2 t) with t the depth into a layer; the lateral
     # layers of Sec. 4.3 use the same profile; overlapping layers take the
