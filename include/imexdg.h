@@ -157,7 +157,9 @@ void imx_mesh_destroy(imx_mesh* mesh);
 /* -------------------------------------------------------------- solver */
 /* Creates a solver for `mesh` (which must outlive it) on HIP stream
  * `hip_stream` (NULL = default stream) of the current device. No device
- * memory is allocated: query the workspace size and bind caller memory. */
+ * memory is allocated: query the workspace size and bind caller memory.
+ * IMX_EINVAL on invalid settings (checked before any device call),
+ * IMX_EHIP when no HIP device is current. */
 imx_status imx_solver_create(const imx_mesh* mesh, const imx_phys* phys, const imx_numerics* num,
                              void* hip_stream, imx_solver** out);
 imx_status imx_solver_workspace_bytes(const imx_solver* s, size_t* bytes);

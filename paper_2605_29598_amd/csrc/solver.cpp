@@ -859,7 +859,11 @@ imx_status imx_solver_create(const imx_mesh* mesh, const imx_phys* phys, const i
     s->phys = *phys;
     s->num = *num;
     s->st = (hipStream_t)stream;
-    hipGetDevice(&s->device);
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        set_error("imx_solver_create: no HIP device");
+        return IMX_EHIP;
+    }
     s->E = mesh->m.E;
     s->Np = mesh->m.Np;
     s->Nf = mesh->m.Nf;
