@@ -86,8 +86,9 @@ typedef struct {
  * sponge_xw of [0, Lx] and sponge_yw of [0, Ly] (0 = no lateral layer),
  * rising from 0 at a layer's inner edge to sponge_lambda at the domain
  * boundary (Lx, Ly: the mesh's extents). imx_solver_create fails with
- * IMX_EINVAL if a width is negative or the two layers of a direction
- * overlap.
+ * IMX_EINVAL if a width is negative, the two layers of a direction
+ * overlap, or a sponge is asked for (sponge_lambda != 0) with
+ * sponge_lambda negative or not finite or with sponge_zT <= sponge_zB.
  * slice != 0 selects the vertical-slice equations (Sec. 2, eq.
  * vertical_slice: d/dy = 0, v prognostic) on a mesh with one periodic
  * element in y, no refinement and flat ground: every step ends with the L2

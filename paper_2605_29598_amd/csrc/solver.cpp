@@ -844,6 +844,11 @@ imx_status imx_solver_create(const imx_mesh* mesh, const imx_phys* phys, const i
             set_error("imx_solver_create: lateral sponge widths must be >= 0 and at most half the domain");
             return IMX_EINVAL;
         }
+        if (phys->sponge_lambda != 0.0 &&
+            (!(phys->sponge_lambda > 0.0) || !std::isfinite(phys->sponge_lambda) || !(phys->sponge_zT > phys->sponge_zB))) {
+            set_error("imx_solver_create: sponge needs a finite sponge_lambda > 0 and sponge_zT > sponge_zB");
+            return IMX_EINVAL;
+        }
     }
     if (phys->slice) {
         const imx_mesh_desc& d = mesh->m.desc;

@@ -6,6 +6,7 @@ order, node coordinates, mass-matrix diagonal), so the GPU parity tests can
 feed both sides the same node-ordered inputs.
 """
 import ctypes
+import math
 import os
 import re
 
@@ -93,6 +94,20 @@ def test_lateral_sponge_widths_validated():
         out = ctypes.c_void_p()
         code = B.lib().imx_solver_create(m.h, ctypes.byref(ph), ctypes.byref(num), None, ctypes.byref(out))
         assert code == B.IMX_EINVAL and b"sponge" in B.lib().imx_last_error(), (xw, yw)
+
+
+def test_sponge_layer_validated():
+    """A sponge with its top at or below its base, or with a negative or
+    non-finite strength, is refused before any device call."""
+    B = _binding()
+    num = B.num_struct(W.NumSpec())
+    m = B.Mesh(W.MeshSpec(4e3, 2e3, 2e3, 2, 2, 2, 2))
+    for lam, zB, zT in ((0.01, 1e3, 1e3), (0.01, 2e3, 1e3), (-0.01, 1e3, 2e3), (math.inf, 1e3, 2e3),
+                        (math.nan, 1e3, 2e3)):
+        ph = B.phys_struct(W.PhysSpec(sponge_lam=lam, sponge_zB=zB, sponge_zT=zT))
+        out = ctypes.c_void_p()
+        code = B.lib().imx_solver_create(m.h, ctypes.byref(ph), ctypes.byref(num), None, ctypes.byref(out))
+        assert code == B.IMX_EINVAL and b"sponge" in B.lib().imx_last_error(), (lam, zB, zT)
 
 
 def test_slice_model_needs_a_slice_mesh():
