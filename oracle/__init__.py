@@ -20,8 +20,12 @@ tableau order conditions; the closed-form inertial oscillation; reduction to
 conservation, R1 = R2 fixed point, slice invariance; the DoF counts and
 Courant numbers printed in Sec. 4.
 
-Parity unpinned: the Rayleigh sponge term (its place in the IMEX split and its
-target state are a reading, not stated in the paper); the explicit Rusanov
+The Rayleigh sponge term of Sec. 4.3 is pinned by hand values of its profile
+and by its closed form on a free stream; its place in the IMEX split (the
+non-stiff part) and its target state (rho u_target) are a reading, not stated
+in the paper.
+
+Parity unpinned: the explicit Rusanov
 split of the energy dissipation into lambda/2 [rho kappa] (non-stiff) and
 lambda/2 [rho e] (stiff) is pinned only as implemented (brute force uses the
 same reading).

@@ -190,6 +190,32 @@ def test_free_stream(desc):
     assert max(np.abs(T0[0]).max(), np.abs(T0[1]).max()) < 1e-13 * scale
 
 
+def test_sponge_relaxes_momentum_towards_target():
+    # eq. damping on a free stream: the advective and pressure terms of a
+    # uniform flow vanish (test_free_stream), so the whole residual is the
+    # damping term: -W detJ lambda (m - rho u_target) in the non-stiff part,
+    # nothing in the mass and energy equations or in the stiff part. A wrong
+    # sign, a target u_target instead of rho u_target, or the term in the stiff
+    # part fails here.
+    mesh = Mesh(MeshDesc(4e3, 3e3, 2e3, 3, 2, 2, 3))
+    ph = dg.Phys(f=0.0, g=0.0, sponge_zB=1e3, sponge_zT=2e3, sponge_lam=0.05, sponge_xw=1e3,
+                 sponge_u=(10.0, 0.0, 0.0))
+    rho, u = 1.2, (10.0, -3.0, 0.0)
+    q = _uniform(mesh, rho, list(u), 1e5)
+    TNS, TS = dg.explicit_residual(mesh, ph, q)
+    lam = dg.sponge_coefficient(ph, mesh.xq, 4e3, 3e3)
+    assert (lam == 0.0).any() and (lam > 0.04).any()
+    WJ = mesh.W3 * mesh.detJ
+    scale = 1e5 * np.abs(mesh.nS).max()
+    for c in range(3):
+        want = -WJ * lam * rho * (u[c] - ph.sponge_u[c])
+        assert np.abs(TNS[1 + c] - want).max() < 1e-13 * scale, c
+    assert np.abs(TNS[2]).max() > 1e3 * 1e-13 * scale        # the y momentum is damped: +3.6 W detJ lambda
+    assert (TNS[2] >= -1e-13 * scale).all()                   # towards the target (v = -3 rises)
+    assert np.abs(TNS[0]).max() < 1e-13 * scale and np.abs(TNS[4]).max() < 1e-13 * scale
+    assert np.abs(TS).max() < 1e-13 * scale
+
+
 @pytest.mark.parametrize("desc", [
     MeshDesc(4e3, 4e3, 3e3, 2, 2, 3, 2),
     MeshDesc(4e3, 4e3, 2e3, 2, 2, 2, 2, ref_boxes=[(0, 1e3, 0, 1e3, 0, 0.5e3)]),
