@@ -26,7 +26,12 @@
  *    queued on the solver's HIP stream; a call that returns host values
  *    synchronises that stream.
  *  - Every function returns IMX_OK (0) or an error code and never aborts or
- *    prints; imx_last_error() describes the last failure on this thread.
+ *    prints. A call on a solver or a server that fails leaves its description
+ *    in that object (imx_solver_last_error, imx_server_last_error); calls with
+ *    no object yet (mesh and solver creation) leave it in imx_last_error(),
+ *    which describes the last failure on the calling thread.
+ *  - The library keeps no global mutable state besides that per-thread error
+ *    text: objects own everything else.
  */
 #ifndef IMEXDG_H
 #define IMEXDG_H
@@ -144,6 +149,9 @@ typedef struct {
 /* Builds the mesh and its geometry on the host. Errors: IMX_EINVAL for bad
  * sizes, unbalanced refinement or inverted elements. */
 imx_status imx_mesh_create(const imx_mesh_desc* desc, imx_mesh** out);
+/* The same call under the name of the box-mesh constructor (every mesh of the
+ * library is such a box, optionally refined and terrain-following). */
+imx_status imx_mesh_create_box(const imx_mesh_desc* desc, imx_mesh** out);
 /* Number of elements, nodes per element, number of coarse hanging faces and
  * whether the geometry is deformed (per-point Jacobians). */
 imx_status imx_mesh_info(const imx_mesh* mesh, int64_t* n_elem, int* nodes_per_elem,
@@ -183,7 +191,11 @@ imx_status imx_solver_set_numerics(imx_solver* s, const imx_numerics* num);
  * the device, not in the launch calls). */
 imx_status imx_solver_set_graphs(imx_solver* s, int enable);
 
-/* Copies the conserved state [5][E][Np] (device) into / out of the solver. */
+/* Copies the conserved state y = (rho, rho u, rho E) of Sec. 2 as nodal values
+ * [5][E][Np] (device, caller-owned, not retained) into / out of the solver's
+ * resident copy y^n that imx_step advances (Sec. 3: y^n -> y^{n+1}).
+ * Asynchronous on the solver's stream; IMX_ESTATE before a workspace is
+ * bound, IMX_EINVAL for a null pointer. */
 imx_status imx_set_state(imx_solver* s, const double* q_dev);
 imx_status imx_get_state(const imx_solver* s, double* q_dev);
 
@@ -214,7 +226,11 @@ imx_status imx_implicit_solve(imx_solver* s, const double* rho_l_dev, const doub
  * fails (IMX_ENOCONV, IMX_ENONFINITE) leaves the state of the last completed
  * step in place. */
 imx_status imx_step(imx_solver* s, int nsteps, imx_step_stats* stats);
-/* Total mass sum_K int_K rho (binary64); synchronises. */
+/* Total mass sum_K int_K rho of the bound state with the elements'
+ * Gauss-Legendre rule (the discrete mass that the DG scheme of Sec. 3
+ * conserves: the density equation is in flux form and b = b~ preserves linear
+ * invariants), accumulated in binary64 in a fixed order; *mass (host)
+ * receives it (NaN if the state holds one). Synchronises the stream. */
 imx_status imx_total_mass(imx_solver* s, double* mass);
 /* Geostrophic imbalance of the bound state (eq. egeo, Sec. 4.2, planetary-
  * scale test): the domain mean int |(1/rho) dp/dx - f v| dV / int dV, with
@@ -224,6 +240,9 @@ imx_status imx_total_mass(imx_solver* s, double* mass);
  * value; synchronises. IMX_EINVAL for a null pointer. */
 imx_status imx_geo_imbalance(imx_solver* s, double* egeo);
 void imx_solver_destroy(imx_solver* s);
+/* Description of the last failure of a call on this solver ("" if none);
+ * the text stays valid until the next failing call on it or its destruction. */
+const char* imx_solver_last_error(const imx_solver* s);
 
 /* ------------------------------------------------------------ timing */
 /* Kernel classes timed by imx_solver_timing. */
@@ -251,7 +270,11 @@ imx_status imx_solver_timing_report(imx_solver* s, int kind, double* total_ms, d
                                     int64_t* launches);
 
 /* ------------------------------------------------------------ serving */
-/* Ensemble server: integrations of different meshes, degrees and physics
+/* Serving form of the method (not a construct of the paper, which integrates
+ * one state at a time): many independent integrations of Sec. 3 (ARK2 steps
+ * of their own meshes and states), each exactly as imx_step would advance it
+ * alone.
+ * Ensemble server: integrations of different meshes, degrees and physics
  * share one device memory pool (the HBM budget). Requests wait in arrival
  * order; imx_server_tick admits every waiting request whose workspace fits
  * the free pool while fewer than max_running members run, and reaps members
@@ -294,8 +317,12 @@ imx_status imx_server_result(imx_server* sv, uint64_t id, double* q_host, imx_me
 imx_status imx_server_query(imx_server* sv, imx_server_stats* stats);
 /* Waits for running members, then destroys the server. */
 void imx_server_destroy(imx_server* sv);
+/* Description of the last failure of a call on this server ("" if none);
+ * valid until the next failing call on it or its destruction. A member's own
+ * failure is reported through imx_server_result. */
+const char* imx_server_last_error(const imx_server* sv);
 
-/* Description of the last error raised on the calling thread. */
+/* Description of the last error raised on the calling thread (by any call). */
 const char* imx_last_error(void);
 
 #ifdef __cplusplus

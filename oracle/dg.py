@@ -508,9 +508,11 @@ def stage_solve(mesh, phys, num: Numerics, rho_l, F, G0, p0, u0, a_ll):
 
 
 # ------------------------------------------------------------------ ARK2 step
-def ark2_step(mesh: Mesh, phys: Phys, num: Numerics, y):
+def ark2_step(mesh: Mesh, phys: Phys, num: Numerics, y, return_stages=False):
     """One IMEX-ARK2 step (Sec. 3): explicit density, implicit (u, p) stages,
-    final update with the shared weights b."""
+    final update with the shared weights b. With return_stages the stage
+    states Y_1..Y_3 and their explicit residuals (T_NS, T_S) are returned as
+    well (stats["stages"], stats["residuals"])."""
     gam, dt = phys.gamma, num.dt
     Mw = mesh.W3 * mesh.detJ
     Ys = [y]
@@ -537,6 +539,8 @@ def ark2_step(mesh: Mesh, phys: Phys, num: Numerics, y):
     ynew = y + dt * sum(B_W[l] * (T[l][0] + T[l][1]) for l in range(3)) / Mw
     if phys.slice:
         ynew = slice_project(mesh, ynew)
+    if return_stages:
+        stats["stages"], stats["residuals"] = Ys, T
     return ynew, stats
 
 

@@ -74,7 +74,10 @@ class imx_server_stats(ctypes.Structure):
 # name -> (restype, argtypes); the exported symbol set of include/imexdg.h
 SIGNATURES = {
     "imx_last_error": (ctypes.c_char_p, []),
+    "imx_solver_last_error": (ctypes.c_char_p, [_vp]),
+    "imx_server_last_error": (ctypes.c_char_p, [_vp]),
     "imx_mesh_create": (ctypes.c_int, [ctypes.POINTER(imx_mesh_desc), ctypes.POINTER(_vp)]),
+    "imx_mesh_create_box": (ctypes.c_int, [ctypes.POINTER(imx_mesh_desc), ctypes.POINTER(_vp)]),
     "imx_mesh_info": (ctypes.c_int, [_vp, _c_i64p, _c_ip, _c_i64p, _c_ip]),
     "imx_mesh_node_coords": (ctypes.c_int, [_vp, _vp]),
     "imx_mesh_mass_diag": (ctypes.c_int, [_vp, _vp]),
@@ -130,15 +133,23 @@ def lib():
 
 
 class IMXError(RuntimeError):
-    def __init__(self, code, where):
-        msg = lib().imx_last_error().decode(errors="replace")
+    def __init__(self, code, where, msg=None):
+        if msg is None:
+            msg = lib().imx_last_error().decode(errors="replace")
         super().__init__(f"{where}: status {code}: {msg}")
         self.code = code
 
 
-def check(code, where):
+def check(code, where, solver=None, server=None):
+    """Raises IMXError for a failed call; the message is the object's own last
+    error when the call acted on a solver or a server."""
     if code != IMX_OK:
-        raise IMXError(code, where)
+        msg = None
+        if solver is not None:
+            msg = lib().imx_solver_last_error(solver).decode(errors="replace")
+        elif server is not None:
+            msg = lib().imx_server_last_error(server).decode(errors="replace")
+        raise IMXError(code, where, msg)
 
 
 def _ptr(t):
@@ -222,33 +233,33 @@ class Solver:
 
     def set_numerics(self, num: W.NumSpec, precision=IMX_FP64, inner_tol=1e-3):
         nm = num_struct(num, precision, inner_tol)
-        check(lib().imx_solver_set_numerics(self.h, ctypes.byref(nm)), "imx_solver_set_numerics")
+        check(lib().imx_solver_set_numerics(self.h, ctypes.byref(nm)), "imx_solver_set_numerics", solver=self.h)
 
     def set_state(self, q):
         q = torch.as_tensor(q, dtype=torch.float64, device=self.device).contiguous()
-        check(lib().imx_set_state(self.h, _ptr(q)), "imx_set_state")
+        check(lib().imx_set_state(self.h, _ptr(q)), "imx_set_state", solver=self.h)
         self._hold = q
 
     def get_state(self):
         out = self._t(5, self.E, self.Np)
-        check(lib().imx_get_state(self.h, _ptr(out)), "imx_get_state")
+        check(lib().imx_get_state(self.h, _ptr(out)), "imx_get_state", solver=self.h)
         return out
 
     def explicit_residual(self, q):
         q = torch.as_tensor(q, dtype=torch.float64, device=self.device).contiguous()
         fNS, fS = self._t(5, self.E, self.Np), self._t(4, self.E, self.Np)
-        check(lib().imx_explicit_residual(self.h, _ptr(q), _ptr(fNS), _ptr(fS)), "imx_explicit_residual")
+        check(lib().imx_explicit_residual(self.h, _ptr(q), _ptr(fNS), _ptr(fS)), "imx_explicit_residual", solver=self.h)
         return fNS, fS
 
     def implicit_setup(self, rho_l, p_lag, u_lag):
         ts = [torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous() for a in (rho_l, p_lag, u_lag)]
-        check(lib().imx_implicit_setup(self.h, *[_ptr(t) for t in ts]), "imx_implicit_setup")
+        check(lib().imx_implicit_setup(self.h, *[_ptr(t) for t in ts]), "imx_implicit_setup", solver=self.h)
         self.stream.synchronize()
 
     def schur_apply(self, p):
         p = torch.as_tensor(p, dtype=torch.float64, device=self.device).contiguous()
         out = self._t(self.E, self.Np)
-        check(lib().imx_schur_apply(self.h, _ptr(p), _ptr(out)), "imx_schur_apply")
+        check(lib().imx_schur_apply(self.h, _ptr(p), _ptr(out)), "imx_schur_apply", solver=self.h)
         return out
 
     def implicit_solve(self, rho_l, F, G0, p0, u0):
@@ -256,16 +267,16 @@ class Solver:
         p, u = self._t(self.E, self.Np), self._t(3, self.E, self.Np)
         st = imx_solve_stats()
         code = lib().imx_implicit_solve(self.h, *[_ptr(t) for t in ts], _ptr(p), _ptr(u), ctypes.byref(st))
-        check(code, "imx_implicit_solve")
+        check(code, "imx_implicit_solve", solver=self.h)
         return p, u, st
 
     def step(self, nsteps=1):
         st = imx_step_stats()
-        check(lib().imx_step(self.h, int(nsteps), ctypes.byref(st)), "imx_step")
+        check(lib().imx_step(self.h, int(nsteps), ctypes.byref(st)), "imx_step", solver=self.h)
         return st
 
     def timing(self, enable):
-        check(lib().imx_solver_timing(self.h, int(bool(enable))), "imx_solver_timing")
+        check(lib().imx_solver_timing(self.h, int(bool(enable))), "imx_solver_timing", solver=self.h)
 
     def timing_report(self):
         """{kind: (total_ms, algorithmic_bytes, launches)} since timing was enabled."""
@@ -273,21 +284,21 @@ class Solver:
         for k, name in enumerate(KERNEL_KINDS):
             ms, by, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
             check(lib().imx_solver_timing_report(self.h, k, ctypes.byref(ms), ctypes.byref(by), ctypes.byref(n)),
-                  "imx_solver_timing_report")
+                  "imx_solver_timing_report", solver=self.h)
             out[name] = (ms.value, by.value, n.value)
         return out
 
     def total_mass(self):
         m = ctypes.c_double()
-        check(lib().imx_total_mass(self.h, ctypes.byref(m)), "imx_total_mass")
+        check(lib().imx_total_mass(self.h, ctypes.byref(m)), "imx_total_mass", solver=self.h)
         return m.value
 
     def set_graphs(self, enable):
-        check(lib().imx_solver_set_graphs(self.h, int(bool(enable))), "imx_solver_set_graphs")
+        check(lib().imx_solver_set_graphs(self.h, int(bool(enable))), "imx_solver_set_graphs", solver=self.h)
 
     def geo_imbalance(self):
         e = ctypes.c_double()
-        check(lib().imx_geo_imbalance(self.h, ctypes.byref(e)), "imx_geo_imbalance")
+        check(lib().imx_geo_imbalance(self.h, ctypes.byref(e)), "imx_geo_imbalance", solver=self.h)
         return e.value
 
     def __del__(self):
@@ -344,14 +355,14 @@ class Server:
         with torch.cuda.device(self.device):
             check(lib().imx_server_submit(self.h, ctypes.byref(d), ctypes.byref(ph), ctypes.byref(nm),
                                           q.ctypes.data_as(_vp), int(nsteps), ctypes.byref(rid)),
-                  "imx_server_submit")
+                  "imx_server_submit", server=self.h)
         self.shapes[rid.value] = q.shape
         return rid.value
 
     def tick(self):
         r, w = ctypes.c_int(), ctypes.c_int()
         with torch.cuda.device(self.device):
-            check(lib().imx_server_tick(self.h, ctypes.byref(r), ctypes.byref(w)), "imx_server_tick")
+            check(lib().imx_server_tick(self.h, ctypes.byref(r), ctypes.byref(w)), "imx_server_tick", server=self.h)
         return r.value, w.value
 
     def result(self, rid):
@@ -361,12 +372,12 @@ class Server:
         code = lib().imx_server_result(self.h, ctypes.c_uint64(rid), out.ctypes.data_as(_vp), ctypes.byref(st))
         if code == IMX_ESTATE:
             return None
-        check(code, "imx_server_result")
+        check(code, "imx_server_result", server=self.h)
         return out, st
 
     def query(self):
         st = imx_server_stats()
-        check(lib().imx_server_query(self.h, ctypes.byref(st)), "imx_server_query")
+        check(lib().imx_server_query(self.h, ctypes.byref(st)), "imx_server_query", server=self.h)
         return st
 
     def drain(self, poll_s=0.001):

@@ -11,6 +11,21 @@ namespace imx {
 enum FaceKind : int { WALL = 0, CONF = 1, FINE = 2, COARSE = 3 };
 
 void set_error(const std::string& msg);
+// Text of the last error raised on the calling thread and a counter that every
+// set_error advances, so that an entry point can tell whether it raised one.
+const std::string& thread_error();
+uint64_t error_generation();
+// Placed at the top of an entry point that acts on an object: when the call
+// raises an error, the object keeps a copy (its own last error, independent
+// of other objects and threads).
+struct ErrScope {
+    std::string* dst;
+    uint64_t gen;
+    explicit ErrScope(std::string* d) : dst(d), gen(error_generation()) {}
+    ~ErrScope() {
+        if (dst && error_generation() != gen) *dst = thread_error();
+    }
+};
 
 // 1D tables of the nodal Gauss-Legendre basis of degree r (n = r + 1 points)
 // on the reference interval [0, 1].

@@ -120,6 +120,7 @@ struct imx_server {
     Clock::time_point t_first_admit, t_last_done;
     std::vector<double> all_step_ms;
     double dof_updates = 0.0;
+    std::string err;   // last error raised by a call on this server
 };
 
 using imx::set_error;
@@ -147,6 +148,7 @@ imx_status imx_server_create(void* pool_dev, size_t pool_bytes, int max_running,
 
 imx_status imx_server_submit(imx_server* sv, const imx_mesh_desc* desc, const imx_phys* phys,
                              const imx_numerics* num, const double* q0, int nsteps, uint64_t* id) {
+    imx::ErrScope es_(sv ? &sv->err : nullptr);
     if (!sv || !desc || !phys || !num || !q0 || nsteps < 0 || !id) return IMX_EINVAL;
     std::unique_ptr<Member> m(new (std::nothrow) Member);
     if (!m) return IMX_ENOMEM;
@@ -207,7 +209,7 @@ static void member_main(imx_server* sv, Member* m, double* state_dev) {
         m->step_ms.push_back(ms_since(t0, t1));
     }
     m->status = rc;
-    if (rc != IMX_OK) m->err = imx_last_error();
+    if (rc != IMX_OK) m->err = imx_solver_last_error(m->solver);
     (void)imx_get_state(m->solver, state_dev);
     (void)hipMemcpyAsync(m->state.data(), state_dev, m->state.size() * 8, hipMemcpyDeviceToHost, m->stream);
     (void)hipStreamSynchronize(m->stream);
@@ -218,6 +220,7 @@ static void member_main(imx_server* sv, Member* m, double* state_dev) {
 extern "C" {
 
 imx_status imx_server_tick(imx_server* sv, int* n_running, int* n_waiting) {
+    imx::ErrScope es_(sv ? &sv->err : nullptr);
     if (!sv) return IMX_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
     (void)hipSetDevice(sv->device);
@@ -293,6 +296,7 @@ imx_status imx_server_tick(imx_server* sv, int* n_running, int* n_waiting) {
 }
 
 imx_status imx_server_result(imx_server* sv, uint64_t id, double* q_host, imx_member_stats* stats) {
+    imx::ErrScope es_(sv ? &sv->err : nullptr);
     if (!sv) return IMX_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
     auto it = sv->members.find(id);
@@ -323,6 +327,7 @@ imx_status imx_server_result(imx_server* sv, uint64_t id, double* q_host, imx_me
 }
 
 imx_status imx_server_query(imx_server* sv, imx_server_stats* st) {
+    imx::ErrScope es_(sv ? &sv->err : nullptr);
     if (!sv || !st) return IMX_EINVAL;
     std::lock_guard<std::mutex> lk(sv->mu);
     int64_t running = 0;
@@ -343,6 +348,8 @@ imx_status imx_server_query(imx_server* sv, imx_server_stats* st) {
     st->busy_seconds = sv->any_admit && sv->completed ? ms_since(sv->t_first_admit, sv->t_last_done) * 1e-3 : 0.0;
     return IMX_OK;
 }
+
+const char* imx_server_last_error(const imx_server* sv) { return sv ? sv->err.c_str() : ""; }
 
 void imx_server_destroy(imx_server* sv) {
     if (!sv) return;

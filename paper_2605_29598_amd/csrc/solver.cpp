@@ -17,7 +17,13 @@
 namespace imx {
 
 static thread_local std::string g_err;
-void set_error(const std::string& msg) { g_err = msg; }
+static thread_local uint64_t g_err_gen = 0;
+void set_error(const std::string& msg) {
+    g_err = msg;
+    ++g_err_gen;
+}
+const std::string& thread_error() { return g_err; }
+uint64_t error_generation() { return g_err_gen; }
 
 #define HIPCHK(call)                                                        \
     do {                                                                    \
@@ -92,8 +98,10 @@ struct imx_solver {
     hipStream_t st = nullptr;
     int device = 0;
     int64_t E = 0, L = 0, Lp = 0;
-    int Np = 0, Nf = 0, m = 30;
+    int Np = 0, Nf = 0, m = 30;   // m: GMRES restart length in use
+    int m_cap = 30;               // restart length the workspace was laid out for
     bool bound = false, mixed = false;
+    mutable std::string err;      // last error raised by a call on this solver
     size_t ws_bytes = 0;
     char* ws = nullptr;
     DevMesh dm;
@@ -205,7 +213,7 @@ static size_t layout(imx_solver* s, char* base) {
     s->w = D(3 * L);
     s->FB = D((size_t)E * 6 * Nf);
     s->FBh = D(std::max<int64_t>(m.nh, 1) * 4 * Nf);
-    s->V = D((size_t)(s->m + 1) * s->Lp);
+    s->V = D((size_t)(s->m_cap + 1) * s->Lp);
     s->z = D(s->Lp);
     s->z1 = D(s->Lp);
     s->b = D(L);
@@ -217,7 +225,7 @@ static size_t layout(imx_solver* s, char* base) {
         s->gst = base ? (GState*)(base + o) : nullptr;
     }
     if (s->mixed) {
-        s->Vf = F((size_t)(s->m + 1) * s->Lp);
+        s->Vf = F((size_t)(s->m_cap + 1) * s->Lp);
         s->zf = F(L);
         s->z1f = F(L);
         s->wf = F(3 * L);
@@ -784,6 +792,8 @@ extern "C" {
 
 const char* imx_last_error(void) { return imx::g_err.c_str(); }
 
+const char* imx_solver_last_error(const imx_solver* s) { return s ? s->err.c_str() : ""; }
+
 imx_status imx_mesh_create(const imx_mesh_desc* desc, imx_mesh** out) {
     if (!desc || !out) {
         set_error("imx_mesh_create: null argument");
@@ -805,6 +815,8 @@ imx_status imx_mesh_create(const imx_mesh_desc* desc, imx_mesh** out) {
     *out = m;
     return IMX_OK;
 }
+
+imx_status imx_mesh_create_box(const imx_mesh_desc* desc, imx_mesh** out) { return imx_mesh_create(desc, out); }
 
 imx_status imx_mesh_info(const imx_mesh* mesh, int64_t* n_elem, int* nodes_per_elem, int64_t* n_hanging,
                          int* deformed) {
@@ -879,7 +891,7 @@ imx_status imx_solver_create(const imx_mesh* mesh, const imx_phys* phys, const i
         set_error("imx_solver_create: mesh too large (9 E Np and 6 E Nf must stay below 2^31)");
         return IMX_EINVAL;
     }
-    s->m = num->gmres_restart;
+    s->m = s->m_cap = num->gmres_restart;
     s->mixed = num->precision == IMX_MIXED;
     s->dm.E = s->E;
     s->dm.Lp = s->Lp;
@@ -906,12 +918,14 @@ imx_status imx_solver_create(const imx_mesh* mesh, const imx_phys* phys, const i
 }
 
 imx_status imx_solver_workspace_bytes(const imx_solver* s, size_t* bytes) {
+    ErrScope es_(s ? &s->err : nullptr);
     if (!s || !bytes) return IMX_EINVAL;
     *bytes = s->ws_bytes;
     return IMX_OK;
 }
 
 imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
+    ErrScope es_(s ? &s->err : nullptr);
     if (!s || !dev) return IMX_EINVAL;
     drop_chunk_graphs(s);   // captured against the previous workspace
     if (bytes < s->ws_bytes) {
@@ -1099,13 +1113,16 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
 }
 
 imx_status imx_solver_set_numerics(imx_solver* s, const imx_numerics* num) {
+    ErrScope es_(s ? &s->err : nullptr);
     if (!s || !num) return IMX_EINVAL;
     CHK(validate_num(*num));
-    if (num->gmres_restart > s->m || (num->precision == IMX_MIXED && !s->mixed)) {
+    if (num->gmres_restart > s->m_cap || (num->precision == IMX_MIXED && !s->mixed)) {
         set_error("imx_solver_set_numerics: restart length / precision exceed the bound workspace");
         return IMX_EINVAL;
     }
     s->num = *num;
+    s->m = num->gmres_restart;
+    drop_chunk_graphs(s);   // captured for the previous cycle length and coefficients
     return IMX_OK;
 }
 
@@ -1119,18 +1136,21 @@ imx_status imx_solver_set_numerics(imx_solver* s, const imx_numerics* num) {
     } while (0)
 
 imx_status imx_set_state(imx_solver* s, const double* q) {
+    ErrScope es_(s ? &s->err : nullptr);
     NEED_BOUND(s);
     HIPCHK(hipMemcpyAsync(s->y, q, 5 * s->L * sizeof(double), hipMemcpyDeviceToDevice, s->st));
     return IMX_OK;
 }
 
 imx_status imx_get_state(const imx_solver* s, double* q) {
+    ErrScope es_(s ? &s->err : nullptr);
     NEED_BOUND(s);
     HIPCHK(hipMemcpyAsync(q, s->y, 5 * s->L * sizeof(double), hipMemcpyDeviceToDevice, s->st));
     return IMX_OK;
 }
 
 imx_status imx_explicit_residual(imx_solver* s, const double* q, double* fNS, double* fS) {
+    ErrScope es_(s ? &s->err : nullptr);
     NEED_BOUND(s);
     if (!q || !fNS || !fS) return IMX_EINVAL;
     const PhysK ph = phys_k(s);
@@ -1141,6 +1161,7 @@ imx_status imx_explicit_residual(imx_solver* s, const double* q, double* fNS, do
 }
 
 imx_status imx_implicit_setup(imx_solver* s, const double* rho_l, const double* p_lag, const double* u_lag) {
+    ErrScope es_(s ? &s->err : nullptr);
     NEED_BOUND(s);
     if (!rho_l || !p_lag || !u_lag) return IMX_EINVAL;
     const size_t L = s->L * sizeof(double);
@@ -1152,6 +1173,7 @@ imx_status imx_implicit_setup(imx_solver* s, const double* rho_l, const double* 
 }
 
 imx_status imx_schur_apply(imx_solver* s, const double* pin, double* out) {
+    ErrScope es_(s ? &s->err : nullptr);
     NEED_BOUND(s);
     if (!pin || !out) return IMX_EINVAL;
     const double a_ll = TAB.at[1][1];
@@ -1169,6 +1191,7 @@ imx_status imx_schur_apply(imx_solver* s, const double* pin, double* out) {
 imx_status imx_implicit_solve(imx_solver* s, const double* rho_l, const double* F, const double* G0,
                               const double* p0, const double* u0, double* pout, double* uout,
                               imx_solve_stats* stats) {
+    ErrScope es_(s ? &s->err : nullptr);
     NEED_BOUND(s);
     if (!rho_l || !F || !G0 || !p0 || !u0 || !pout || !uout) return IMX_EINVAL;
     const int64_t L = s->L;
@@ -1186,6 +1209,7 @@ imx_status imx_implicit_solve(imx_solver* s, const double* rho_l, const double* 
 }
 
 imx_status imx_step(imx_solver* s, int nsteps, imx_step_stats* stats) {
+    ErrScope es_(s ? &s->err : nullptr);
     NEED_BOUND(s);
     if (nsteps < 0) return IMX_EINVAL;
     imx_step_stats acc{};
@@ -1201,6 +1225,7 @@ imx_status imx_step(imx_solver* s, int nsteps, imx_step_stats* stats) {
 }
 
 imx_status imx_total_mass(imx_solver* s, double* mass) {
+    ErrScope es_(s ? &s->err : nullptr);
     NEED_BOUND(s);
     if (!mass) return IMX_EINVAL;
     double* bb = s->dsc + imx_solver::S_MISC;
@@ -1211,6 +1236,7 @@ imx_status imx_total_mass(imx_solver* s, double* mass) {
 }
 
 imx_status imx_geo_imbalance(imx_solver* s, double* egeo) {
+    ErrScope es_(s ? &s->err : nullptr);
     NEED_BOUND(s);
     if (!egeo) return IMX_EINVAL;
     double* bb = s->dsc + imx_solver::S_MISC;
@@ -1222,6 +1248,7 @@ imx_status imx_geo_imbalance(imx_solver* s, double* egeo) {
 }
 
 imx_status imx_solver_set_graphs(imx_solver* s, int enable) {
+    ErrScope es_(s ? &s->err : nullptr);
     if (!s) return IMX_EINVAL;
     s->graphs = enable != 0;
     if (!s->graphs) drop_chunk_graphs(s);
@@ -1229,6 +1256,7 @@ imx_status imx_solver_set_graphs(imx_solver* s, int enable) {
 }
 
 imx_status imx_solver_timing(imx_solver* s, int enable) {
+    ErrScope es_(s ? &s->err : nullptr);
     NEED_BOUND(s);
     timing_flush(s);
     if (enable) {
@@ -1243,6 +1271,7 @@ imx_status imx_solver_timing(imx_solver* s, int enable) {
 }
 
 imx_status imx_solver_timing_report(imx_solver* s, int kind, double* ms, double* bytes, int64_t* launches) {
+    ErrScope es_(s ? &s->err : nullptr);
     NEED_BOUND(s);
     if (kind < 0 || kind >= IMX_K_COUNT) return IMX_EINVAL;
     timing_flush(s);

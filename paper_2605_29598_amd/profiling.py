@@ -151,7 +151,83 @@ def steps(name, nsteps=3, mixed=False):
             "gmres_per_step": st.gmres_iters / nsteps, "picard_per_step": st.picard_iters / nsteps}
 
 
+def run(name, nsteps, mixed=False, scheme=None, out=None, every=10):
+    """A workload run to its stated length from its initial state, one step at
+    a time: per step the Picard and GMRES iterations, the wall time, max|w|
+    (diagnostic, from the device state) and, every `every` steps, the total
+    mass; one JSON line per step to `out` and a progress line to stdout."""
+    import time
+    import torch
+    from . import binding as B
+    from . import workloads as W
+    w = WORKLOADS[name](W)
+    if scheme is not None:
+        w.num.scheme = scheme
+    mesh = B.Mesh(w.mesh)
+    sol = B.Solver(mesh, w.phys, w.num, precision=B.IMX_MIXED if mixed else B.IMX_FP64)
+    sol.set_state(W.initial_state(w, mesh.node_coords()))
+    m0 = sol.total_mass()
+    fh = open(out, "w") if out else None
+    recs = []
+    t_run = time.perf_counter()
+    status = "ok"
+    for k in range(nsteps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            st = sol.step(1)
+        except B.IMXError as e:
+            status = f"step {k + 1}: {e}"
+            print(status, flush=True)
+            break
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0)
+        q = sol.get_state()
+        wmax = float((q[3] / q[0]).abs().max())
+        rec = {"step": k + 1, "ms": ms, "picard": st.picard_iters, "gmres": st.gmres_iters, "max_w": wmax}
+        if (k + 1) % every == 0 or k + 1 == nsteps:
+            rec["mass_rel_change"] = (sol.total_mass() - m0) / m0
+            print(json.dumps(rec), flush=True)
+        recs.append(rec)
+        if fh:
+            fh.write(json.dumps(rec) + "\n")
+            fh.flush()
+    wall = time.perf_counter() - t_run
+    dofs = 5 * mesh.E * mesh.Np
+    n = len(recs)
+    summary = {"workload": name, "precision": "fp32_inner" if mixed else "fp64",
+               "scheme": "R1" if w.num.scheme == B.IMX_R1 else "R2", "dt": w.num.dt,
+               "steps_asked": nsteps, "steps_done": n, "status": status, "elements": mesh.E, "dofs": dofs,
+               "wall_s": wall}
+    if n:
+        ms = [r["ms"] for r in recs]
+        summary.update({
+            "mean_ms_per_step": sum(ms) / n, "dof_updates_per_s": dofs * n / (sum(ms) * 1e-3),
+            "gmres_per_step_first10": sum(r["gmres"] for r in recs[:10]) / min(n, 10),
+            "gmres_per_step_last10": sum(r["gmres"] for r in recs[-10:]) / min(n, 10),
+            "picard_per_step_first10": sum(r["picard"] for r in recs[:10]) / min(n, 10),
+            "picard_per_step_last10": sum(r["picard"] for r in recs[-10:]) / min(n, 10),
+            "max_w_first": recs[0]["max_w"], "max_w_last": recs[-1]["max_w"],
+            "max_w_max": max(r["max_w"] for r in recs),
+            "mass_rel_change_last": recs[-1].get("mass_rel_change")})
+    if fh:
+        fh.close()
+    return summary
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "run":
+        ap = argparse.ArgumentParser(description="a workload run to its stated length, logged per step")
+        ap.add_argument("mode")
+        ap.add_argument("--workload", choices=list(WORKLOADS), required=True)
+        ap.add_argument("--steps", type=int, required=True)
+        ap.add_argument("--mixed", action="store_true")
+        ap.add_argument("--scheme", choices=["R1", "R2"], default=None)
+        ap.add_argument("--out", default=None, help="per-step JSON lines")
+        a = ap.parse_args()
+        sch = None if a.scheme is None else (1 if a.scheme == "R1" else 2)
+        print("SUMMARY " + json.dumps(run(a.workload, a.steps, a.mixed, sch, a.out)), flush=True)
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "steps":
         ap = argparse.ArgumentParser(description="ARK2 step rate of a full workload")
         ap.add_argument("mode")

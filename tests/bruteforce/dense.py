@@ -359,6 +359,50 @@ class Dense:
                     TS[1:, e] -= wq * fl[6:, None] * v[None, :]
         return TNS, TS
 
+    def euler_total_residual(self, q, gamma):
+        """Textbook DG residual of the full Euler equations (no sources):
+        int F(q) : grad psi - int_dK (F^ . n) psi with the flux tensor
+        F = (m, m u^T + p I, (E + p) u) and the Rusanov flux
+        F^ . n = {F(q) . n} + lambda/2 (q^- - q^+), lambda = max |u^+- . n|
+        applied to every conserved variable, rho E included; slip walls by
+        the mirror state. Written in total-energy form, without the split of
+        the energy flux and its dissipation into advective and stiff parts."""
+        E, Np = self.E, self.Np
+        out = np.zeros((5, E, Np))
+
+        def flux_tensor(s):
+            rho, m, Et = s[0], s[1:4], s[4]
+            u = m / rho
+            p = (gamma - 1) * (Et - 0.5 * rho * (u @ u))
+            Fm = np.zeros((5, 3))
+            Fm[0] = m
+            Fm[1:4] = np.outer(m, u) + p * np.eye(3)
+            Fm[4] = (Et + p) * u
+            return Fm, u
+
+        for e in range(E):
+            V, G, WJ, _ = self.vol[e]
+            for qp in range(V.shape[0]):
+                s = np.array([V[qp] @ q[fd, e] for fd in range(5)])
+                Fm, _ = flux_tensor(s)
+                out[:, e] += WJ[qp] * (Fm @ G[qp].T)
+            for pts in self.faces[e]:
+                for (v, nb, vn, wq, area) in pts:
+                    dS = np.linalg.norm(area)
+                    nh = area / dS
+                    sA = np.array([v @ q[fd, e] for fd in range(5)])
+                    if nb < 0:
+                        sB = sA.copy()
+                        sB[1:4] = sA[1:4] - 2 * (sA[1:4] @ nh) * nh
+                    else:
+                        sB = np.array([vn @ q[fd, nb] for fd in range(5)])
+                    FA, uA = flux_tensor(sA)
+                    FB, uB = flux_tensor(sB)
+                    lam = max(abs(uA @ nh), abs(uB @ nh))
+                    Fn = 0.5 * (FA + FB) @ area + 0.5 * lam * (sA - sB) * dS
+                    out[:, e] -= wq * Fn[:, None] * v[None, :]
+        return out
+
     def lam_vector(self, c_dt, u_nodal, p_nodal, gamma):
         """c_dt int_dK lambda/2 ((rho e)^- - (rho e)^+) psi, lambda from u traces."""
         out = np.zeros((self.E, self.Np))

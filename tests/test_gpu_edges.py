@@ -106,3 +106,49 @@ def test_schur_limits(f, g, scheme):
     assert np.abs(got - ref).max() < TOL * np.abs(ref).max()
     # a zero pressure gives exactly zero
     assert not np.any(_cpu(sol.schur_apply(np.zeros(shp))))
+
+
+def test_set_numerics_restart_takes_effect():
+    """A restart length lowered through imx_solver_set_numerics is the one the
+    Krylov loop uses: GMRES(5) set on a GMRES(30) solver gives the iteration
+    counts and the state of a solver created with GMRES(5), bit for bit."""
+    B = _B()
+    w = W.tiny_box()
+    gm = B.Mesh(w.mesh)
+    y0 = W.initial_state(w, gm.node_coords())
+    # dt = 20 s: about 20 Krylov iterations per stage solve, so the restart matters
+    n30 = W.NumSpec(dt=20.0, gmres_restart=30)
+    n5 = W.NumSpec(dt=20.0, gmres_restart=5)
+    a = B.Solver(gm, w.phys, n30)
+    a.set_numerics(n5)
+    b = B.Solver(gm, w.phys, n5)
+    c = B.Solver(gm, w.phys, n30)
+    for s in (a, b, c):
+        s.set_state(y0)
+    sa, sb, sc = a.step(1), b.step(1), c.step(1)
+    assert (sa.gmres_iters, sa.picard_iters) == (sb.gmres_iters, sb.picard_iters)
+    assert sa.gmres_iters != sc.gmres_iters      # the restart length does change the iterations
+    assert np.array_equal(_cpu(a.get_state()), _cpu(b.get_state()))
+    # raising it again up to the bound length is allowed, beyond it is not
+    a.set_numerics(n30)
+    with pytest.raises(B.IMXError) as e:
+        a.set_numerics(W.NumSpec(dt=20.0, gmres_restart=31))
+    assert e.value.code == B.IMX_EINVAL
+
+
+def test_last_error_is_per_solver():
+    """A failing call leaves its description in that solver only."""
+    B = _B()
+    w = W.tiny_box()
+    gm = B.Mesh(w.mesh)
+    a = B.Solver(gm, w.phys, w.num)
+    b = B.Solver(gm, w.phys, w.num)
+    with pytest.raises(B.IMXError) as e:
+        a.set_numerics(W.NumSpec(dt=2.0, gmres_restart=31))
+    assert b"restart" in B.lib().imx_solver_last_error(a.h)
+    assert b"restart" in str(e.value).encode()
+    assert B.lib().imx_solver_last_error(b.h) == b""
+    b.set_state(W.initial_state(w, gm.node_coords()))
+    b.step(1)                                     # a success on b leaves a's error in place
+    assert b"restart" in B.lib().imx_solver_last_error(a.h)
+    assert B.lib().imx_solver_last_error(b.h) == b""

@@ -17,6 +17,7 @@ from oracle import dg
 from oracle.diagnostics import geostrophic_imbalance
 from oracle.mesh import Mesh as OMesh, MeshDesc
 from paper_2605_29598_amd import workloads as W
+from tests.bars import check_state
 
 pytestmark = pytest.mark.gpu
 
@@ -50,13 +51,6 @@ def test_geo_imbalance_matches_oracle(name):
         assert abs(got - ref) < 1e-12 * ref, (name, seed, got, ref)
 
 
-def _scale(y, gamma):
-    rho = np.abs(y[0]).max()
-    p = np.abs(dg.primitives(y, gamma)[5]).max()
-    c = np.sqrt(gamma * p / rho)
-    return [rho, p / c, p / c, p / c, np.abs(y[4]).max()]
-
-
 @pytest.mark.parametrize("planetary,scheme", [(False, W.R2), (False, W.R1), (True, W.R2), (True, W.R1)])
 def test_slice_steps_match_oracle(planetary, scheme):
     B = _B()
@@ -72,9 +66,7 @@ def test_slice_steps_match_oracle(planetary, scheme):
     y = y0
     for _ in range(n):
         y, _ = dg.ark2_step(om, dg.Phys(**vars(w.phys)), dg.Numerics(**vars(w.num)), y)
-    sc = _scale(y, w.phys.gamma)
-    for t in range(5):
-        assert np.abs(got[t] - y[t]).max() < 1e-12 * sc[t], (t, np.abs(got[t] - y[t]).max() / sc[t])
+    check_state(got, y, om, w.num.dt, n, tag=f"slice planetary={planetary} R{scheme}")
     # the perturbation has moved the state: the comparison is not of y0 with itself
     assert np.abs(y[3]).max() > 0
     # slice model: the state after a step is constant along every y-line of nodes

@@ -104,6 +104,22 @@ def test_explicit_residual(name):
             assert rel(TS[fld], BS[fld]) < 1e-11, fld
 
 
+@pytest.mark.parametrize("name", ["periodic_r2", "walls_r3", "terrain_r2", "hanging_r2", "hanging_terrain_r2"])
+def test_split_residual_sums_to_textbook_euler(name):
+    """T_NS + T_S without sources is the textbook Rusanov DG residual of the
+    full Euler equations in total-energy form: the split of the energy flux
+    (kappa m + rho h u = (E + p) u) and of its dissipation
+    (lambda/2 [rho kappa] + lambda/2 [rho e] = lambda/2 [rho E]) between the
+    non-stiff and stiff parts loses and doubles nothing."""
+    mesh, dense, F = setup(name)
+    from paper_2605_29598_amd.workloads import conserved_from_primitive
+    q = conserved_from_primitive(F["rho"], F["u"], F["p"])
+    TNS, TS = dg.explicit_residual(mesh, dg.Phys(f=0.0, g=0.0), q)
+    ref = dense.euler_total_residual(q, GAM)
+    for fld in range(5):
+        assert rel(TNS[fld] + TS[fld], ref[fld]) < 1e-11, fld
+
+
 @pytest.mark.parametrize("name", ["periodic_r2", "hanging_r2", "terrain_r2"])
 def test_lambda_and_k_vectors(name):
     mesh, dense, F = setup(name)
