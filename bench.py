@@ -1,16 +1,23 @@
-"""Benchmark: IMEX-ARK2 steps of the rotating inertia-gravity-wave channel on one MI355X.
+"""Benchmark: IMEX-ARK2 steps of the stratified rotating flow over orography on one MI355X.
 
-Workload: 3000x1000x10 km channel, 120x40x10 hexahedra of degree 3 (48,000
-elements, 15.36 M DoF over the 5 conserved fields), N = 0.01 1/s, theta0 =
-300 K, U = 20 m/s, f = 1e-4 1/s, dt = 20 s, R2 treatment, GMRES / Picard
-tolerance 1e-10, binary64. A step is one whole IMEX-ARK2 step (three explicit
+Workload: 60x60x20 km Gal-Chen box over a Gaussian hill (h0 = 400 m,
+half-width 2 km), 64x64x24 hexahedra of degree 4 (98,304 elements, 61.44 M DoF
+over the 5 conserved fields, per-point Jacobians stored), theta_ref =
+293.15 K, N = 0.01 1/s, U = 10 m/s, f = 1e-4 1/s, Rayleigh sponge above 12 km
+with lambda dt = 1.2, dt = 4 s, R2 treatment, GMRES(30) / Picard tolerance
+1e-10, binary64. A step is one whole IMEX-ARK2 step (three explicit
 residuals, two implicit stages with their Picard and GMRES iterations, stage
 combinations, final update and mass check) on device-resident state.
 
-Prints one JSON line: DoF-updates/s (5 E Np per step), the roofline of the
-kernel class that takes the most device time in the timed region (algorithmic
-bytes / HIP-event time on the solver stream), and the CPU oracle timed on a
-bounded sample of the same workload.
+Prints one JSON line: DoF-updates/s (5 E Np per step); the roofline of the
+Schur-complement apply (pass 1 + pass 2, the operator that dominates the
+step) and every kernel class, timed on the same steps as the headline (the
+state at the start of the timed region is kept and the steps are replayed
+with a HIP event pair around every launch: the solver is deterministic, so
+the replay does the same iterations); the same steps with the binary32
+Krylov inner loop; the rotating IGW channel as a second workload; the served
+ensemble; and the CPU oracle on the host's cores on a bounded sample of the
+same workload.
 """
 import argparse
 import json
@@ -24,12 +31,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "DoF-updates/s per IMEX step (FP64 vs FP32-inner); operator GB/s; p99 latency"
+OPERATORS = ("explicit", "pass1", "pass2", "lambda")
 
 
-def measured_traffic(kind):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if the
-    kernels have not changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+def measured_traffic(workload, classes):
+    """HBM bytes per launch (summed over `classes`) from the committed
+    rocprofv3 --pmc summary of this workload, if the kernels have not changed
+    since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -37,43 +46,69 @@ def measured_traffic(kind):
     from paper_2605_29598_amd.profiling import kernel_source_hash
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    k = rec.get("kernels", {}).get(kind)
-    return None if k is None else k.get("bytes_per_launch")
+    tot = 0.0
+    for c in classes:
+        k = rec.get("kernels", {}).get(c)
+        if k is None:
+            return None
+        tot += k["bytes_per_launch"]
+    return tot
 
 
-def cpu_baseline(seconds_budget=30.0):
-    """Oracle (plain numpy, one thread) on a 12x4x10-element piece of the same
-    channel: identical element size, degree, dt, physics and tolerances."""
+def _oracle_worker(args):
+    """One host process: the oracle's ARK2 steps on its own copy of the sample."""
+    spec, phys, num, steps = args
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import dg
     from oracle.mesh import Mesh as OMesh, MeshDesc
     from paper_2605_29598_amd import workloads as W
-
-    w = W.igw_channel()
-    nx, ny = 12, 4
-    w.mesh.Lx, w.mesh.Ly = 3000e3 * nx / 120, 1000e3 * ny / 40
-    w.mesh.nx, w.mesh.ny = nx, ny
-    w.pert_xc = w.mesh.Lx / 2
-    om = OMesh(MeshDesc(**vars(w.mesh)))
-    q = W.initial_state(w, om.node_coords())
-    ph, num = dg.Phys(**vars(w.phys)), dg.Numerics(**vars(w.num))
-    steps, t_total = 0, 0.0
     with threadpool_limits(1):
-        while steps < 4 and t_total < seconds_budget:
-            t0 = time.perf_counter()
-            q, _ = dg.ark2_step(om, ph, num, q)
-            t_total += time.perf_counter() - t0
-            steps += 1
-    dofs = 5 * om.E * om.Np
-    return {"value": dofs * steps / t_total, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} ARK2 steps of a {nx}x{ny}x10-element piece of the channel "
-                      f"({om.E} elements, r=3, same dt/physics/tolerances), numpy on 1 thread, "
-                      f"{t_total:.1f} s"}
+        w = W.orography()
+        w.mesh = W.MeshSpec(**spec)
+        om = OMesh(MeshDesc(**spec))
+        q = W.initial_state(w, om.node_coords())
+        ph, nm = dg.Phys(**phys), dg.Numerics(**num)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            q, _ = dg.ark2_step(om, ph, nm, q)
+        el = time.perf_counter() - t0
+    return 5 * om.E * om.Np * steps, el
+
+
+def cpu_baseline(procs=None, n=2, steps=1):
+    """The oracle (plain numpy, one thread per process) on the host's cores:
+    `procs` processes (all cores the process may use, at most 16, the CPU
+    share of one GPU on the box) each advance their own copy of an n x n x 24
+    element piece of the orography box (same element size, degree, dt,
+    physics and tolerances, the hill at its centre, periodic) by `steps` ARK2
+    steps; the rate is the total DoF updates over the wall time of the pool."""
+    import multiprocessing as mp
+    from paper_2605_29598_amd import workloads as W
+    if procs is None:
+        procs = max(1, min(len(os.sched_getaffinity(0)), 16))
+    w = W.orography()
+    spec = dict(vars(w.mesh))
+    spec.update(Lx=60e3 * n / 64, Ly=60e3 * n / 64, nx=n, ny=n, xc=30e3 * n / 64, yc=30e3 * n / 64)
+    job = (spec, dict(vars(w.phys)), dict(vars(w.num)), steps)
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_oracle_worker, [job] * procs)
+    wall = time.perf_counter() - t0
+    dof_updates = sum(r[0] for r in res)
+    per_proc = [r[1] for r in res]
+    return {"value": dof_updates / wall, "unit": "DoF-updates/s", "cores": procs, "kind": "oracle",
+            "sample": f"{procs} processes x 1 thread, each {steps} ARK2 step(s) of its own {n}x{n}x24-element "
+                      f"piece of the orography box ({n * n * 24} elements, r = 4, same element size, dt, "
+                      f"physics, tolerances; hill at the centre, periodic); wall {wall:.1f} s, "
+                      f"per-process step time {min(per_proc):.1f}-{max(per_proc):.1f} s"}
 
 
 def field_errors(a, b, gamma=1.4):
-    """Max error per conserved field, relative to rho, p/c (momentum) and rho E scales."""
+    """Max error per conserved field against its own maximum, and against the
+    tolerance-mode scale (momentum in p / c: two solves that stop at a relative
+    tolerance tol may differ by tol p / c in momentum)."""
     import numpy as np
     rho = np.abs(b[0]).max()
     kin = 0.5 * (b[1] ** 2 + b[2] ** 2 + b[3] ** 2) / b[0]
@@ -81,46 +116,103 @@ def field_errors(a, b, gamma=1.4):
     c = math.sqrt(gamma * p / rho)
     scale = [rho, p / c, p / c, p / c, np.abs(b[4]).max()]
     names = ["rho", "rho_u", "rho_v", "rho_w", "rho_E"]
-    return {names[t]: float(np.abs(a[t] - b[t]).max() / scale[t]) for t in range(5)}
+    own = {names[t]: float(np.abs(a[t] - b[t]).max() / np.abs(b[t]).max()) for t in range(5)}
+    tol = {names[t]: float(np.abs(a[t] - b[t]).max() / scale[t]) for t in range(5)}
+    return {"vs_own_max": own, "vs_tolerance_scale": tol}
 
 
-def kernel_pass(sol, steps):
-    """{class: (ms, algorithmic bytes, launches)} over `steps` further steps,
-    and their GMRES iteration count."""
+def timed_steps(sol, steps):
+    """Wall time of `steps` steps with nothing else queued; iteration counts."""
     import torch
     torch.cuda.synchronize()
-    sol.timing(True)
-    gm = 0
+    picard = gmres = 0
+    t0 = time.perf_counter()
     for _ in range(steps):
-        gm += sol.step(1).gmres_iters
+        st = sol.step(1)
+        picard += st.picard_iters
+        gmres += st.gmres_iters
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, picard, gmres
+
+
+def kernel_replay(sol, q_start, steps):
+    """The same steps again from the saved state with a HIP event pair around
+    every launch on the solver's stream: {class: (ms, bytes, launches)} and
+    the iteration counts of the replay."""
+    import torch
+    sol.set_state(q_start)
+    torch.cuda.synchronize()
+    sol.timing(True)
+    picard = gmres = 0
+    for _ in range(steps):
+        st = sol.step(1)
+        picard += st.picard_iters
+        gmres += st.gmres_iters
     torch.cuda.synchronize()
     rep = sol.timing_report()
     sol.timing(False)
-    return rep, gm
+    return rep, picard, gmres
 
 
-def mixed_run(w, mesh, q0, args, ref_state, dofs):
-    """Same steps with the binary32 Krylov inner loop (binary64 defect
-    correction to the same tolerance), timed the same way."""
+def roofline_of(rep, classes, steps, traffic, note):
+    ms = sum(rep[c][0] for c in classes)
+    by = sum(rep[c][1] for c in classes)
+    n = rep[classes[0]][2]
+    achieved = by / (ms * 1e-3) / 1e9
+    return {"kernel": " + ".join(classes), "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "avg_launch_us": 1e3 * ms / max(n, 1), "algorithmic_bytes_per_launch": by / max(n, 1),
+            "launches_per_step": n / steps, "timing": note}
+
+
+def kernels_block(rep, steps):
+    out = {}
+    for k, v in rep.items():
+        if not v[2]:
+            continue
+        gbs = v[1] / (v[0] * 1e-3) / 1e9 if v[0] > 0 else 0.0
+        out[k] = {"ms_per_step": round(v[0] / steps, 3), "GB_per_s": round(gbs, 1),
+                  "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 3), "avg_launch_us": round(1e3 * v[0] / v[2], 1),
+                  "launches_per_step": round(v[2] / steps, 1)}
+    return out
+
+
+def run_workload(w, args, precision, ref_state=None, replay=True):
+    """Warm-up, timed steps, and (replay) the kernel-timed replay of the same
+    steps. Returns the result block and the final state."""
     import torch
     from paper_2605_29598_amd import binding as B
-    sol = B.Solver(mesh, w.phys, w.num, device="cuda:0", precision=B.IMX_MIXED, inner_tol=1e-3)
+    mesh = B.Mesh(w.mesh)
+    sol = B.Solver(mesh, w.phys, w.num, device="cuda:0", precision=precision, inner_tol=1e-3)
+    q0 = W_initial(w, mesh)
     sol.set_state(q0)
-    for _ in range(args.warmup):
+    dofs = 5 * mesh.E * mesh.Np
+    for i in range(args.warmup):
         sol.step(1)
-    torch.cuda.synchronize()
-    gm = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        gm += sol.step(1).gmres_iters
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    err = field_errors(sol.get_state().cpu().numpy(), ref_state)
-    rep, _ = kernel_pass(sol, args.steps)
-    return {"value": dofs * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
-            "gmres_inner_per_step": gm / args.steps, "inner_tol": 1e-3,
-            "max_rel_error_vs_fp64": err,
-            "kernels_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in rep.items() if v[2]}}
+    q_start = sol.get_state().clone()
+    el, picard, gmres = timed_steps(sol, args.steps)
+    final = sol.get_state().cpu().numpy()
+    out = {"value": dofs * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+           "iterations_per_step": {"picard": picard / args.steps, "gmres": gmres / args.steps},
+           "elements": mesh.E, "degree": w.mesh.degree, "dofs": dofs, "mass": sol.total_mass()}
+    rep = None
+    if replay:
+        rep, rp, rg = kernel_replay(sol, q_start, args.steps)
+        same = (rp, rg) == (picard, gmres) and bool((sol.get_state().cpu().numpy() == final).all())
+        out["kernels"] = kernels_block(rep, args.steps)
+        out["kernels_timing"] = ("HIP event pair around every launch on the solver stream, on a replay of the "
+                                 "timed steps from their saved start state; replay identical to the timed "
+                                 f"steps (iterations and final state bitwise): {same}")
+    if ref_state is not None:
+        out["max_rel_error_vs_fp64"] = field_errors(final, ref_state)
+    del sol
+    torch.cuda.empty_cache()
+    return out, final, rep
+
+
+def W_initial(w, mesh):
+    from paper_2605_29598_amd import workloads as W
+    return W.initial_state(w, mesh.node_coords())
 
 
 def served_run(args):
@@ -164,7 +256,6 @@ def served_run(args):
         torch.cuda.synchronize()
         dur.append(time.perf_counter() - t0)
         del sol
-        print(f"serve: alone {r.workload.name} {dur[-1]:.2f} s", file=sys.stderr, flush=True)
     end, lat = 0.0, []
     for r, d in zip(trace, dur):
         end = max(end, r.arrival_s) + d
@@ -173,6 +264,7 @@ def served_run(args):
               "step_ms_p50": float(np.percentile(alone_steps, 50)), "step_ms_p99": float(np.percentile(alone_steps, 99)),
               "request_latency_s_p50": float(np.percentile(lat, 50)),
               "request_latency_s_p99": float(np.percentile(lat, 99))}
+    print(f"serve: queue alone makespan {serial['makespan_s']:.2f} s", file=sys.stderr, flush=True)
 
     def served(precision):
         sv = B.Server(pool_bytes=args.serve_pool_gb << 30, max_running=args.serve_slots)
@@ -196,14 +288,14 @@ def served_run(args):
         for k, (rid, t_sub) in enumerate(ids):
             q, ms = sv.result(rid)
             if ms.status != B.IMX_OK:
-                msg = B.lib().imx_last_error().decode(errors="replace")
+                msg = B.lib().imx_server_last_error(sv.h).decode(errors="replace")
                 raise RuntimeError(f"served member {k} ({trace[k].workload.name}) failed with status {ms.status} "
                                    f"after {ms.steps_done} steps: {msg}")
             lat.append(1e-3 * (ms.queue_ms + ms.run_ms))
             if precision == B.IMX_FP64:
                 worst = max(worst, float(np.abs(q - finals[k]).max()))
             else:
-                worst = max(worst, max(field_errors(q, finals[k]).values()))
+                worst = max(worst, max(field_errors(q, finals[k])["vs_tolerance_scale"].values()))
         out = {"dof_updates_per_s": total / makespan, "makespan_s": makespan,
                "step_ms_p50": st.p50_step_ms, "step_ms_p99": st.p99_step_ms,
                "request_latency_s_p50": float(np.percentile(lat, 50)),
@@ -213,7 +305,7 @@ def served_run(args):
         if precision == B.IMX_FP64:
             out["max_abs_diff_vs_alone"] = worst
         else:
-            out["max_rel_error_vs_fp64_alone"] = worst
+            out["max_rel_error_vs_fp64_alone_tolerance_scale"] = worst
         del sv
         print(f"serve: {'fp64' if precision == B.IMX_FP64 else 'mixed'} makespan {makespan:.2f} s",
               file=sys.stderr, flush=True)
@@ -237,7 +329,7 @@ def main():
     ap.add_argument("--scheme", default="R2", choices=["R1", "R2"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-inner comparison run")
-    ap.add_argument("--profile-steps", action="store_true", help="print progress per step")
+    ap.add_argument("--no-channel", action="store_true", help="skip the IGW channel run")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-ensemble run")
     ap.add_argument("--serve-only", action="store_true", help="run only the served-ensemble comparison")
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -246,6 +338,7 @@ def main():
     # 4, 8 and 12 slots give the same throughput, more slots only queue longer
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-pool-gb", type=int, default=64)
+    ap.add_argument("--cpu-procs", type=int, default=None)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only a 1 GiB device-to-device copy, the calibration run for HBM byte counters")
     args = ap.parse_args()
@@ -272,76 +365,66 @@ def main():
     if args.serve_only:
         print(json.dumps({"served": served_run(args)}))
         return
-    w = W.igw_channel(scheme=B.IMX_R1 if args.scheme == "R1" else B.IMX_R2)
-    mesh = B.Mesh(w.mesh)
-    sol = B.Solver(mesh, w.phys, w.num, device="cuda:0")
-    q0 = W.initial_state(w, mesh.node_coords())
-    sol.set_state(q0)
-    dofs = 5 * mesh.E * mesh.Np
-    for i in range(args.warmup):
-        sol.step(1)
-        if args.profile_steps:
-            print(f"warmup step {i} done", file=sys.stderr, flush=True)
 
-    # timed region: K steps with nothing but the solver's own work queued
-    torch.cuda.synchronize()
-    picard = gmres = 0
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        st = sol.step(1)
-        picard += st.picard_iters
-        gmres += st.gmres_iters
-        if args.profile_steps:
-            print(f"step {i}: picard {st.picard_iters} gmres {st.gmres_iters}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ref_state = sol.get_state().cpu().numpy()
-    # kernel timing: the next K steps with a HIP event pair around every launch
-    # on the solver's stream (the events themselves add ~7% to a step)
-    rep, k_gmres = kernel_pass(sol, args.steps)
-
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = dofs * args.steps / elapsed
-    dom = max(rep, key=lambda k: rep[k][0])
-    ms, by, n = rep[dom]
-    achieved = by / (ms * 1e-3) / 1e9
-    traffic = measured_traffic(dom)
-    kernels = {k: {"ms_per_step": round(v[0] / args.steps, 3),
-                   "GB_per_s": round(v[1] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else 0,
-                   "frac_of_hbm_peak": round(v[1] / (v[0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 3) if v[0] > 0 else 0,
-                   "avg_launch_us": round(1e3 * v[0] / v[2], 1),
-                   "launches_per_step": round(v[2] / args.steps, 1)} for k, v in rep.items() if v[2]}
+    scheme = B.IMX_R1 if args.scheme == "R1" else B.IMX_R2
+    w = W.orography(scheme=scheme)
+    head, ref_state, rep = run_workload(w, args, B.IMX_FP64)
+    print(f"bench: {w.name} fp64 {head['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+    note = (f"HIP events on the solver stream around every launch, on a replay of the {args.steps} timed steps "
+            f"from their saved start state")
+    traffic = measured_traffic(w.name, ["pass1", "pass2"])
+    roof = roofline_of(rep, ["pass1", "pass2"], args.steps, traffic,
+                       note + "; one Schur-complement apply = one pass-1 and one pass-2 launch")
+    operators = {}
+    for name, cls in (("schur_apply", ["pass1", "pass2"]), ("explicit_residual", ["explicit"]),
+                      ("picard_refresh", ["lambda"])):
+        r = roofline_of(rep, cls, args.steps, measured_traffic(w.name, cls), note)
+        operators[name] = {k: r[k] for k in ("achieved", "frac", "avg_launch_us", "algorithmic_bytes_per_launch",
+                                             "launches_per_step", "traffic")}
+    kern = head.pop("kernels")
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "DoF-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "elements": mesh.E, "degree": w.mesh.degree, "dofs": dofs,
+        "config": {"workload": w.name, "elements": head["elements"], "degree": head["degree"], "dofs": head["dofs"],
                    "dt": w.num.dt, "scheme": args.scheme, "precision": "fp64",
                    "gmres_restart": w.num.gmres_restart, "tolerances": [w.num.picard_tol, w.num.gmres_tol]},
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "avg_launch_us": 1e3 * ms / max(n, 1), "algorithmic_bytes_per_launch": by / max(n, 1),
-                     "timing": f"HIP events on the solver stream around every launch, over {args.steps} steps "
-                               f"following the timed ones"},
-        "iterations_per_step": {"picard": picard / args.steps, "gmres": gmres / args.steps},
-        "kernels": kernels,
-        "mass": sol.total_mass(),
+        "roofline": roof,
+        "operators": operators,
+        "iterations_per_step": head["iterations_per_step"],
+        "kernels": kern,
+        "kernels_timing": head["kernels_timing"],
+        "dominant_class_by_time": max(kern, key=lambda k: kern[k]["ms_per_step"]),
+        "mass": head["mass"],
     }
     if not args.no_mixed:
-        out["fp32_inner"] = mixed_run(w, mesh, q0, args, ref_state, dofs)
+        mixed, _, _ = run_workload(w, args, B.IMX_MIXED, ref_state=ref_state, replay=False)
+        mixed["inner_tol"] = 1e-3
+        for k in ("elements", "degree", "dofs", "mass"):
+            mixed.pop(k, None)
+        out["fp32_inner"] = mixed
+        print(f"bench: {w.name} fp32-inner {mixed['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+    if not args.no_channel:
+        wc = W.igw_channel(scheme=scheme)
+        ch, _, crep = run_workload(wc, args, B.IMX_FP64)
+        ch["workload"] = wc.name
+        ch["schur_apply"] = roofline_of(crep, ["pass1", "pass2"], args.steps, None, note)
+        ch["schur_apply"].pop("timing")
+        out["igw_channel"] = ch
+        print(f"bench: {wc.name} fp64 {ch['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
     if not args.no_serve:
         out["served"] = served_run(args)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(args.cpu_procs)
     print(json.dumps(out))
 
 

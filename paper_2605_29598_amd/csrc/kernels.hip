@@ -1273,6 +1273,187 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
     }
 }
 
+// Schur pass 1 inside the Krylov loop on terrain-following (Gal-Chen)
+// elements. Same result as k_mv1 with AFF = false, organised for few
+// synchronisation points: every global load (own fields, the five stored
+// entries of W cof(J), 1 / W detJ, rho_l, this lane's face table entries, n dS
+// of its face points and the neighbour values along the normal) is issued
+// before the first barrier and kept in registers, and the volume pressure
+// term uses the sparsity of W cof(J): -int p div(phi_c) is
+// D_x^T(G00 p) + D_z^T(G20 p), D_y^T(G11 p) + D_z^T(G21 p) and D_z^T(G22 p),
+// five 1D contractions staged together, instead of nine in three rounds.
+// Four barriers in all.
+template <int N, typename R, int SCH>
+__global__ void __launch_bounds__(threads_mv(N))
+k_mv1_gc(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
+         const R* __restrict__ cr, const R* __restrict__ pk, const R* __restrict__ rho, R* __restrict__ w,
+         R* __restrict__ FB, Geom<R> g, const Tab<N, R>* __restrict__ Tg, StageK sk, const int* __restrict__ ctrl) {
+    if (ctrl && *ctrl != 0) return;   // the Krylov cycle has stopped
+    constexpr int NP = N * N * N, NF = N * N, EPB = epb_mv(N);
+    constexpr int NR = (6 * NF + NP - 1) / NP;   // face points per lane
+    constexpr int LU = 18 * NF > 3 * NP ? 18 * NF : 3 * NP;
+    __shared__ R s_p[EPB][NP];
+    __shared__ R s_pk[EPB][NP];
+    __shared__ R s_a[EPB][5][NP];   // G p (five entries), then w (three components)
+    __shared__ R s_u[EPB][LU];      // {p} n dS per face point, then the contravariant (rho h)^k w
+    __shared__ Tab<N, R> T;
+    load_tab<N, R>(Tg, &T);
+    const int tid = threadIdx.x, le = elem_slot<NP>(tid), node = tid - le * NP;
+    const int slot = (int)xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+    const bool act = le < EPB && slot < nel;
+    const int e = act ? (elist ? elist[slot] : slot) : 0;
+    const unsigned fs = (unsigned)g.E * NP, o = (unsigned)e * NP + node;
+    const R sc = pscale ? pscale[0] : (R)1;
+    R* U = &s_u[le][0];
+    R crv = 0, iwj = 0, rl = 0, gv[5] = {0, 0, 0, 0, 0}, nbv[NR][N], nsv[NR][3];
+    int kf[NR], nf[NR];
+    uint64_t fo[NR];
+    if (act) {
+        const R pv = p[o];
+        s_p[le][node] = pv;
+        s_pk[le][node] = pk[o];
+        crv = cr[o];
+        iwj = g.iWJ[o];
+        if constexpr (SCH == 2) rl = rho[o];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) gv[t] = g.G[t * fs + o];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            fo[r] = g.fofs[r * NP + node];
+            const bool full = (r + 1) * NP <= 6 * NF;   // every lane has a point in this round
+            const int f = fo_face(fo[r]);
+            const bool has = full || f < 6;
+            const int fc = has ? f : 5;
+            kf[r] = has ? g.kind[e * 6 + fc] : WALL;
+            nf[r] = g.nbr[e * 6 + fc];
+            nS_gc<N, R>(g, e, fc, fo_point(fo[r]), nsv[r]);
+            const bool ld = kf[r] == CONF;
+            const R* src = p + (size_t)(unsigned)(ld ? nf[r] : 0) * NP;
+#pragma unroll
+            for (int m = 0; m < N; ++m) nbv[r][m] = ld ? src[fo_node(fo[r], m)] : (R)0;
+        }
+        const R pvs = sc * pv;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) s_a[le][t][node] = gv[t] * pvs;
+    }
+    __syncthreads();
+    // {p} n dS at every face point of the element
+    if (act)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int f = fo_face(fo[r]);
+            if ((r + 1) * NP > 6 * NF && f >= 6) continue;
+            const int pt = fo_point(fo[r]), d = f >> 1, s = f & 1;
+            R vals[N];
+#pragma unroll
+            for (int m = 0; m < N; ++m) vals[m] = s_p[le][fo_node(fo[r], m)];
+            const R pa = sc * trace_chain<N, R>(T.f[s], vals);
+            R pb = pa;
+            if (kf[r] == CONF) pb = sc * trace_chain<N, R>(T.f[1 - s], nbv[r]);
+            else if (kf[r] == FINE)
+                pb = sc * coarse_point<N>(p + (size_t)(unsigned)nf[r] * NP, T.f[1 - s], T, d, g.aux[e * 6 + f] & 3, pt);
+            const R avg = (R)0.5 * (pa + pb);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) U[(f * 3 + c) * NF + pt] = avg * nsv[r][c];
+        }
+    // volume: -int (sc p) div(phi_c) from the five metric-weighted pressures
+    R vol[3] = {0, 0, 0};
+    if (act) {
+        const int i = node % N, j = (node / N) % N, k = node / (N * N);
+        const R* A0 = &s_a[le][0][0];
+        const R* A1 = &s_a[le][1][0];
+        const R* A20 = &s_a[le][2][0];
+        const R* A21 = &s_a[le][3][0];
+        const R* A22 = &s_a[le][4][0];
+        R x0 = 0, x1 = 0, z0 = 0, z1 = 0, z2 = 0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            x0 += T.D[q][i] * A0[q + N * (j + N * k)];
+            x1 += T.D[q][j] * A1[i + N * (q + N * k)];
+            const int zq = i + N * (j + N * q);
+            z0 += T.D[q][k] * A20[zq];
+            z1 += T.D[q][k] * A21[zq];
+            z2 += T.D[q][k] * A22[zq];
+        }
+        vol[0] = x0 + z0;
+        vol[1] = x1 + z1;
+        vol[2] = z2;
+    }
+    __syncthreads();
+    // w = (I + beta J)^{-1} A^{-1} (-B p) [R2] or A^{-1}(-B p) [R1]
+    R hq[3] = {0, 0, 0}, wz = 0;
+    if (act) {
+        R acc[3] = {0, 0, 0};
+        for (int f = 0; f < 6; ++f) {
+            int m, pt;
+            split_node<N>(f >> 1, node, m, pt);
+            const R lf = T.f[f & 1][m];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[c] += lf * U[(f * 3 + c) * NF + pt];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] -= vol[c];
+        const R cdt = (R)sk.c_dt, beta = (R)sk.beta;
+        R v[3], wv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = -(cdt * acc[c]) * crv;
+        if constexpr (SCH == 2) {
+            const R si = (R)sk.rot_si;
+            wv[0] = si * (v[0] + beta * v[1]);
+            wv[1] = si * (-beta * v[0] + v[1]);
+            wv[2] = v[2];
+        } else {
+            wv[0] = v[0];
+            wv[1] = v[1];
+            wv[2] = v[2];
+        }
+        const R rh = (R)sk.hfac * s_pk[le][node];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            hq[c] = rh * wv[c];
+            s_a[le][c][node] = wv[c];
+        }
+        wz = wv[2];
+    }
+    __syncthreads();
+    if (act) {
+        // face buffer: (rho h)^k (w . n dS) on this element's side of each face
+        const R hfac = (R)sk.hfac;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int f = fo_face(fo[r]);
+            if (((r + 1) * NP > 6 * NF && f >= 6) || kf[r] == WALL) continue;
+            const int pt = fo_point(fo[r]), s = f & 1;
+            R vk[N];
+#pragma unroll
+            for (int m = 0; m < N; ++m) vk[m] = s_pk[le][fo_node(fo[r], m)];
+            const R hk = hfac * trace_chain<N, R>(T.f[s], vk);
+            R wn = 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                R vw[N];
+#pragma unroll
+                for (int m = 0; m < N; ++m) vw[m] = s_a[le][c][fo_node(fo[r], m)];
+                wn += trace_chain<N, R>(T.f[s], vw) * nsv[r][c];
+            }
+            FB[(size_t)(unsigned)(e * 6 + f) * NF + pt] = hk * wn;
+        }
+        // contravariant (rho h)^k w for the own part of pass 2 (U is free:
+        // every lane has lifted its face values before the last barrier)
+        U[node] = gv[0] * hq[0];
+        U[NP + node] = gv[1] * hq[1];
+        U[2 * NP + node] = gv[2] * hq[0] + gv[3] * hq[1] + gv[4] * hq[2];
+    }
+    __syncthreads();
+    if (act) {
+        const R dv = div_T<N>(U, T, node);
+        const R cdt = (R)sk.c_dt;
+        R qv = cdt * dv * iwj;
+        if constexpr (SCH == 2) qv -= cdt * (R)sk.g * (rl * wz);
+        w[o] = qv;
+    }
+}
+
 // Schur pass 2 inside the Krylov loop: qw[0] holds the element's own volume
 // and gravity part formed by pass 1; the pressure and face terms are added.
 template <int N, typename R, bool AFF>
@@ -1294,11 +1475,16 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
     const unsigned o = (unsigned)e * NP + node;
     R* U = &s_face[le][0];
     R pv = 0, qv = 0;   // scaled x, own part from pass 1
+    R iwj = 0, wjd = 0;  // terrain-following: 1 / W detJ (and W detJ for the dual form), loaded up front
     ElemGeo<N, R, AFF> eg;
     if (act) {
         eg.load(g.eg, e);
         qv = qw[o];
         pv = (pscale ? pscale[0] : (R)1) * p[o];
+        if constexpr (!AFF) {
+            iwj = g.iWJ[o];
+            if (dual) wjd = g.WJ[o];
+        }
         // {(rho h)^k w} . n dS from the two sides' face buffers
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -1328,14 +1514,14 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
         split_node<N>(f >> 1, node, m, pt);
         acc += T.f[f & 1][m] * U[f * NF + pt];
     }
-    const R iwj = AFF ? T.iW3[node] * eg.idJ : g.iWJ[o];
+    if constexpr (AFF) iwj = T.iW3[node] * eg.idJ;
     const R cdt = (R)sk.c_dt;
     R res = -(pv * (R)sk.igm1);
     res -= cdt * acc * iwj;
     res += qv;
     // z = -res = M^{-1} S (sc x); the dual form is S (sc x) = -res W detJ
     if (dual) {
-        const R wj = AFF ? T.W3[node] * eg.dJ : g.WJ[o];
+        const R wj = AFF ? T.W3[node] * eg.dJ : wjd;
         out[o] = -res * wj;
     } else {
         out[o] = -res;
@@ -1777,9 +1963,14 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
         fork_join(
             m, st,
             [&](hipStream_t s) {
-                if (bf > 0)
-                    hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
-                                       (int)nf, x, xs, cr, pk, rho, w, FB, geom<R>(m), T, sk, ctrl);
+                if (bf > 0) {
+                    if constexpr (AFF)
+                        hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s,
+                                           fl, (int)nf, x, xs, cr, pk, rho, w, FB, geom<R>(m), T, sk, ctrl);
+                    else
+                        hipLaunchKernelGGL((k_mv1_gc<N, R, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s,
+                                           fl, (int)nf, x, xs, cr, pk, rho, w, FB, geom<R>(m), T, sk, ctrl);
+                }
             },
             [&](hipStream_t s) {
                 if (bs > 0)
