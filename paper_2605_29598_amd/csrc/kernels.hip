@@ -587,6 +587,205 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
     for (int t = 0; t < 4; ++t) fS[t * fs + e * NP + node] = acc[5 + t] * iwj;
 }
 
+// Explicit residual on terrain-following (Gal-Chen) elements without a
+// coarse hanging face. Same weak forms as k_explicit, organised for few
+// synchronisation points and few LDS round trips:
+//  - every global load that does not depend on another (own fields, the five
+//    stored entries of W cof(J), 1 / W detJ, the sponge coefficient, this
+//    lane's face table entries, kinds, neighbours and n dS) is issued before
+//    the first barrier; the neighbour values along the normal are gathered
+//    face point by face point after it (holding them all would halve the
+//    occupancy);
+//  - the volume term uses the sparsity of W cof(J): a flux vector F has the
+//    contravariant components (G00 F0, G11 F1, G20 F0 + G21 F1 + G22 F2), and
+//    the pressure terms need five staged arrays instead of nine, so the nine
+//    outputs take 23 contractions in three rounds;
+//  - the sources (gravity, Coriolis, sponge) are added after the division by
+//    W detJ, which they carry as a factor, so W detJ itself is not read.
+template <int N, typename R>
+__global__ void __launch_bounds__(threads_of(N))
+k_explicit_gc(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, R* __restrict__ fNS,
+              R* __restrict__ fS, Geom<R> g, const Tab<N, R>* __restrict__ Tg, PhysK ph,
+              const double* __restrict__ sponge) {
+    constexpr int NP = N * N * N, NF = N * N, EPB = epb_of(N);
+    constexpr int NR = (6 * NF + NP - 1) / NP;   // face points per lane
+    constexpr int LU = 54 * NF > 9 * NP ? 54 * NF : 9 * NP;
+    __shared__ R s_q[EPB][5][NP];
+    __shared__ R s_u[EPB][LU];
+    __shared__ Tab<N, R> T;
+    load_tab<N, R>(Tg, &T);
+    const int tid = threadIdx.x, le = elem_slot<NP>(tid), node = tid - le * NP;
+    const int64_t slot = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
+    const bool act = le < EPB && slot < nel;
+    const int64_t e = act ? (elist ? (int64_t)elist[slot] : slot) : 0;
+    const size_t fs = (size_t)g.E * NP, o = (size_t)e * NP + node;
+    const R gm1 = (R)ph.gm1, igm1 = (R)ph.igm1, hfac = (R)ph.hfac;
+    R* U = &s_u[le][0];
+    R qv[5] = {1, 0, 0, 0, 1}, gv[5] = {0, 0, 0, 0, 0}, iwj = 0, lam = 0;
+    R nsv[NR][3];
+    int kf[NR], nf[NR];
+    uint64_t fo[NR];
+    if (act) {
+#pragma unroll
+        for (int t = 0; t < 5; ++t) s_q[le][t][node] = q[t * fs + o];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) gv[t] = g.G[t * fs + o];
+        iwj = g.iWJ[o];
+        if (ph.sponge) lam = (R)sponge[o];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            fo[r] = g.fofs[r * NP + node];
+            const bool full = (r + 1) * NP <= 6 * NF;
+            const int f = fo_face(fo[r]);
+            const bool has = full || f < 6;
+            const int fc = has ? f : 5;
+            kf[r] = has ? g.kind[e * 6 + fc] : WALL;
+            nf[r] = g.nbr[e * 6 + fc];
+            nS_gc<N, R>(g, e, fc, fo_point(fo[r]), nsv[r]);
+        }
+    }
+    __syncthreads();
+    R acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = 0;
+    // numerical fluxes at every face point: U[(f*9 + o)*NF + pt]
+    if (act)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int f = fo_face(fo[r]);
+            if ((r + 1) * NP > 6 * NF && f >= 6) continue;
+            const int pt = fo_point(fo[r]), d = f >> 1, s = f & 1;
+            R qa[5], qb[5], fl[9];
+#pragma unroll
+            for (int t = 0; t < 5; ++t) {
+                R v[N];
+#pragma unroll
+                for (int m = 0; m < N; ++m) v[m] = s_q[le][t][fo_node(fo[r], m)];
+                qa[t] = trace_chain<N, R>(T.f[s], v);
+            }
+            if (kf[r] == FINE) {
+#pragma unroll 1
+                for (int t = 0; t < 5; ++t)
+                    qb[t] = coarse_point<N>(q + t * fs + (size_t)nf[r] * NP, T.f[1 - s], T, d,
+                                            g.aux[e * 6 + f] & 3, pt);
+            } else {
+                // the neighbour's values along the normal (conforming and periodic faces)
+                const bool ld = kf[r] == CONF;
+                const size_t nb = (size_t)(ld ? nf[r] : 0) * NP;
+#pragma unroll
+                for (int t = 0; t < 5; ++t) {
+                    R v[N];
+#pragma unroll
+                    for (int m = 0; m < N; ++m) v[m] = ld ? q[t * fs + nb + fo_node(fo[r], m)] : (R)0;
+                    qb[t] = trace_chain<N, R>(T.f[1 - s], v);
+                }
+            }
+            euler_flux<R>(qa, qb, nsv[r], kf[r] == WALL, gm1, igm1, hfac, fl);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) U[(f * 9 + k) * NF + pt] = fl[k];
+            // one face point at a time: keeps the next point's gathers from
+            // being hoisted above this one's flux (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    __syncthreads();
+    if (act)
+        for (int f = 0; f < 6; ++f) {
+            int m, pt;
+            split_node<N>(f >> 1, node, m, pt);
+            const R lf = T.f[f & 1][m];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) acc[k] -= lf * U[(f * 9 + k) * NF + pt];
+        }
+    __syncthreads();   // the volume staging reuses U
+    // own values again from LDS (not kept in registers across the face phase)
+    if (act)
+#pragma unroll
+        for (int t = 0; t < 5; ++t) qv[t] = s_q[le][t][node];
+    const R rho = qv[0], irho = (R)1 / rho;
+    const R u[3] = {qv[1] * irho, qv[2] * irho, qv[3] * irho};
+    const R kin = (R)0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const R p = gm1 * (qv[4] - rho * kin);
+    const int ix = node % N, jy = (node / N) % N, kz = node / (N * N);
+    // contravariant components of a flux vector F into U[3*a .. 3*a+2]
+    auto stage3 = [&](int a, R F0, R F1, R F2) {
+        U[(3 * a) * NP + node] = gv[0] * F0;
+        U[(3 * a + 1) * NP + node] = gv[1] * F1;
+        U[(3 * a + 2) * NP + node] = gv[2] * F0 + gv[3] * F1 + gv[4] * F2;
+    };
+    auto div3 = [&](int a) -> R {
+        const R* A0 = U + (3 * a) * NP;
+        const R* A1 = U + (3 * a + 1) * NP;
+        const R* A2 = U + (3 * a + 2) * NP;
+        R v = 0;
+#pragma unroll
+        for (int qq = 0; qq < N; ++qq) v += T.D[qq][ix] * A0[qq + N * (jy + N * kz)];
+#pragma unroll
+        for (int qq = 0; qq < N; ++qq) v += T.D[qq][jy] * A1[ix + N * (qq + N * kz)];
+#pragma unroll
+        for (int qq = 0; qq < N; ++qq) v += T.D[qq][kz] * A2[ix + N * (jy + N * qq)];
+        return v;
+    };
+    // round 1: mass flux and the x and y momentum fluxes
+    if (act) {
+        stage3(0, qv[1], qv[2], qv[3]);
+        stage3(1, qv[1] * u[0], qv[1] * u[1], qv[1] * u[2]);
+        stage3(2, qv[2] * u[0], qv[2] * u[1], qv[2] * u[2]);
+    }
+    __syncthreads();
+    if (act) {
+        acc[0] += div3(0);
+        acc[1] += div3(1);
+        acc[2] += div3(2);
+    }
+    __syncthreads();
+    // round 2: z momentum, kinetic energy and enthalpy fluxes
+    if (act) {
+        stage3(0, qv[3] * u[0], qv[3] * u[1], qv[3] * u[2]);
+        stage3(1, kin * qv[1], kin * qv[2], kin * qv[3]);
+        const R rh = hfac * p;
+        stage3(2, rh * u[0], rh * u[1], rh * u[2]);
+    }
+    __syncthreads();
+    if (act) {
+        acc[3] += div3(0);
+        acc[4] += div3(1);
+        acc[8] += div3(2);
+    }
+    __syncthreads();
+    // round 3: the pressure, (G00 p, G11 p, G20 p, G21 p, G22 p)
+    if (act)
+#pragma unroll
+        for (int t = 0; t < 5; ++t) U[t * NP + node] = gv[t] * p;
+    __syncthreads();
+    if (!act) return;
+    {
+        R x0 = 0, y1 = 0, z0 = 0, z1 = 0, z2 = 0;
+#pragma unroll
+        for (int qq = 0; qq < N; ++qq) {
+            x0 += T.D[qq][ix] * U[qq + N * (jy + N * kz)];
+            y1 += T.D[qq][jy] * U[NP + ix + N * (qq + N * kz)];
+            const int zq = ix + N * (jy + N * qq);
+            z0 += T.D[qq][kz] * U[2 * NP + zq];
+            z1 += T.D[qq][kz] * U[3 * NP + zq];
+            z2 += T.D[qq][kz] * U[4 * NP + zq];
+        }
+        acc[5] += x0 + z0;
+        acc[6] += y1 + z1;
+        acc[7] += z2;
+    }
+    const R fc = (R)ph.f, gg = (R)ph.g;
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+        R v = acc[t] * iwj;
+        if (t >= 1 && t <= 3 && ph.sponge) v -= lam * (qv[t] - rho * (R)ph.su[t - 1]);
+        fNS[t * fs + o] = v;
+    }
+    fS[o] = acc[5] * iwj + rho * fc * u[1];
+    fS[fs + o] = acc[6] * iwj - rho * fc * u[0];
+    fS[2 * fs + o] = acc[7] * iwj - rho * gg;
+    fS[3 * fs + o] = acc[8] * iwj - rho * gg * u[2];
+}
+
 // =====================================================================
 // Schur pass 1: w = P (Fh/rho - M^{-1} B p / rho) (+ R1 lag), face buffers
 // =====================================================================
@@ -1879,7 +2078,7 @@ void launch_explicit(const DevMesh& m, const HostTab&, const PhysK& ph, const R*
 #define CALL(NN)                                                                                            \
     do {                                                                                                    \
         if (m.deformed)                                                                                     \
-            launch_split<NN, true>(m, k_explicit<NN, R, false, false>, k_explicit<NN, R, true, false>, st, q, fNS, \
+            launch_split<NN, true>(m, k_explicit_gc<NN, R>, k_explicit<NN, R, true, false>, st, q, fNS,       \
                              fS, geom<R>(m), (const Tab<NN, R>*)tab_ptr<R>(m), ph, m.sponge);              \
         else                                                                                                \
             launch_split<NN, true>(m, k_explicit<NN, R, false, true>, k_explicit<NN, R, true, true>, st, q, fNS,  \

@@ -9,7 +9,7 @@ sources: a summary taken from other kernels is not used.
 
     python -m paper_2605_29598_amd.profiling \
         --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \
-        --copy-bytes 1073741824 --out profiles/pmc_traffic.json
+        --copy-bytes 1073741824 --out profiles/pmc_traffic_<workload>.json
 """
 import argparse
 import collections
@@ -24,7 +24,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 # kernel-name stem -> class reported by the solver's timers
 CLASSES = {
-    "k_explicit": "explicit", "k_pass1": "pass1", "k_mv1": "pass1", "k_pass2": "pass2", "k_mv2": "pass2",
+    "k_explicit": "explicit", "k_pass1": "pass1", "k_mv1": "pass1", "k_mv1_gc": "pass1", "k_pass2": "pass2",
+    "k_mv2": "pass2",
     "k_mv2w": "pass2", "k_lambda": "lambda", "k_dots": "dots", "k_axpy_norm": "ortho", "k_lincomb": "lincomb",
 }
 
@@ -151,7 +152,7 @@ def steps(name, nsteps=3, mixed=False):
             "gmres_per_step": st.gmres_iters / nsteps, "picard_per_step": st.picard_iters / nsteps}
 
 
-def run(name, nsteps, mixed=False, scheme=None, out=None, every=10):
+def run(name, nsteps, mixed=False, scheme=None, out=None, every=10, dt=None):
     """A workload run to its stated length from its initial state, one step at
     a time: per step the Picard and GMRES iterations, the wall time, max|w|
     (diagnostic, from the device state) and, every `every` steps, the total
@@ -163,6 +164,9 @@ def run(name, nsteps, mixed=False, scheme=None, out=None, every=10):
     w = WORKLOADS[name](W)
     if scheme is not None:
         w.num.scheme = scheme
+    if dt is not None:
+        # the sponge strength is stated as lambda dt; keep lambda itself
+        w.num.dt = dt
     mesh = B.Mesh(w.mesh)
     sol = B.Solver(mesh, w.phys, w.num, precision=B.IMX_MIXED if mixed else B.IMX_FP64)
     sol.set_state(W.initial_state(w, mesh.node_coords()))
@@ -224,9 +228,10 @@ def main():
         ap.add_argument("--mixed", action="store_true")
         ap.add_argument("--scheme", choices=["R1", "R2"], default=None)
         ap.add_argument("--out", default=None, help="per-step JSON lines")
+        ap.add_argument("--dt", type=float, default=None, help="time step instead of the workload's")
         a = ap.parse_args()
         sch = None if a.scheme is None else (1 if a.scheme == "R1" else 2)
-        print("SUMMARY " + json.dumps(run(a.workload, a.steps, a.mixed, sch, a.out)), flush=True)
+        print("SUMMARY " + json.dumps(run(a.workload, a.steps, a.mixed, sch, a.out, dt=a.dt)), flush=True)
         return
     if len(sys.argv) > 1 and sys.argv[1] == "steps":
         ap = argparse.ArgumentParser(description="ARK2 step rate of a full workload")

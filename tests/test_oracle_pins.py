@@ -387,3 +387,42 @@ def test_slice_invariance():
     # and within an element, along y
     for fld in range(5):
         assert np.abs(a[fld] - a[fld][:, :, :1, :]).max() < 1e-12 * np.abs(a[fld]).max() + 1e-12
+
+
+def _explicit_growth(r, nus, nth=721):
+    """Largest |R_e(dt lambda)| of the explicit ARK2 tableau over the Fourier
+    spectrum of upwind DG (degree r, Gauss-Legendre nodes, unit speed, cell
+    size 1) for linear advection on a periodic grid."""
+    b = B.Basis1D(r)
+    M = np.diag(b.w)
+    K = b.deriv.T @ M                      # int u l_i' (volume)
+    f0, f1 = b.face[0], b.face[1]
+    eigs = []
+    for th in np.linspace(0.0, 2.0 * np.pi, nth):
+        A = K - np.outer(f1, f1) + np.exp(-1j * th) * np.outer(f0, f1)   # upwind: inflow from the left cell
+        eigs.extend(np.linalg.eigvals(np.linalg.solve(M, A)))
+    eigs = np.array(eigs)
+
+    def R(z):
+        return 1 + z * (dg.B_W @ np.linalg.solve(np.eye(3) - z * dg.A_EXP, np.ones(3)))
+    return [max(abs(R(nu * lam)) for lam in eigs) for nu in nus]
+
+
+def test_explicit_tableau_advective_limit():
+    """The advection is explicit, so dt is bounded by the advective Courant
+    number of the smallest elements. For r = 4 the explicit tableau of Sec. 3
+    on upwind DG grows by less than 1e-4 per step at a dt/h = 0.05 but by 1.5
+    per step at 0.15 (it contains no part of the imaginary axis:
+    |R_e(iy)|^2 = 1 + 0.078 y^4 + ..., so the DG dissipation has to cover it).
+    This is why the refined orography box, whose level-2 elements reach
+    sum |u_c| dt / h_c = 0.11-0.13 near the hill at dt = 4 s, diverges after 18
+    steps, and runs its 500 steps at dt = 2 s."""
+    g05, g085, g15 = _explicit_growth(4, [0.05, 0.085, 0.15])
+    assert g05 < 1 + 1e-4
+    assert 1 + 1e-5 < g085 < 1.01
+    assert g15 > 1.3
+    # |R_e(iy)|^2 - 1 = (1/4 - chi^2/2) y^4 + (chi^2/4)^2 y^6 > 0 on the imaginary axis
+    chi = 2 - math.sqrt(2)
+    for y in (0.1, 0.5, 1.0):
+        R = 1 + 1j * y * (dg.B_W @ np.linalg.solve(np.eye(3) - 1j * y * dg.A_EXP, np.ones(3)))
+        assert abs(abs(R) ** 2 - (1 + (0.25 - chi ** 2 / 2) * y ** 4 + (chi ** 2 / 4) ** 2 * y ** 6)) < 1e-13
