@@ -232,6 +232,22 @@ imx_status imx_step(imx_solver* s, int nsteps, imx_step_stats* stats);
  * invariants), accumulated in binary64 in a fixed order; *mass (host)
  * receives it (NaN if the state holds one). Synchronises the stream. */
 imx_status imx_total_mass(imx_solver* s, double* mass);
+/* Allocation-free form of imx_total_mass, for callers that cannot allocate
+ * device memory or synchronise (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). Writes the mass sum_K int_K rho of
+ * the caller's state q_dev [5][E][Np] (device, caller-owned, this solver's
+ * mesh) to out_dev[0] and the number of NaN or Inf values among its 5 fields
+ * to out_dev[1] (device, caller-owned, 2 doubles), asynchronously on the
+ * solver's stream: no synchronisation and no host copy. Same kernels and
+ * summation order as imx_total_mass, so the same bits for the same state.
+ * The partial sums go to a static device array of 4096 x 2 doubles (64 KiB)
+ * that every GPU the library runs on holds until the process ends; the
+ * reduction never uses more than 4096 workgroups, so every mesh a solver
+ * accepts fits. All calls on one GPU share that array: calls that overlap on
+ * one GPU (different streams or threads) race. Allocates nothing.
+ * IMX_ESTATE before a workspace is bound, IMX_EINVAL for a null pointer or
+ * when the solver's device is not the current device. */
+imx_status imx_total_mass_noalloc(const imx_solver* s, const double* q_dev, double* out_dev);
 /* Geostrophic imbalance of the bound state (eq. egeo, Sec. 4.2, planetary-
  * scale test): the domain mean int |(1/rho) dp/dx - f v| dV / int dV, with
  * dp/dx the derivative of each element's own pressure polynomial at its

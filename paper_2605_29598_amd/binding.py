@@ -95,6 +95,7 @@ SIGNATURES = {
     "imx_implicit_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(imx_solve_stats)]),
     "imx_step": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(imx_step_stats)]),
     "imx_total_mass": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
+    "imx_total_mass_noalloc": (ctypes.c_int, [_vp, _vp, _vp]),
     "imx_geo_imbalance": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
     "imx_solver_set_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
     "imx_solver_destroy": (None, [_vp]),

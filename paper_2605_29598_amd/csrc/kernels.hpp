@@ -191,8 +191,10 @@ void launch_wdot(int64_t L, const double* a, const double* b, const double* WJ, 
 void launch_picard_var(int64_t L, const double* p0, const double* u0, const double* p1, const double* u1,
                        const double* rho, const double* WJ, double gamma, double* partial, double* out,
                        hipStream_t st);
-// sum WJ rho (out[0]) and a non-finite flag over the state (out[1] = count)
+// sum WJ rho (out[0]) and a non-finite flag over the state (out[1] = count);
+// partial holds mass_blocks(L) x 2 doubles
 void launch_mass(int64_t L, const double* q, const double* WJ, double* partial, double* out, hipStream_t st);
+int mass_blocks(int64_t L);
 // Geostrophic imbalance partial sums: partial[b][0] = sum W detJ |(1/rho) dp/dx - f v|,
 // partial[b][1] = sum W detJ over the elements of workgroup b; returns the
 // number of workgroups (at most max_blocks).

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -67,6 +68,39 @@ static ChunkKey chunk_key(int prec, const void* V, const void* WJ, const void* a
     key.igm1 = k.igm1;
     key.rot_si = k.rot_si;
     return key;
+}
+
+// Scratch of the allocation-free entry point imx_total_mass_noalloc: the
+// mass reduction's per-workgroup partial sums (at most RED_BLOCKS workgroups
+// of 2 values, whatever the mesh size). Each GPU holds its own copy until the
+// process ends. Host code never uses the array's name as a device address:
+// its address on each device is taken once with hipGetSymbolAddress (with that
+// device current) and kept in g_scratch_dev.
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = (size_t)RED_BLOCKS * 2;
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device`, which must be the current device;
+// looked up on the first call per device.
+static imx_status noalloc_scratch(int device, double** out) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) {
+        set_error("allocation-free scratch: device index out of range");
+        return IMX_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error(std::string("allocation-free scratch: hipGetSymbolAddress: ") + hipGetErrorString(e));
+            return IMX_EHIP;
+        }
+        g_scratch_dev[device] = (double*)ptr;
+    }
+    *out = g_scratch_dev[device];
+    return IMX_OK;
 }
 
 // Butcher tableaux of Sec. 3 (explicit / implicit), chi = 2 - sqrt(2), a32 = 1/2.
@@ -881,6 +915,15 @@ imx_status imx_solver_create(const imx_mesh* mesh, const imx_phys* phys, const i
         set_error("imx_solver_create: no HIP device");
         return IMX_EHIP;
     }
+    {
+        // the allocation-free entry point's scratch address on this device
+        double* scr = nullptr;
+        const imx_status rs = noalloc_scratch(s->device, &scr);
+        if (rs != IMX_OK) {
+            delete s;
+            return rs;
+        }
+    }
     s->E = mesh->m.E;
     s->Np = mesh->m.Np;
     s->Nf = mesh->m.Nf;
@@ -1232,6 +1275,31 @@ imx_status imx_total_mass(imx_solver* s, double* mass) {
     launch_mass(s->L, s->y, s->dm.WJ, s->partial, bb, s->st);
     CHK(sync_read(s, bb, 2));
     *mass = s->hsc[0];
+    return IMX_OK;
+}
+
+imx_status imx_total_mass_noalloc(const imx_solver* s, const double* q_dev, double* out_dev) {
+    ErrScope es_(s ? &s->err : nullptr);
+    NEED_BOUND(s);
+    if (!q_dev || !out_dev) {
+        set_error("imx_total_mass_noalloc: null pointer");
+        return IMX_EINVAL;
+    }
+    // the reduction uses at most RED_BLOCKS workgroups of 2 partial sums
+    if ((size_t)mass_blocks(s->L) * 2 > NOALLOC_SCRATCH_DOUBLES) {
+        set_error("imx_total_mass_noalloc: reduction grid exceeds the static scratch");
+        return IMX_EINVAL;
+    }
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != s->device) {
+        set_error("imx_total_mass_noalloc: the solver's device is not the current device");
+        return IMX_EINVAL;
+    }
+    double* scr = nullptr;
+    CHK(noalloc_scratch(s->device, &scr));
+    launch_mass(s->L, q_dev, s->dm.WJ, scr, out_dev, s->st);
+    HIPCHK(hipGetLastError());
     return IMX_OK;
 }
 

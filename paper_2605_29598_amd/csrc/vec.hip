@@ -577,8 +577,11 @@ k_mass(int64_t L, const double* __restrict__ q, const double* __restrict__ WJ, d
     block_sum<2>(acc, red);
     if (threadIdx.x < 2) partial[blockIdx.x * 2 + threadIdx.x] = red[TPB / 64 * 2 + threadIdx.x];
 }
+int mass_blocks(int64_t L) {
+    return (int)(grid_for(L, TPB * 8) > RED_BLOCKS ? RED_BLOCKS : grid_for(L, TPB * 8));
+}
 void launch_mass(int64_t L, const double* q, const double* WJ, double* partial, double* out, hipStream_t st) {
-    const unsigned g = grid_for(L, TPB * 8) > RED_BLOCKS ? RED_BLOCKS : grid_for(L, TPB * 8);
+    const unsigned g = (unsigned)mass_blocks(L);
     hipLaunchKernelGGL(k_mass, dim3(g), dim3(TPB), 0, st, L, q, WJ, partial);
     final_sum(partial, (int)g, 2, out, st);
 }
