@@ -260,6 +260,31 @@ void imx_solver_destroy(imx_solver* s);
  * the text stays valid until the next failing call on it or its destruction. */
 const char* imx_solver_last_error(const imx_solver* s);
 
+/* ------------------------------------------------------- adaptivity */
+/* Dynamic adaptivity: the refinement of Sec. 4.3 (nested 2:1 boxes around
+ * the hill, static in the paper) changed during a run. Transfers nodal
+ * fields [nfields][E][Np] from mesh `from` to mesh `to`, two refinements of
+ * the same box, base grid, degree and terrain whose leaves differ by at most
+ * two levels: a leaf present in both is copied; a new leaf inside an old,
+ * coarser one takes the old polynomial at its nodes (exact: the restriction
+ * of a polynomial of degree r is one); a new leaf covering old, finer leaves
+ * takes the L2 projection of the old fields onto its polynomials with the
+ * mass-matrix quadrature of Sec. 3 (W detJ at the Gauss-Legendre nodes), so
+ * the integral of every field (mass, momentum, energy for the conserved
+ * state) is kept in both directions, and on affine elements coarsening
+ * undoes refinement. q_from_dev / q_to_dev: device, caller-owned, not
+ * aliased. ws_dev: caller-owned device workspace of at least the queried
+ * bytes (256-byte aligned) holding the leaf map, W detJ of both meshes and
+ * the interpolation tables; it is written on `hip_stream` (NULL = default
+ * stream) and may be reused once the stream has passed the transfer. The
+ * host part (the leaf map) synchronises the stream once before the kernel
+ * is queued; the kernel itself runs asynchronously. IMX_EINVAL if the meshes
+ * are not two refinements of one grid or differ by more than two levels,
+ * IMX_ENOMEM if the workspace is too small. */
+imx_status imx_transfer_workspace_bytes(const imx_mesh* from, const imx_mesh* to, size_t* bytes);
+imx_status imx_transfer_state(const imx_mesh* from, const imx_mesh* to, void* ws_dev, size_t ws_bytes,
+                              const double* q_from_dev, double* q_to_dev, int nfields, void* hip_stream);
+
 /* ------------------------------------------------------------ timing */
 /* Kernel classes timed by imx_solver_timing. */
 enum {

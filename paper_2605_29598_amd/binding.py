@@ -110,6 +110,8 @@ SIGNATURES = {
     "imx_server_result": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, ctypes.POINTER(imx_member_stats)]),
     "imx_server_query": (ctypes.c_int, [_vp, ctypes.POINTER(imx_server_stats)]),
     "imx_server_destroy": (None, [_vp]),
+    "imx_transfer_workspace_bytes": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "imx_transfer_state": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_size_t, _vp, _vp, ctypes.c_int, _vp]),
 }
 
 KERNEL_KINDS = ["explicit", "pass1", "pass2", "lambda", "dots", "ortho", "lincomb", "stage", "reduce"]
@@ -310,6 +312,27 @@ class Solver:
                 pass
             _lib.imx_solver_destroy(self.h)
             self.h = None
+
+
+def transfer_state(src: "Mesh", dst: "Mesh", q, device="cuda:0"):
+    """Nodal fields q [nf][src.E][Np] (array or device tensor) transferred onto
+    the refinement `dst` of the same grid (imx_transfer_state); returns a
+    device tensor [nf][dst.E][Np]."""
+    dev = torch.device(device)
+    q = torch.as_tensor(q, dtype=torch.float64, device=dev).contiguous()
+    nf = q.shape[0] if q.dim() == 3 else 1
+    nb = ctypes.c_size_t()
+    check(lib().imx_transfer_workspace_bytes(src.h, dst.h, ctypes.byref(nb)), "imx_transfer_workspace_bytes")
+    ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=dev)
+    base = ws.data_ptr()
+    off = (-base) % 256
+    out = torch.empty((nf, dst.E, dst.Np), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        check(lib().imx_transfer_state(src.h, dst.h, ctypes.c_void_p(base + off), nb.value, _ptr(q), _ptr(out),
+                                       int(nf), ctypes.c_void_p(stream.cuda_stream)), "imx_transfer_state")
+    stream.synchronize()   # the workspace is released when this returns
+    return out if q.dim() == 3 else out[0]
 
 
 def member_pool_bytes(mesh: Mesh, phys: W.PhysSpec, num: W.NumSpec, precision=IMX_FP64, inner_tol=1e-3):

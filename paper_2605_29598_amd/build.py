@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libimexdg.so")
-SOURCES = ["kernels.hip", "vec.hip", "mesh.cpp", "solver.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "vec.hip", "adapt.hip", "mesh.cpp", "solver.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-fopenmp",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -140,6 +140,21 @@ def orography(nx=64, ny=64, nz=24, degree=4, scheme=R2, refined=False):
         seed=3 if not refined else 4)
 
 
+def advected_bubble(nx=8, ny=4, nz=4, degree=3, scheme=R2, amp=10.0):
+    """A warm bubble carried by a uniform wind through a periodic 40 x 20 x 10
+    km box (stratified rest state N = 0.01, theta0 = 300 K, f = 1e-4,
+    U = 20 m/s along x; Gaussian theta' of `amp` K and radius 2 km at
+    (8, 10, 4) km), dt = 2 s: the feature that a moving refinement box
+    follows in the adaptive runs."""
+    return Workload(
+        name="advected_bubble_%dx%dx%d_r%d" % (nx, ny, nz, degree),
+        mesh=MeshSpec(40e3, 20e3, 10e3, nx, ny, nz, degree),
+        phys=PhysSpec(f=1e-4),
+        num=NumSpec(dt=2.0, scheme=scheme),
+        steps=200, background="stratified", T0=300.0, N=0.01, U=20.0,
+        pert="gauss", pert_amp=amp, pert_a=2e3, pert_xc=8e3, pert_yc=10e3, pert_zc=4e3, seed=11)
+
+
 def hill_benchmark(rotating=True, nx=30, ny=20, nz=8, degree=4, scheme=R2):
     """Benchmark flow over orography of Sec. 4.3: a 60 x 40 x 16 km Gal-Chen box
     over the bell mountain h0 / (1 + r^2/a^2) (h0 = 400 m, a = 1 km, centre

@@ -123,3 +123,24 @@ def test_slice_model_needs_a_slice_mesh():
         out = ctypes.c_void_p()
         code = B.lib().imx_solver_create(m.h, ctypes.byref(ph), ctypes.byref(num), None, ctypes.byref(out))
         assert code == B.IMX_EINVAL and b"slice" in B.lib().imx_last_error()
+
+
+def test_transfer_plan_host_checks():
+    """imx_transfer_workspace_bytes builds the leaf map on the host: sizes for
+    refinements of one grid, refusal of different grids or of leaves more than
+    two levels apart."""
+    B = _binding()
+    base = dict(Lx=4e3, Ly=4e3, Lz=2e3, nx=4, ny=4, nz=2, degree=2)
+    a = B.Mesh(W.MeshSpec(**base))
+    b = B.Mesh(W.MeshSpec(**base, ref_boxes=[(1e3, 3e3, 1e3, 3e3, 0.0, 1e3)]))
+    n = ctypes.c_size_t()
+    assert B.lib().imx_transfer_workspace_bytes(a.h, b.h, ctypes.byref(n)) == B.IMX_OK
+    # leaf map, two W detJ arrays and the tables
+    assert n.value >= 8 * (a.E + b.E) * a.Np
+    other = B.Mesh(W.MeshSpec(**dict(base, nx=5)))
+    assert B.lib().imx_transfer_workspace_bytes(a.h, other.h, ctypes.byref(n)) == B.IMX_EINVAL
+    assert b"base grid" in B.lib().imx_last_error()
+    deep = B.Mesh(W.MeshSpec(**base, ref_boxes=[(0.2e3, 3.8e3, 0.2e3, 3.8e3, 0.0, 1.8e3),
+                                                 (1.1e3, 2.9e3, 1.1e3, 2.9e3, 0.0, 0.9e3),
+                                                 (1.6e3, 2.4e3, 1.6e3, 2.4e3, 0.0, 0.3e3)]))
+    assert B.lib().imx_transfer_workspace_bytes(a.h, deep.h, ctypes.byref(n)) == B.IMX_EINVAL
