@@ -267,47 +267,14 @@ def served_run(args):
     print(f"serve: queue alone makespan {serial['makespan_s']:.2f} s", file=sys.stderr, flush=True)
 
     def served(precision):
-        sv = B.Server(pool_bytes=args.serve_pool_gb << 30, max_running=args.serve_slots)
-        ids, i, t0 = [], 0, time.perf_counter()
-        first = None
-        while True:
-            now = time.perf_counter() - t0
-            while i < len(trace) and trace[i].arrival_s <= now:
-                r = trace[i]
-                ids.append((sv.submit(r.workload.mesh, r.workload.phys, r.workload.num, q0s[i], r.steps,
-                                      precision=precision), time.perf_counter() - t0))
-                first = first if first is not None else ids[-1][1]
-                i += 1
-            nr, nw = sv.tick()
-            if i == len(trace) and nr == 0 and nw == 0:
-                break
-            time.sleep(0.0005)
-        makespan = time.perf_counter() - t0 - first
-        st = sv.query()
-        lat, worst = [], 0.0
-        for k, (rid, t_sub) in enumerate(ids):
-            q, ms = sv.result(rid)
-            if ms.status != B.IMX_OK:
-                msg = B.lib().imx_server_last_error(sv.h).decode(errors="replace")
-                raise RuntimeError(f"served member {k} ({trace[k].workload.name}) failed with status {ms.status} "
-                                   f"after {ms.steps_done} steps: {msg}")
-            lat.append(1e-3 * (ms.queue_ms + ms.run_ms))
-            if precision == B.IMX_FP64:
-                worst = max(worst, float(np.abs(q - finals[k]).max()))
-            else:
-                worst = max(worst, max(field_errors(q, finals[k])["vs_tolerance_scale"].values()))
-        out = {"dof_updates_per_s": total / makespan, "makespan_s": makespan,
-               "step_ms_p50": st.p50_step_ms, "step_ms_p99": st.p99_step_ms,
-               "request_latency_s_p50": float(np.percentile(lat, 50)),
-               "request_latency_s_p99": float(np.percentile(lat, 99)),
-               "pool_gb": args.serve_pool_gb, "pool_peak_gb": st.pool_bytes_peak / 2 ** 30,
-               "slots": args.serve_slots, "completed": st.completed}
+        from paper_2605_29598_amd import ensemble
+        out, qs = ensemble.serve(trace, q0s, dofs, precision, args.serve_pool_gb, args.serve_slots)
         if precision == B.IMX_FP64:
-            out["max_abs_diff_vs_alone"] = worst
+            out["max_abs_diff_vs_alone"] = max(float(np.abs(q - f).max()) for q, f in zip(qs, finals))
         else:
-            out["max_rel_error_vs_fp64_alone_tolerance_scale"] = worst
-        del sv
-        print(f"serve: {'fp64' if precision == B.IMX_FP64 else 'mixed'} makespan {makespan:.2f} s",
+            out["max_rel_error_vs_fp64_alone_tolerance_scale"] = max(
+                max(field_errors(q, f)["vs_tolerance_scale"].values()) for q, f in zip(qs, finals))
+        print(f"serve: {'fp64' if precision == B.IMX_FP64 else 'mixed'} makespan {out['makespan_s']:.2f} s",
               file=sys.stderr, flush=True)
         return out
 

@@ -140,17 +140,20 @@ struct Geom {
     const double* eg;     // affine elements: h[3], 1/h[3], det J, 1/det J (8 per element)
     const R* iWJ;         // 1 / WJ (deformed meshes)
     const uint64_t* fofs; // face-point words per (round, lane), see fo_node
+    int gnx, gny, gnz, gpx, gpy;   // unrefined box meshes: base grid and periodicity
 };
 
 template <typename R>
 static Geom<R> geom(const DevMesh& m);
 template <>
 Geom<double> geom<double>(const DevMesh& m) {
-    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJ, m.G, m.nS, m.eg, m.iWJ, m.fofs};
+    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJ, m.G, m.nS, m.eg, m.iWJ, m.fofs,
+            m.gnx, m.gny, m.gnz, m.gpx, m.gpy};
 }
 template <>
 Geom<float> geom<float>(const DevMesh& m) {
-    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJf, m.Gf, m.nSf, m.eg, m.iWJf, m.fofs};
+    return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJf, m.Gf, m.nSf, m.eg, m.iWJf, m.fofs,
+            m.gnx, m.gny, m.gnz, m.gpx, m.gpy};
 }
 
 constexpr int epb_of(int N) { return N == 2 ? 16 : (N == 3 ? 9 : (N == 4 ? 4 : 2)); }
@@ -186,10 +189,74 @@ __device__ __forceinline__ int fo_node(uint64_t w, int m) { return (int)((w >> (
 __device__ __forceinline__ int fo_face(uint64_t w) { return (int)((w >> 40) & 0xff); }
 __device__ __forceinline__ int fo_point(uint64_t w) { return (int)((w >> 48) & 0xff); }
 
+// Neighbour across face f of element e of an unrefined box mesh (elements
+// numbered bz + nz (bx + nx by)): kind CONF (also across a periodic seam) or
+// WALL, computed instead of read from the face tables.
+template <typename R>
+__device__ __forceinline__ void grid_nbr(const Geom<R>& g, int e, int f, int& kind, int& nb) {
+    const int bz = e % g.gnz, t = e / g.gnz, bx = t % g.gnx, by = t / g.gnx;
+    const int d = f >> 1, step = (f & 1) ? 1 : -1;
+    int c[3] = {bx, by, bz};
+    const int n[3] = {g.gnx, g.gny, g.gnz}, per[3] = {g.gpx, g.gpy, 0};
+    int v = c[d] + step;
+    bool wall = false;
+    if (v < 0 || v >= n[d]) {
+        if (per[d]) v = v < 0 ? v + n[d] : v - n[d];
+        else wall = true;
+    }
+    c[d] = v;
+    kind = wall ? WALL : CONF;
+    nb = wall ? e : c[2] + g.gnz * (c[0] + g.gnx * c[1]);
+}
+
 template <int N>
 __device__ __forceinline__ int node_of(int d, int m, int a, int b) {
     return d == 0 ? m + N * (a + N * b) : (d == 1 ? a + N * (m + N * b) : a + N * (b + N * m));
 }
+
+// The face points a lane handles in the all-faces kernels: points
+// it = node + r NP (r < NR) of the element's 6 (r+1)^2 face points. With ST
+// (unrefined box meshes) face, point and the node offsets along the normal
+// are computed from `it`; otherwise they come from the host-built words.
+template <int N, bool ST>
+struct LanePoints {
+    static constexpr int NP = N * N * N, NF = N * N, NR = (6 * NF + NP - 1) / NP;
+    uint64_t fo[ST ? 1 : NR];
+    int node;
+    __device__ __forceinline__ void init(const uint64_t* __restrict__ fofs, int nd) {
+        node = nd;
+        if constexpr (!ST) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) fo[r] = fofs[r * NP + nd];
+        }
+    }
+    // face of point r (6: the lane has no point in round r)
+    __device__ __forceinline__ int face(int r) const {
+        if constexpr (ST) {
+            const int it = node + r * NP;
+            return it < 6 * NF ? it / NF : 6;
+        } else {
+            return fo_face(fo[r]);
+        }
+    }
+    __device__ __forceinline__ int point(int r) const {
+        if constexpr (ST) {
+            const int it = node + r * NP;
+            return it < 6 * NF ? it % NF : 0;
+        } else {
+            return fo_point(fo[r]);
+        }
+    }
+    // node offset within the element of the m-th node along the normal through point r
+    __device__ __forceinline__ int off(int r, int m) const {
+        if constexpr (ST) {
+            const int pt = point(r);
+            return node_of<N>(face(r) >> 1, m, pt % N, pt / N);
+        } else {
+            return fo_node(fo[r], m);
+        }
+    }
+};
 
 template <int N>
 __device__ __forceinline__ void split_node(int d, int node, int& m, int& pt) {
@@ -1506,7 +1573,7 @@ k_mv1_gc(const int* __restrict__ elist, int nel, const R* __restrict__ p, const 
     R* U = &s_u[le][0];
     R crv = 0, iwj = 0, rl = 0, gv[5] = {0, 0, 0, 0, 0}, nbv[NR][N], nsv[NR][3];
     int kf[NR], nf[NR];
-    uint64_t fo[NR];
+    LanePoints<N, false> lp;
     if (act) {
         const R pv = p[o];
         s_p[le][node] = pv;
@@ -1516,20 +1583,20 @@ k_mv1_gc(const int* __restrict__ elist, int nel, const R* __restrict__ p, const 
         if constexpr (SCH == 2) rl = rho[o];
 #pragma unroll
         for (int t = 0; t < 5; ++t) gv[t] = g.G[t * fs + o];
+        lp.init(g.fofs, node);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            fo[r] = g.fofs[r * NP + node];
             const bool full = (r + 1) * NP <= 6 * NF;   // every lane has a point in this round
-            const int f = fo_face(fo[r]);
+            const int f = lp.face(r);
             const bool has = full || f < 6;
             const int fc = has ? f : 5;
             kf[r] = has ? g.kind[e * 6 + fc] : WALL;
             nf[r] = g.nbr[e * 6 + fc];
-            nS_gc<N, R>(g, e, fc, fo_point(fo[r]), nsv[r]);
+            nS_gc<N, R>(g, e, fc, lp.point(r), nsv[r]);
             const bool ld = kf[r] == CONF;
             const R* src = p + (size_t)(unsigned)(ld ? nf[r] : 0) * NP;
 #pragma unroll
-            for (int m = 0; m < N; ++m) nbv[r][m] = ld ? src[fo_node(fo[r], m)] : (R)0;
+            for (int m = 0; m < N; ++m) nbv[r][m] = ld ? src[lp.off(r, m)] : (R)0;
         }
         const R pvs = sc * pv;
 #pragma unroll
@@ -1540,12 +1607,12 @@ k_mv1_gc(const int* __restrict__ elist, int nel, const R* __restrict__ p, const 
     if (act)
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int f = fo_face(fo[r]);
+            const int f = lp.face(r);
             if ((r + 1) * NP > 6 * NF && f >= 6) continue;
-            const int pt = fo_point(fo[r]), d = f >> 1, s = f & 1;
+            const int pt = lp.point(r), d = f >> 1, s = f & 1;
             R vals[N];
 #pragma unroll
-            for (int m = 0; m < N; ++m) vals[m] = s_p[le][fo_node(fo[r], m)];
+            for (int m = 0; m < N; ++m) vals[m] = s_p[le][lp.off(r, m)];
             const R pa = sc * trace_chain<N, R>(T.f[s], vals);
             R pb = pa;
             if (kf[r] == CONF) pb = sc * trace_chain<N, R>(T.f[1 - s], nbv[r]);
@@ -1620,19 +1687,19 @@ k_mv1_gc(const int* __restrict__ elist, int nel, const R* __restrict__ p, const 
         const R hfac = (R)sk.hfac;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int f = fo_face(fo[r]);
+            const int f = lp.face(r);
             if (((r + 1) * NP > 6 * NF && f >= 6) || kf[r] == WALL) continue;
-            const int pt = fo_point(fo[r]), s = f & 1;
+            const int pt = lp.point(r), s = f & 1;
             R vk[N];
 #pragma unroll
-            for (int m = 0; m < N; ++m) vk[m] = s_pk[le][fo_node(fo[r], m)];
+            for (int m = 0; m < N; ++m) vk[m] = s_pk[le][lp.off(r, m)];
             const R hk = hfac * trace_chain<N, R>(T.f[s], vk);
             R wn = 0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 R vw[N];
 #pragma unroll
-                for (int m = 0; m < N; ++m) vw[m] = s_a[le][c][fo_node(fo[r], m)];
+                for (int m = 0; m < N; ++m) vw[m] = s_a[le][c][lp.off(r, m)];
                 wn += trace_chain<N, R>(T.f[s], vw) * nsv[r][c];
             }
             FB[(size_t)(unsigned)(e * 6 + f) * NF + pt] = hk * wn;
@@ -1655,7 +1722,12 @@ k_mv1_gc(const int* __restrict__ elist, int nel, const R* __restrict__ p, const 
 
 // Schur pass 2 inside the Krylov loop: qw[0] holds the element's own volume
 // and gravity part formed by pass 1; the pressure and face terms are added.
-template <int N, typename R, bool AFF>
+// With ST (unrefined box meshes) the neighbour of each face comes from the
+// element index instead of the face tables, which takes two dependent loads
+// off the path to the neighbour's face buffer (orography box: 166 -> 127 us;
+// the same change made Schur pass 1 slower, 400 -> 560 us, and is not used
+// there).
+template <int N, typename R, bool AFF, bool ST>
 __global__ void __launch_bounds__(threads_mv(N))
 k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
       const R* __restrict__ qw, const R* __restrict__ FB,
@@ -1685,16 +1757,22 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
             if (dual) wjd = g.WJ[o];
         }
         // {(rho h)^k w} . n dS from the two sides' face buffers
+        LanePoints<N, ST> lp;
+        lp.init(g.fofs, node);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const uint64_t fo = g.fofs[r * NP + node];
-            const int f = fo_face(fo);
+            const int f = lp.face(r);
             if ((r + 1) * NP > 6 * NF && f >= 6) continue;
-            const int pt = fo_point(fo);
-            const int kind = g.kind[e * 6 + f];
+            const int pt = lp.point(r);
+            int kind, nb;
+            if constexpr (ST) {
+                grid_nbr<R>(g, e, f, kind, nb);
+            } else {
+                kind = g.kind[e * 6 + f];
+                nb = g.nbr[e * 6 + f];
+            }
             R v = 0;
             if (kind == CONF) {
-                const int nb = g.nbr[e * 6 + f];
                 v = (R)0.5 * (FB[(size_t)(unsigned)(e * 6 + f) * NF + pt] - FB[(size_t)(unsigned)(nb * 6 + (f ^ 1)) * NF + pt]);
             } else if (kind == FINE) {
                 const int aux = g.aux[e * 6 + f];
@@ -2167,8 +2245,8 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
                         hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s,
                                            fl, (int)nf, x, xs, cr, pk, rho, w, FB, geom<R>(m), T, sk, ctrl);
                     else
-                        hipLaunchKernelGGL((k_mv1_gc<N, R, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s,
-                                           fl, (int)nf, x, xs, cr, pk, rho, w, FB, geom<R>(m), T, sk, ctrl);
+                        hipLaunchKernelGGL((k_mv1_gc<N, R, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
+                                           (int)nf, x, xs, cr, pk, rho, w, FB, geom<R>(m), T, sk, ctrl);
                 }
             },
             [&](hipStream_t s) {
@@ -2182,10 +2260,16 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
         fork_join(
             m, st,
             [&](hipStream_t s) {
-                if (bf > 0)
-                    hipLaunchKernelGGL((k_mv2<N, R, AFF>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
-                                       (int)nf, x, xs, (const R*)w, (const R*)FB, (const R*)FBh, out, dual,
-                                       geom<R>(m), T, sk, ctrl);
+                if (bf > 0) {
+                    if (m.structured)
+                        hipLaunchKernelGGL((k_mv2<N, R, AFF, true>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s,
+                                           fl, (int)nf, x, xs, (const R*)w, (const R*)FB, (const R*)FBh, out, dual,
+                                           geom<R>(m), T, sk, ctrl);
+                    else
+                        hipLaunchKernelGGL((k_mv2<N, R, AFF, false>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s,
+                                           fl, (int)nf, x, xs, (const R*)w, (const R*)FB, (const R*)FBh, out, dual,
+                                           geom<R>(m), T, sk, ctrl);
+                }
             },
             [&](hipStream_t s) {
                 if (bs > 0)

@@ -31,6 +31,10 @@ struct DevMesh {
     const double* iWJ = nullptr;    // [E*Np] 1 / WJ (deformed meshes)
     const float* iWJf = nullptr;
     const uint64_t* fofs = nullptr; // [fofs_count(n)] face-point words of the all-faces kernels
+    // unrefined box meshes: element e = bz + nz (bx + nx by), so neighbours and
+    // face kinds follow from the index (structured != 0 once the host has
+    // checked this against the face tables)
+    int structured = 0, gnx = 0, gny = 0, gnz = 0, gpx = 0, gpy = 0;
     int64_t ncoarse = 0;            // elements owning a coarse hanging face
     const int* reg_list = nullptr;  // [E - ncoarse] the other elements
     const int* crs_list = nullptr;  // [ncoarse]

@@ -1001,6 +1001,41 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
         HIPCHK(hipStreamSynchronize(s->st));
         return IMX_OK;
     };
+    {
+        // unrefined box: neighbours and face kinds follow from the element
+        // index; use that in the all-faces kernels only if it reproduces the
+        // face tables exactly
+        const imx_mesh_desc& d = m.desc;
+        DevMesh& dm = s->dm;
+        dm.structured = 0;
+        dm.gnx = d.nx;
+        dm.gny = d.ny;
+        dm.gnz = d.nz;
+        dm.gpx = d.periodic_x ? 1 : 0;
+        dm.gpy = d.periodic_y ? 1 : 0;
+        if (m.nh == 0 && m.E == (int64_t)d.nx * d.ny * d.nz) {
+            bool ok = true;
+            for (int64_t e = 0; e < m.E && ok; ++e) {
+                const int bz = (int)(e % d.nz), t = (int)(e / d.nz), bx = t % d.nx, by = t / d.nx;
+                for (int f = 0; f < 6 && ok; ++f) {
+                    const int dir = f >> 1, step = (f & 1) ? 1 : -1;
+                    int c[3] = {bx, by, bz};
+                    const int n[3] = {d.nx, d.ny, d.nz}, per[3] = {dm.gpx, dm.gpy, 0};
+                    int v = c[dir] + step;
+                    bool wall = false;
+                    if (v < 0 || v >= n[dir]) {
+                        if (per[dir]) v = v < 0 ? v + n[dir] : v - n[dir];
+                        else wall = true;
+                    }
+                    c[dir] = v;
+                    const int kind = wall ? WALL : CONF;
+                    const int nb = c[2] + d.nz * (c[0] + d.nx * c[1]);
+                    ok = m.fkind[6 * e + f] == kind && (wall || m.fnbr[6 * e + f] == nb);
+                }
+            }
+            dm.structured = ok ? 1 : 0;
+        }
+    }
     CHK(up(s->dm.kind, m.fkind.data(), m.fkind.size() * sizeof(int)));
     CHK(up(s->dm.nbr, m.fnbr.data(), m.fnbr.size() * sizeof(int)));
     CHK(up(s->dm.aux, m.faux.data(), m.faux.size() * sizeof(int)));

@@ -306,24 +306,40 @@ class Request:
 
 def served_trace(n_requests=64, rate_per_s=2.0, elem_min=2000, elem_max=200000, degrees=(2, 3, 4), steps=50,
                  seed=5):
-    """Ensemble requests with Poisson arrivals: exponential gaps of mean
-    1/rate, each member a rotating IGW channel or an orography member with
-    element count uniform in [elem_min, elem_max] (rounded to the nearest
-    layout the family allows), degree drawn from `degrees`, and a seeded
-    1e-6 perturbation of its own."""
+    """Ensemble requests with Poisson arrivals (exponential gaps of mean
+    1/rate). Each member is, with probability 1/2, a rotating IGW channel
+    (the channel's physics and 25 x 25 x 1 km elements, nz = 10, nx = 3 ny,
+    ny = round(sqrt(E / 30))) or an orography member (the orography box's
+    physics and 0.9375 x 0.9375 x 0.833 km elements, nz = 24, nx = ny =
+    round(sqrt(E / 24)), the hill at the centre), with E uniform in
+    [elem_min, elem_max] and the degree drawn from `degrees`: the element sizes,
+    and with them the Courant numbers, are those of the two workloads. Each
+    member has its own seeded potential-temperature perturbation, amplitude
+    0.01 K x (1 + 0.1 xi) with its centre moved by up to 5 % of the domain."""
     g = np.random.default_rng(seed)
     t, out = 0.0, []
     for k in range(n_requests):
         t += g.exponential(1.0 / rate_per_s)
         E = g.uniform(elem_min, elem_max)
         r = int(g.choice(degrees))
+        amp = 0.01 * (1.0 + 0.1 * g.uniform(-1.0, 1.0))
+        jx, jy = g.uniform(-0.05, 0.05, 2)
         if g.uniform() < 0.5:
             ny = max(2, int(round(np.sqrt(E / 30.0))))
             w = igw_channel(nx=3 * ny, ny=ny, nz=10, degree=r)
+            w.mesh.Lx, w.mesh.Ly = 25e3 * 3 * ny, 25e3 * ny
+            w.pert_xc = w.mesh.Lx * (0.5 + jx)
+            w.pert_a = min(100e3, 0.1 * w.mesh.Lx)
+            w.pert_amp = amp
         else:
-            n = max(3, int(round(np.sqrt(E / 12.0))))
-            w = orography(nx=n, ny=n, nz=12, degree=r)
-        w.noise, w.seed = 1e-6, 1000 + k
+            n = max(3, int(round(np.sqrt(E / 24.0))))
+            w = orography(nx=n, ny=n, nz=24, degree=r)
+            L = 0.9375e3 * n
+            w.mesh.Lx = w.mesh.Ly = L
+            w.mesh.xc = w.mesh.yc = L / 2
+            w.pert, w.pert_amp, w.pert_a = "gauss", amp, 2e3
+            w.pert_xc, w.pert_yc, w.pert_zc = L * (0.5 + jx), L * (0.5 + jy), 2e3
+        w.seed = 1000 + k
         w.name += "_m%d" % k
         out.append(Request(t, w, steps))
     return out
