@@ -229,8 +229,9 @@ def served_run(args):
     # members are scaled down from the full ensemble (E uniform in 2k-200k, 50
     # steps, Poisson arrivals at 2/s); the arrival rate is scaled up by the same
     # factor as the work per member, so the offered load matches the full trace
+    from paper_2605_29598_amd import ensemble
     e_lo, e_hi = 2000, 24000
-    rate = 2.0 * ((2000 + 200000) / (e_lo + e_hi)) * (50.0 / args.serve_steps)
+    rate = ensemble.scaled_rate(e_lo, e_hi, args.serve_steps)
     trace = W.served_trace(n_requests=args.serve_requests, rate_per_s=rate, elem_min=e_lo, elem_max=e_hi,
                            steps=args.serve_steps, seed=5)
     meshes, q0s, dofs = [], [], []
@@ -267,7 +268,6 @@ def served_run(args):
     print(f"serve: queue alone makespan {serial['makespan_s']:.2f} s", file=sys.stderr, flush=True)
 
     def served(precision):
-        from paper_2605_29598_amd import ensemble
         out, qs = ensemble.serve(trace, q0s, dofs, precision, args.serve_pool_gb, args.serve_slots)
         if precision == B.IMX_FP64:
             out["max_abs_diff_vs_alone"] = max(float(np.abs(q - f).max()) for q, f in zip(qs, finals))

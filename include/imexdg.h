@@ -356,6 +356,10 @@ imx_status imx_server_tick(imx_server* sv, int* n_running, int* n_waiting);
  * IMX_ESTATE while it has not finished, IMX_EINVAL for an unknown id. */
 imx_status imx_server_result(imx_server* sv, uint64_t id, double* q_host, imx_member_stats* stats);
 imx_status imx_server_query(imx_server* sv, imx_server_stats* stats);
+/* Members admitted after this call replay the chunks of their Krylov loop
+ * from HIP graphs (enable != 0; see imx_solver_set_graphs) or launch every
+ * kernel directly (0, the default). Results are bitwise the same either way. */
+imx_status imx_server_set_graphs(imx_server* sv, int enable);
 /* Waits for running members, then destroys the server. */
 void imx_server_destroy(imx_server* sv);
 /* Description of the last failure of a call on this server ("" if none);

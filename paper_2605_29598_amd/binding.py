@@ -110,6 +110,7 @@ SIGNATURES = {
     "imx_server_result": (ctypes.c_int, [_vp, ctypes.c_uint64, _vp, ctypes.POINTER(imx_member_stats)]),
     "imx_server_query": (ctypes.c_int, [_vp, ctypes.POINTER(imx_server_stats)]),
     "imx_server_destroy": (None, [_vp]),
+    "imx_server_set_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
     "imx_transfer_workspace_bytes": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]),
     "imx_transfer_state": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_size_t, _vp, _vp, ctypes.c_int, _vp]),
 }
@@ -369,6 +370,9 @@ class Server:
                                           ctypes.byref(h)), "imx_server_create")
         self.h = h
         self.shapes = {}
+
+    def set_graphs(self, enable):
+        check(lib().imx_server_set_graphs(self.h, int(bool(enable))), "imx_server_set_graphs", server=self.h)
 
     def submit(self, spec: W.MeshSpec, phys: W.PhysSpec, num: W.NumSpec, q0, nsteps, precision=IMX_FP64,
                inner_tol=1e-3):

@@ -120,6 +120,7 @@ struct imx_server {
     Clock::time_point t_first_admit, t_last_done;
     std::vector<double> all_step_ms;
     double dof_updates = 0.0;
+    int graphs = 0;    // members admitted from now on replay their Krylov chunks from HIP graphs
     std::string err;   // last error raised by a call on this server
 };
 
@@ -262,6 +263,7 @@ imx_status imx_server_tick(imx_server* sv, int* n_running, int* n_waiting) {
         }
         if (rc == IMX_OK) rc = imx_solver_create(m->mesh, &m->phys, &m->num, m->stream, &m->solver);
         if (rc == IMX_OK) rc = imx_solver_bind_workspace(m->solver, sv->pool_base + off, m->ws_bytes);
+        if (rc == IMX_OK && sv->graphs) rc = imx_solver_set_graphs(m->solver, 1);
         m->t_admit = Clock::now();
         it = sv->waiting.erase(it);
         if (rc != IMX_OK) {
@@ -346,6 +348,14 @@ imx_status imx_server_query(imx_server* sv, imx_server_stats* st) {
     st->p99_step_ms = percentile(sv->all_step_ms, 0.99);
     st->dof_updates = sv->dof_updates;
     st->busy_seconds = sv->any_admit && sv->completed ? ms_since(sv->t_first_admit, sv->t_last_done) * 1e-3 : 0.0;
+    return IMX_OK;
+}
+
+imx_status imx_server_set_graphs(imx_server* sv, int enable) {
+    imx::ErrScope es_(sv ? &sv->err : nullptr);
+    if (!sv) return IMX_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->graphs = enable ? 1 : 0;
     return IMX_OK;
 }
 

@@ -10,6 +10,11 @@ alone through a plain solver.
 
     python -m paper_2605_29598_amd.ensemble serve [--precision fp64|mixed] [--requests 64] [--steps 50]
     python -m paper_2605_29598_amd.ensemble alone [--requests 64] [--steps 3]
+    python -m paper_2605_29598_amd.ensemble graphs-ab --requests 24 --elem-max 24000 --steps 20 --pool-gb 64
+
+`graphs-ab` serves the trace four times in one process, alternating direct
+launches and Krylov-chunk graph replay, and checks that the final states are
+bitwise equal.
 """
 import argparse
 import json
@@ -19,6 +24,14 @@ import time
 import numpy as np
 
 from . import workloads as W
+
+
+def scaled_rate(elem_min, elem_max, steps):
+    """Arrival rate of a trace scaled down from the full ensemble (elements
+    uniform in 2k-200k, 50 steps, arrivals at 2/s): scaled up by the same factor
+    as the work per member, so that the offered load relative to the work is
+    the same."""
+    return 2.0 * ((2000 + 200000) / (elem_min + elem_max)) * (50.0 / steps)
 
 
 def prepare(trace, log=None):
@@ -35,12 +48,14 @@ def prepare(trace, log=None):
     return q0s, dofs
 
 
-def serve(trace, q0s, dofs, precision, pool_gb, slots, log=None):
+def serve(trace, q0s, dofs, precision, pool_gb, slots, log=None, graphs=False):
     """Submits every request at its arrival time and ticks the server until
-    all are done; returns the aggregate figures and the final states."""
+    all are done; returns the aggregate figures and the final states. With
+    `graphs` the members replay their Krylov chunks from HIP graphs."""
     from . import binding as B
     total = float(sum(d * r.steps for d, r in zip(dofs, trace)))
     sv = B.Server(pool_bytes=int(pool_gb) << 30, max_running=slots)
+    sv.set_graphs(graphs)
     ids, i, t0, first, done = [], 0, time.perf_counter(), None, set()
     while True:
         now = time.perf_counter() - t0
@@ -78,7 +93,7 @@ def serve(trace, q0s, dofs, precision, pool_gb, slots, log=None):
            "request_latency_s_p50": float(np.percentile(lat, 50)),
            "request_latency_s_p99": float(np.percentile(lat, 99)),
            "pool_gb": pool_gb, "pool_peak_gb": st.pool_bytes_peak / 2 ** 30, "slots": slots,
-           "completed": st.completed}
+           "completed": st.completed, "graphs": bool(graphs)}
     del sv
     return out, finals
 
@@ -112,28 +127,42 @@ def alone(trace, q0s, dofs, steps, warmup=1, log=None):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description="served ensemble at the stated shape")
-    ap.add_argument("mode", choices=["serve", "alone"])
+    ap.add_argument("mode", choices=["serve", "alone", "graphs-ab"])
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--elem-min", type=int, default=2000)
     ap.add_argument("--elem-max", type=int, default=200000)
-    ap.add_argument("--rate", type=float, default=2.0)
+    ap.add_argument("--rate", type=float, default=None,
+                    help="arrivals per second (default: 2/s scaled by the work per member)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--pool-gb", type=int, default=200)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--alone-steps", type=int, default=3)
+    ap.add_argument("--graphs", action="store_true", help="members replay their Krylov chunks from HIP graphs")
     a = ap.parse_args(argv)
     from . import binding as B
-    trace = W.served_trace(n_requests=a.requests, rate_per_s=a.rate, elem_min=a.elem_min, elem_max=a.elem_max,
+    rate = a.rate if a.rate is not None else scaled_rate(a.elem_min, a.elem_max, a.steps)
+    trace = W.served_trace(n_requests=a.requests, rate_per_s=rate, elem_min=a.elem_min, elem_max=a.elem_max,
                            steps=a.steps, seed=5)
     q0s, dofs = prepare(trace, log=sys.stdout)
-    if a.mode == "serve":
+    if a.mode == "graphs-ab":
         prec = B.IMX_MIXED if a.precision == "mixed" else B.IMX_FP64
-        out, _ = serve(trace, q0s, dofs, prec, a.pool_gb, a.slots, log=sys.stdout)
+        runs, ref = [], None
+        for graphs in (False, True, False, True):
+            out, finals = serve(trace, q0s, dofs, prec, a.pool_gb, a.slots, graphs=graphs)
+            ref = finals if ref is None else ref
+            out["bitwise_equal_to_first_run"] = all(np.array_equal(x, y) for x, y in zip(ref, finals))
+            runs.append(out)
+            print(json.dumps({k: out[k] for k in ("graphs", "dof_updates_per_s", "makespan_s", "step_ms_p50",
+                                                  "step_ms_p99", "bitwise_equal_to_first_run")}), flush=True)
+        out = {"runs": runs, "precision": a.precision}
+    elif a.mode == "serve":
+        prec = B.IMX_MIXED if a.precision == "mixed" else B.IMX_FP64
+        out, _ = serve(trace, q0s, dofs, prec, a.pool_gb, a.slots, log=sys.stdout, graphs=a.graphs)
         out["precision"] = a.precision
     else:
         out = alone(trace, q0s, dofs, a.alone_steps, log=sys.stdout)
-    out.update({"requests": a.requests, "steps": a.steps, "elements": [a.elem_min, a.elem_max], "rate": a.rate})
+    out.update({"requests": a.requests, "steps": a.steps, "elements": [a.elem_min, a.elem_max], "rate": rate})
     print("SUMMARY " + json.dumps(out), flush=True)
 
 

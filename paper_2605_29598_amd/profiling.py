@@ -10,6 +10,11 @@ sources: a summary taken from other kernels is not used.
     python -m paper_2605_29598_amd.profiling \
         --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \
         --copy-bytes 1073741824 --out profiles/pmc_traffic_<workload>.json
+
+Any other counters (occupancy, VALU and LDS activity, instruction counts) are
+averaged per kernel and printed as a markdown table:
+
+    python -m paper_2605_29598_amd.profiling counters A.csv [B.csv ...] [--match REGEX]
 """
 import argparse
 import collections
@@ -81,6 +86,33 @@ def summarize(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes):
         "kernels": {c: {"bytes_per_launch": b / n, "dispatches": n} for c, (b, n) in classes.items()},
         "per_kernel": kernels,
     }
+
+
+def counter_table(paths, match=None):
+    """Mean value per dispatch of every counter in the given rocprofv3 CSVs,
+    per kernel (kernels whose name matches `match`, if given)."""
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    res = {}
+    for path in paths:
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if match and not re.search(match, r["Kernel_Name"]):
+                    continue
+                k = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                per[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+                res[k] = (r["VGPR_Count"], r["Accum_VGPR_Count"], r["SGPR_Count"], r["LDS_Block_Size"],
+                          r["Workgroup_Size"])
+    names = sorted({c for v in per.values() for c in v})
+    head = ["kernel", "dispatches", "VGPR", "AGPR", "SGPR", "LDS B", "WG"] + names
+    rows = ["| " + " | ".join(head) + " |", "|---" * len(head) + "|"]
+    for k in sorted(per):
+        n = max(len(v) for v in per[k].values())
+        cells = [f"`{k}`", str(n)] + list(res[k])
+        for c in names:
+            v = per[k].get(c)
+            cells.append("" if not v else f"{sum(v) / len(v):.4g}")
+        rows.append("| " + " | ".join(cells) + " |")
+    return "\n".join(rows)
 
 
 WORKLOADS = {
@@ -249,6 +281,14 @@ def main():
         ap.add_argument("--reps", type=int, default=20)
         a = ap.parse_args()
         print(json.dumps(operators(a.workload, a.reps)))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "counters":
+        ap = argparse.ArgumentParser(description="per-kernel mean of rocprofv3 counters")
+        ap.add_argument("mode")
+        ap.add_argument("csv", nargs="+")
+        ap.add_argument("--match", default=None, help="regular expression on the kernel name")
+        a = ap.parse_args()
+        print(counter_table(a.csv, a.match))
         return
     ap = argparse.ArgumentParser()
     for a in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--out"):

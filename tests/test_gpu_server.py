@@ -66,11 +66,14 @@ def _drain(sv, limit_s=120.0):
         time.sleep(0.002)
 
 
-def test_mix_equals_alone_bitwise():
+@pytest.mark.parametrize("graphs", [False, True])
+def test_mix_equals_alone_bitwise(graphs):
     B = _B()
     mem = _members()
     ref = [_alone(*m) for m in mem]
     sv = B.Server(pool_bytes=4 << 30, max_running=6)
+    # with graphs the members replay their Krylov chunks from HIP graphs
+    sv.set_graphs(graphs)
     ids = [sv.submit(*m) for m in mem]
     _drain(sv)
     st = sv.query()

@@ -1,0 +1,53 @@
+"""Host logic of the counter summaries: the copy calibration and the per-class
+byte counts, and the per-kernel counter table, on small synthetic rocprofv3
+CSV files (no GPU)."""
+import csv
+
+from paper_2605_29598_amd import profiling as P
+
+FIELDS = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "Thread_Id", "Grid_Size",
+          "Kernel_Id", "Kernel_Name", "Workgroup_Size", "LDS_Block_Size", "Scratch_Size", "VGPR_Count",
+          "Accum_VGPR_Count", "SGPR_Count", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+
+
+def _csv(path, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        for i, (kernel, counter, value) in enumerate(rows):
+            w.writerow({"Correlation_Id": i, "Dispatch_Id": i, "Agent_Id": "Agent 1", "Queue_Id": 1,
+                        "Process_Id": 1, "Thread_Id": 1, "Grid_Size": 256, "Kernel_Id": 1,
+                        "Kernel_Name": kernel, "Workgroup_Size": 256, "LDS_Block_Size": 1024,
+                        "Scratch_Size": 0, "VGPR_Count": 64, "Accum_VGPR_Count": 0, "SGPR_Count": 32,
+                        "Counter_Name": counter, "Counter_Value": value, "Start_Timestamp": 0,
+                        "End_Timestamp": 1})
+    return str(path)
+
+
+def test_traffic_summary_scales_by_the_copy(tmp_path):
+    copy = "void copy_kernel(double*)"
+    # the probe copies 1 MiB: FETCH_SIZE reads 512 KiB (factor 2), WRITE_SIZE 1024 KiB (factor 1)
+    cf = _csv(tmp_path / "cf.csv", [(copy, "FETCH_SIZE", 512.0), ("void small()", "FETCH_SIZE", 1.0)])
+    cw = _csv(tmp_path / "cw.csv", [(copy, "WRITE_SIZE", 1024.0)])
+    k1 = "void imx::k_mv2<5, double, false>(int const*)"
+    k2 = "void imx::k_dots<double, 4, 7, false>(double const*)"
+    f = _csv(tmp_path / "f.csv", [(k1, "FETCH_SIZE", 100.0), (k1, "FETCH_SIZE", 300.0), (k2, "FETCH_SIZE", 50.0)])
+    w = _csv(tmp_path / "w.csv", [(k1, "WRITE_SIZE", 10.0), (k1, "WRITE_SIZE", 30.0), (k2, "WRITE_SIZE", 0.0)])
+    rec = P.summarize(f, w, cf, cw, 1 << 20)
+    assert rec["calibration"]["fetch_factor"] == 2.0 and rec["calibration"]["write_factor"] == 1.0
+    assert rec["kernels"]["pass2"]["dispatches"] == 2
+    assert rec["kernels"]["pass2"]["bytes_per_launch"] == 1024.0 * (2.0 * 200.0 + 20.0)
+    assert rec["kernels"]["dots"]["bytes_per_launch"] == 1024.0 * 2.0 * 50.0
+    assert rec["kernel_source_hash"] == P.kernel_source_hash()
+
+
+def test_counter_table_means_per_kernel(tmp_path):
+    k1 = "void imx::k_explicit_gc<5, double>(int const*, long)"
+    k2 = "void imx::k_givens(double*)"
+    a = _csv(tmp_path / "a.csv", [(k1, "SQ_WAVES", 10.0), (k1, "SQ_WAVES", 30.0), (k2, "SQ_WAVES", 1.0)])
+    b = _csv(tmp_path / "b.csv", [(k1, "VALUBusy", 12.5)])
+    t = P.counter_table([a, b], match="k_explicit")
+    lines = t.splitlines()
+    assert lines[0] == "| kernel | dispatches | VGPR | AGPR | SGPR | LDS B | WG | SQ_WAVES | VALUBusy |"
+    assert len(lines) == 3
+    assert lines[2] == "| `imx::k_explicit_gc<5, double>` | 2 | 64 | 0 | 32 | 1024 | 256 | 20 | 12.5 |"
