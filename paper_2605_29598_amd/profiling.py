@@ -29,7 +29,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 # kernel-name stem -> class reported by the solver's timers
 CLASSES = {
-    "k_explicit": "explicit", "k_pass1": "pass1", "k_mv1": "pass1", "k_mv1_gc": "pass1", "k_pass2": "pass2",
+    "k_explicit": "explicit", "k_explicit_gc": "explicit", "k_pass1": "pass1", "k_mv1": "pass1", "k_mv1_gc": "pass1", "k_pass2": "pass2",
     "k_mv2": "pass2",
     "k_mv2w": "pass2", "k_lambda": "lambda", "k_dots": "dots", "k_axpy_norm": "ortho", "k_lincomb": "lincomb",
 }
