@@ -25,11 +25,15 @@ and by its closed form on a free stream; its place in the IMEX split (the
 non-stiff part) and its target state (rho u_target) are a reading, not stated
 in the paper.
 
-The energy dissipation is split into lambda/2 [rho kappa] (non-stiff) and
-lambda/2 [rho e] (stiff). Its sum is pinned against a textbook total-energy
-Rusanov residual of the full Euler equations (tests/test_oracle_bruteforce.py),
-and the implicit stage operators (C^k, M_g, Lambda^k, k^k, B, R, f_g) are
-pinned term by term against the explicit stiff part T_S
+Face values are formed from the traces of the nodal (rho, u, p), the
+variables in which Sec. 3 writes its averages and jumps and on whose traces
+the stage operators B and C act. The energy dissipation is split into
+lambda/2 [rho kappa] (non-stiff) and lambda/2 [rho e] (stiff). Its sum is
+pinned against a textbook total-energy Rusanov residual of the full Euler
+equations (tests/test_oracle_bruteforce.py); the implicit stage operators
+(C^k, M_g, Lambda^k, k^k, B, R, f_g) are pinned term by term against the
+explicit stiff part T_S, and the whole stage equation of Sec. 3 is pinned at
+converged stages of ARK2 steps from random states, row by row to round-off
 (tests/test_oracle_stage_pins.py), so the lagged Lambda^k is the stiff
 dissipation of the explicit residual. Which part of the split is stiff is the
 paper's statement (the energy stage equations of Sec. 3), not a derived

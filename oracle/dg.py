@@ -213,6 +213,16 @@ def explicit_residual(mesh: Mesh, phys: Phys, q):
     rho, m, rho*kappa (and the optional sponge). Stiff: pressure p I with a
     centred flux, enthalpy flux rho h u with Rusanov dissipation on rho e,
     gravity -rho g k and Coriolis -rho f k x u, and the gravity work -rho g w.
+
+    Face values are formed from the traces of the nodal primitive fields
+    (rho, u, p): the averages and jumps of Sec. 3 are written in rho, u, p, h,
+    kappa and e, and the stage operators B and C act on the traces of the
+    unknowns p and u, so T_S evaluated here at a converged stage is the same
+    discrete operator as the one the stage equation was solved with (and the
+    final update, whose implicit weights equal the last stage's, reproduces
+    the stage solution). Taking the face values from traces of the conserved
+    fields instead gives u_face = trace(m)/trace(rho), not trace(u): a linear
+    difference about a stratified state that the update then fails to cancel.
     """
     gam = phys.gamma
     rho, m, E, u, kin, p = primitives(q, gam)
@@ -238,20 +248,20 @@ def explicit_residual(mesh: Mesh, phys: Phys, q):
         for c in range(3):
             TNS[1 + c] -= WJ * lam * (m[c] - rho * phys.sponge_u[c])
 
-    def flux(qA, qB, nS):
+    def flux(PA, PB, nS):
+        # PA, PB: traces of (rho, u, p) on the two sides; slip walls mirror u
         nh, dS = _unit(nS)
-        if qB is None:
-            qB = qA.copy()
-            qB[1:4] = _mirror(qA[1:4], nh)
+        if PB is None:
+            PB = PA.copy()
+            PB[1:4] = _mirror(PA[1:4], nh)
         sides = []
-        for qq in (qA, qB):
-            r, mm, EE = qq[0], qq[1:4], qq[4]
-            uu = mm / r
+        for P in (PA, PB):
+            r, uu, pp = P[0], P[1:4], P[4]
+            mm = r * uu
             kk = 0.5 * (uu * uu).sum(0)
-            pp = (gam - 1.0) * (EE - r * kk)
             un = np.einsum('cfp,fpc->fp', uu, nh)
-            sides.append((r, mm, EE, uu, kk, pp, un))
-        (rA, mA, EA, uA, kA, pA, unA), (rB, mB, EB, uB, kB, pB, unB) = sides
+            sides.append((r, mm, uu, kk, pp, un))
+        (rA, mA, uA, kA, pA, unA), (rB, mB, uB, kB, pB, unB) = sides
         lam = np.maximum(np.abs(unA), np.abs(unB))
         mnA = np.einsum('cfp,fpc->fp', mA, nS)
         mnB = np.einsum('cfp,fpc->fp', mB, nS)
@@ -268,7 +278,7 @@ def explicit_residual(mesh: Mesh, phys: Phys, q):
         out[9] = 0.5 * (hA * unSA + hB * unSB) + 0.5 * lam * (pA - pB) / (gam - 1.0) * dS
         return out
 
-    Fc = face_integrals(mesh, q, flux, 10)
+    Fc = face_integrals(mesh, np.concatenate([rho[None], u, p[None]]), flux, 10)
     TNS -= Fc[:5]
     TS -= Fc[5:]
     return TNS, TS

@@ -7,7 +7,9 @@ T_NS + T_S on a periodic 1 x 1 x nz column of boxes with slip walls at the
 bottom and top, interpolating the nodal state to Q points per direction:
 Q = r + 1 reproduces the oracle (checked in the test), Q > r + 1 integrates
 the nonlinear and variable-coefficient products more exactly
-(over-integration). It is written for flat boxes only.
+(over-integration). Face values come from the traces of the nodal primitive
+fields (rho, u, p), as in the method; the volume integrands from the
+conserved state at the Q points. It is written for flat boxes only.
 """
 import numpy as np
 
@@ -22,6 +24,20 @@ def prim(q):
     k = 0.5 * (u * u).sum(0)
     p = (GAM - 1) * (E - rho * k)
     return rho, m, E, u, k, p
+
+
+def nodal_prims(qq):
+    """(rho, u, p) of a nodal conserved state (5, ...)."""
+    rho = qq[0]
+    u = qq[1:4] / rho
+    p = (GAM - 1) * (qq[4] - 0.5 * rho * (u * u).sum(0))
+    return np.concatenate([rho[None], u, p[None]])
+
+
+def cons(P):
+    """Conserved state from (rho, u, p) (5, ...)."""
+    rho, u, p = P[0], P[1:4], P[4]
+    return np.concatenate([rho[None], rho * u, (p / (GAM - 1) + 0.5 * rho * (u * u).sum(0))[None]])
 
 
 def face_flux(qA, qB, nS, wall):
@@ -77,6 +93,7 @@ class Column:
         n, Q, (hx, hy, hz), nz = self.n, self.Q, self.h, self.nz
         L, D, F, wq = self.L, self.D, self.F, self.wq
         qq = q.reshape(5, nz, n, n, n)
+        Pn = nodal_prims(qq)
         Vq = self.quad(qq)
         rho, m, E, u, k, p = prim(Vq)
         J = hx * hy * hz
@@ -105,20 +122,20 @@ class Column:
         # faces: traces at the quad points of each face
         W2 = lambda w1, w2: np.einsum('b,a->ba', w1, w2)
         # x faces (periodic, one element): A = element at x=1, B = same element at x=0
-        tA = np.einsum('fekji,i,bj,ck->fecb', qq, F[1], L, L)
-        tB = np.einsum('fekji,i,bj,ck->fecb', qq, F[0], L, L)
+        tA = cons(np.einsum('fekji,i,bj,ck->fecb', Pn, F[1], L, L))
+        tB = cons(np.einsum('fekji,i,bj,ck->fecb', Pn, F[0], L, L))
         fl = face_flux(tA, tB, [hy * hz, 0, 0], False) * np.einsum('c,b->cb', wq, wq)
         T -= np.einsum('tecb,i,bj,ck->tekji', fl, F[1], L, L)
         T += np.einsum('tecb,i,bj,ck->tekji', fl, F[0], L, L)
         # y faces
-        tA = np.einsum('fekji,ai,j,ck->feca', qq, L, F[1], L)
-        tB = np.einsum('fekji,ai,j,ck->feca', qq, L, F[0], L)
+        tA = cons(np.einsum('fekji,ai,j,ck->feca', Pn, L, F[1], L))
+        tB = cons(np.einsum('fekji,ai,j,ck->feca', Pn, L, F[0], L))
         fl = face_flux(tA, tB, [0, hx * hz, 0], False) * np.einsum('c,a->ca', wq, wq)
         T -= np.einsum('teca,ai,j,ck->tekji', fl, L, F[1], L)
         T += np.einsum('teca,ai,j,ck->tekji', fl, L, F[0], L)
         # z faces: interior between e (top, s=1) and e+1 (bottom, s=0); walls at the ends
-        top = np.einsum('fekji,ai,bj,k->feba', qq, L, L, F[1])
-        bot = np.einsum('fekji,ai,bj,k->feba', qq, L, L, F[0])
+        top = cons(np.einsum('fekji,ai,bj,k->feba', Pn, L, L, F[1]))
+        bot = cons(np.einsum('fekji,ai,bj,k->feba', Pn, L, L, F[0]))
         wba = np.einsum('b,a->ba', wq, wq)
         nS = [0, 0, hx * hy]
         if nz > 1:

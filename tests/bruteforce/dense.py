@@ -303,6 +303,24 @@ class Dense:
         return Mg
 
     # ---------------------------------------------------- nonlinear vectors
+    @staticmethod
+    def _nodal_prims(q, gamma):
+        """(rho, u, p) at the nodes of every element: (5, E, Np)."""
+        rho = q[0]
+        u = q[1:4] / rho
+        p = (gamma - 1) * (q[4] - 0.5 * rho * (u * u).sum(0))
+        return np.concatenate([rho[None], u, p[None]])
+
+    @staticmethod
+    def _face_state(v, P, e, gamma):
+        """Conserved state at a face point from the traces of the nodal
+        primitives (the face values of the method: averages and jumps of rho,
+        u, p and of what is formed from them)."""
+        r = v @ P[0, e]
+        u = np.array([v @ P[1 + c, e] for c in range(3)])
+        p = v @ P[4, e]
+        return np.concatenate([[r], r * u, [p / (gamma - 1) + 0.5 * r * (u @ u)]])
+
     def explicit_residual(self, q, gamma, g, f):
         """T_NS and T_S (5, E, Np) by direct point-by-point quadrature."""
         E, Np = self.E, self.Np
@@ -316,6 +334,7 @@ class Dense:
             p = (gamma - 1) * (Et - rho * k)
             return rho, m, Et, u, k, p
 
+        P = self._nodal_prims(q, gamma)
         for e in range(E):
             V, G, WJ, _ = self.vol[e]
             for qp in range(V.shape[0]):
@@ -337,13 +356,13 @@ class Dense:
                 for (v, nb, vn, wq, area) in pts:
                     dS = np.linalg.norm(area)
                     nh = area / dS
-                    sA = np.array([v @ q[fd, e] for fd in range(5)])
+                    sA = self._face_state(v, P, e, gamma)
                     if nb < 0:
                         sB = sA.copy()
                         mB = sA[1:4] - 2 * (sA[1:4] @ nh) * nh
                         sB[1:4] = mB
                     else:
-                        sB = np.array([vn @ q[fd, nb] for fd in range(5)])
+                        sB = self._face_state(vn, P, nb, gamma)
                     rA, mA, EA, uA, kA, pA = prim(sA)
                     rB, mB, EB, uB, kB, pB = prim(sB)
                     lam = max(abs(uA @ nh), abs(uB @ nh))
@@ -365,10 +384,12 @@ class Dense:
         F = (m, m u^T + p I, (E + p) u) and the Rusanov flux
         F^ . n = {F(q) . n} + lambda/2 (q^- - q^+), lambda = max |u^+- . n|
         applied to every conserved variable, rho E included; slip walls by
-        the mirror state. Written in total-energy form, without the split of
-        the energy flux and its dissipation into advective and stiff parts."""
+        the mirror state; face states from the traces of the nodal
+        primitives. Written in total-energy form, without the split of the
+        energy flux and its dissipation into advective and stiff parts."""
         E, Np = self.E, self.Np
         out = np.zeros((5, E, Np))
+        P = self._nodal_prims(q, gamma)
 
         def flux_tensor(s):
             rho, m, Et = s[0], s[1:4], s[4]
@@ -390,12 +411,12 @@ class Dense:
                 for (v, nb, vn, wq, area) in pts:
                     dS = np.linalg.norm(area)
                     nh = area / dS
-                    sA = np.array([v @ q[fd, e] for fd in range(5)])
+                    sA = self._face_state(v, P, e, gamma)
                     if nb < 0:
                         sB = sA.copy()
                         sB[1:4] = sA[1:4] - 2 * (sA[1:4] @ nh) * nh
                     else:
-                        sB = np.array([vn @ q[fd, nb] for fd in range(5)])
+                        sB = self._face_state(vn, P, nb, gamma)
                     FA, uA = flux_tensor(sA)
                     FB, uB = flux_tensor(sB)
                     lam = max(abs(uA @ nh), abs(uB @ nh))

@@ -329,7 +329,10 @@ def test_advection_reduces_to_upwind_dg():
             assert np.abs(got[:, k, j, :].ravel() - ref).max() < 1e-12
     assert np.abs(y[1] - U * y[0]).max() < 1e-11
     _, _, _, u, _, p = dg.primitives(y, 1.4)
-    assert np.abs(p - 1e5).max() < 1e-8
+    # p = 1e5 exactly in exact arithmetic; it is recovered from rho E = 2.5e5
+    # plus the kinetic part after three steps of stage solves at GMRES
+    # tolerance 1e-14: a few units in the last place of rho E
+    assert np.abs(p - 1e5).max() < 5e-13 * 1e5
 
 
 def test_mass_conservation():

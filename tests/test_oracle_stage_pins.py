@@ -14,15 +14,21 @@ must be the matching explicit term times -a~_ll dt:
 with c = a~_ll dt. The test states are chosen so that these hold to round-off:
 density and velocity constant in each element (but jumping across faces, so
 lambda and the jumps of rho e are nonzero on every face) and the pressure a
-random polynomial per element. Then the energy is linear in p within each
-element and the pressure the explicit residual forms from face traces of
-(rho, rho u, rho E) is the trace of p, as in the implicit operators. (For a
-general state the two differ: T_S forms p from traces of the conserved
-variables, B and C^k take traces of the unknown p; at a converged stage of
-the ARK2 step the stage equation therefore holds only up to that difference,
-1e-3 to 1e-2 relative on random states, not to round-off.) A sign or side
-error in Lambda^k, C^k, M_g or k^k leaves a residual of the size of that term
-(checked below by planting such errors in the oracle).
+random polynomial per element. A sign or side error in Lambda^k, C^k, M_g or
+k^k leaves a residual of the size of that term (checked below by planting
+such errors in the oracle).
+
+The stage equation itself is pinned at converged stages of whole ARK2 steps
+from random states: with the Picard and GMRES loops converged to 1e-14,
+
+    M (Y_l - y^n) - dt sum_{m<l} (a_lm T_NS + a~_lm T_S)(Y_m) - dt a~_ll T_S(Y_l) = 0
+
+row by row to round-off, for l = 2, 3, R1 and R2, on walled, periodic,
+terrain-following and hanging-face meshes, with T_NS and T_S from the explicit
+residual. This ties every implicit operator to the explicit stiff part at a
+general state, and it holds because both take their face values from the
+traces of (rho, u, p); with face values from traces of the conserved
+variables it fails at 1e-3 relative (planted below).
 
 The Picard variation measure is pinned by closed forms on manufactured iterate
 pairs.
@@ -139,6 +145,61 @@ def test_stage_identity_detects_planted_mistakes(monkeypatch, what):
     _planted(monkeypatch, what)
     res = stage_term_residuals(mesh, dg.Phys(f=1e-3, g=9.81), dg.R2)
     assert max(res.values()) > 1e4 * IDENTITY_BAR, (what, res)
+
+
+# --------------------------------------------------------- stage equation
+STAGE_EQ_BAR = 1e-11
+
+
+def stage_equation_residuals(mesh, scheme, seed=5):
+    """Largest relative residual of the stage equation of each row at the
+    converged stages 2 and 3 of one ARK2 step: the density row against
+    M rho_l, the momentum and energy rows against dt a~_ll T_S(Y_l)."""
+    q = W.random_positive_state((mesh.E, mesh.Np), seed, urms=5.0, rel=0.02)
+    phys = dg.Phys(f=1e-4, g=9.81)
+    num = dg.Numerics(dt=3.0, scheme=scheme, picard_tol=1e-14, gmres_tol=1e-14, picard_max=60, gmres_max=2000)
+    _, st = dg.ark2_step(mesh, phys, num, q, return_stages=True)
+    Ys, T = st["stages"], st["residuals"]
+    Mw = mesh.W3 * mesh.detJ
+    worst = np.zeros(5)
+    for l in (1, 2):
+        implicit = num.dt * dg.A_IMP[l, l] * T[l][1]
+        res = Mw * (Ys[l] - q) - num.dt * sum(dg.A_EXP[l, m] * T[m][0] + dg.A_IMP[l, m] * T[m][1]
+                                              for m in range(l)) - implicit
+        scale = np.abs(implicit).reshape(5, -1).max(1)
+        scale[0] = np.abs(Mw * Ys[l][0]).max()
+        worst = np.maximum(worst, np.abs(res).reshape(5, -1).max(1) / scale)
+    return worst
+
+
+@pytest.mark.parametrize("name", list(STAGE_MESHES))
+@pytest.mark.parametrize("scheme", [dg.R1, dg.R2])
+def test_stage_equation_holds_at_converged_stages(name, scheme):
+    worst = stage_equation_residuals(_mesh(name), scheme)
+    assert worst.max() < STAGE_EQ_BAR, worst
+
+
+def test_stage_equation_detects_conserved_face_traces(monkeypatch):
+    """Planted: the explicit residual's face values from traces of the
+    conserved variables (u_face = trace(m) / trace(rho)) while the stage
+    operators take traces of u and p."""
+    orig = dg.face_integrals
+    gam = dg.Phys().gamma
+
+    def conserved_traces(mesh, fields, flux, nout):
+        if nout != 10:
+            return orig(mesh, fields, flux, nout)
+        rho, u, p = fields[0], fields[1:4], fields[4]
+        q = np.concatenate([rho[None], rho * u, (p / (gam - 1) + 0.5 * rho * (u * u).sum(0))[None]])
+
+        def prim(qq):
+            uu = qq[1:4] / qq[0]
+            pp = (gam - 1) * (qq[4] - 0.5 * qq[0] * (uu * uu).sum(0))
+            return np.concatenate([qq[0][None], uu, pp[None]])
+        return orig(mesh, q, lambda qA, qB, nS: flux(prim(qA), None if qB is None else prim(qB), nS), nout)
+    monkeypatch.setattr(dg, "face_integrals", conserved_traces)
+    worst = stage_equation_residuals(_mesh("terrain_r2"), dg.R2)
+    assert worst.max() > 1e4 * STAGE_EQ_BAR, worst
 
 
 # --------------------------------------------------------- Picard variation
