@@ -273,6 +273,24 @@ __device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(
 __device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
 __device__ __forceinline__ double fma_rn(double a, double b, double c) { return __fma_rn(a, b, c); }
 __device__ __forceinline__ float fma_rn(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+__device__ __forceinline__ double div_rn(double a, double b) { return __ddiv_rn(a, b); }
+__device__ __forceinline__ float div_rn(float a, float b) { return __fdiv_rn(a, b); }
+
+// (rho, u, p) of a node from its conserved (rho, m, E). Face values are
+// traces of these primitives; each operation is rounded on its own, so the
+// lane that stages its own node and a lane that gathers it as a neighbour
+// value get the same bits (both sides of a face then trace the same values).
+template <typename R>
+__device__ __forceinline__ void prim_of(const R* c, R* P, R gm1) {
+    const R r = c[0];
+    const R u0 = div_rn(c[1], r), u1 = div_rn(c[2], r), u2 = div_rn(c[3], r);
+    const R kin = mul_rn((R)0.5, add_rn(add_rn(mul_rn(u0, u0), mul_rn(u1, u1)), mul_rn(u2, u2)));
+    P[0] = r;
+    P[1] = u0;
+    P[2] = u1;
+    P[3] = u2;
+    P[4] = mul_rn(gm1, add_rn(c[4], -mul_rn(r, kin)));
+}
 
 // Trace of a Q_r field along the normal: sum over m (in order) of
 // l_m(s) v_m as one product and a chain of fused multiply-adds. Every trace
@@ -295,6 +313,28 @@ __device__ __forceinline__ R face_value(const P* f, const R* fv, int d, int pt) 
 #pragma unroll
     for (int m = 0; m < N; ++m) v[m] = (R)f[node_of<N>(d, m, a, b)];
     return trace_chain<N, R>(fv, v);
+}
+
+// traces of (rho, u, p) of one element (conserved fields at q + t * fs + base)
+// at face point pt: each node along the normal converted by prim_of, then the
+// chain of trace_chain per field
+template <int N, typename R>
+__device__ __forceinline__ void face_value_prim(const R* q, size_t fs, size_t base, const R* fv, int d, int pt,
+                                                R gm1, R* P) {
+    const int a = pt % N, b = pt / N;
+    R acc[5];
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const size_t nd = base + node_of<N>(d, m, a, b);
+        R c[5], v[5];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) c[t] = q[t * fs + nd];
+        prim_of<R>(c, v, gm1);
+#pragma unroll
+        for (int t = 0; t < 5; ++t) acc[t] = m == 0 ? mul_rn(fv[0], v[t]) : fma_rn(fv[m], v[t], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 5; ++t) P[t] = acc[t];
 }
 
 // face polynomial with GL values fv (LDS) at GL point pt of quarter h
@@ -405,44 +445,45 @@ __device__ __forceinline__ R div_T(const R* G, const Tab<N, R>& T, int node) {
 }
 
 // ---------------------------------------------------------- Euler fluxes
-// Normal fluxes seen from side A (area vector nS of side A): 0..4 non-stiff
-// (rho, m, E with Rusanov dissipation on rho, m, rho kappa), 5..7 stiff
-// pressure {p} nS, 8 stiff enthalpy {rho h u}.nS + Rusanov on rho e.
+// Normal fluxes seen from side A (area vector nS of side A) from the face
+// values (rho, u, p) of both sides: 0..4 non-stiff (rho, m, E with Rusanov
+// dissipation on rho, m, rho kappa; m = rho u, kappa = |u|^2 / 2), 5..7
+// stiff pressure {p} nS, 8 stiff enthalpy {rho h u}.nS + Rusanov on rho e.
+// A slip wall mirrors u.
 template <typename R>
-__device__ __forceinline__ void euler_flux(const R* qa, const R* qbin, const R* nS, bool wall, R gm1, R igm1, R hfac,
+__device__ __forceinline__ void euler_flux(const R* pa, const R* pbin, const R* nS, bool wall, R igm1, R hfac,
                                            R* fl) {
     const R dS = sqrt(nS[0] * nS[0] + nS[1] * nS[1] + nS[2] * nS[2]);
     const R idS = (R)1 / dS;
     const R nh[3] = {nS[0] * idS, nS[1] * idS, nS[2] * idS};
-    R qb[5];
+    R pb[5];
     if (wall) {
-        const R mn = qa[1] * nh[0] + qa[2] * nh[1] + qa[3] * nh[2];
-        qb[0] = qa[0];
-        qb[4] = qa[4];
-        for (int c = 0; c < 3; ++c) qb[1 + c] = qa[1 + c] - (R)2 * mn * nh[c];
+        const R un = pa[1] * nh[0] + pa[2] * nh[1] + pa[3] * nh[2];
+        pb[0] = pa[0];
+        pb[4] = pa[4];
+        for (int c = 0; c < 3; ++c) pb[1 + c] = pa[1 + c] - (R)2 * un * nh[c];
     } else {
-        for (int t = 0; t < 5; ++t) qb[t] = qbin[t];
+        for (int t = 0; t < 5; ++t) pb[t] = pbin[t];
     }
-    const R irA = (R)1 / qa[0], irB = (R)1 / qb[0];
-    R uA[3], uB[3];
+    const R rA = pa[0], rB = pb[0];
+    const R uA[3] = {pa[1], pa[2], pa[3]}, uB[3] = {pb[1], pb[2], pb[3]};
+    R mA[3], mB[3];
     for (int c = 0; c < 3; ++c) {
-        uA[c] = qa[1 + c] * irA;
-        uB[c] = qb[1 + c] * irB;
+        mA[c] = rA * uA[c];
+        mB[c] = rB * uB[c];
     }
     const R kA = (R)0.5 * (uA[0] * uA[0] + uA[1] * uA[1] + uA[2] * uA[2]);
     const R kB = (R)0.5 * (uB[0] * uB[0] + uB[1] * uB[1] + uB[2] * uB[2]);
-    const R pA = gm1 * (qa[4] - qa[0] * kA);
-    const R pB = gm1 * (qb[4] - qb[0] * kB);
+    const R pA = pa[4], pB = pb[4];
     const R unSA = uA[0] * nS[0] + uA[1] * nS[1] + uA[2] * nS[2];
     const R unSB = uB[0] * nS[0] + uB[1] * nS[1] + uB[2] * nS[2];
     // lambda dS = max(|u_A . n|, |u_B . n|) dS = max(|u_A . nS|, |u_B . nS|)
     const R hl = (R)0.5 * fmax(fabs(unSA), fabs(unSB));
-    const R mnA = qa[1] * nS[0] + qa[2] * nS[1] + qa[3] * nS[2];
-    const R mnB = qb[1] * nS[0] + qb[2] * nS[1] + qb[3] * nS[2];
-    fl[0] = (R)0.5 * (mnA + mnB) + hl * (qa[0] - qb[0]);
-    for (int c = 0; c < 3; ++c)
-        fl[1 + c] = (R)0.5 * (qa[1 + c] * unSA + qb[1 + c] * unSB) + hl * (qa[1 + c] - qb[1 + c]);
-    fl[4] = (R)0.5 * (kA * mnA + kB * mnB) + hl * (qa[0] * kA - qb[0] * kB);
+    const R mnA = mA[0] * nS[0] + mA[1] * nS[1] + mA[2] * nS[2];
+    const R mnB = mB[0] * nS[0] + mB[1] * nS[1] + mB[2] * nS[2];
+    fl[0] = (R)0.5 * (mnA + mnB) + hl * (rA - rB);
+    for (int c = 0; c < 3; ++c) fl[1 + c] = (R)0.5 * (mA[c] * unSA + mB[c] * unSB) + hl * (mA[c] - mB[c]);
+    fl[4] = (R)0.5 * (kA * mnA + kB * mnB) + hl * (rA * kA - rB * kB);
     const R pavg = (R)0.5 * (pA + pB);
     for (int c = 0; c < 3; ++c) fl[5 + c] = pavg * nS[c];
     const R hA = hfac * pA, hB = hfac * pB;
@@ -473,6 +514,30 @@ __device__ __forceinline__ R coarse_point(const P* f, const R* fv, const Tab<N, 
     return acc;
 }
 
+// coarse_point for the five primitives (rho, u, p) of the coarse neighbour
+// (conserved fields at q + t * fs + base)
+template <int N, typename R>
+__device__ __forceinline__ void coarse_point_prim(const R* q, size_t fs, size_t base, const R* fv, const Tab<N, R>& T,
+                                                  int d, int sub, int pt, R gm1, R* P) {
+    const int a = pt % N, b = pt / N, h1 = sub & 1, h2 = sub >> 1;
+    R acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll 1
+    for (int bb = 0; bb < N; ++bb) {
+        R s[5] = {0, 0, 0, 0, 0};
+#pragma unroll 1
+        for (int aa = 0; aa < N; ++aa) {
+            R v[5];
+            face_value_prim<N, R>(q, fs, base, fv, d, aa + N * bb, gm1, v);
+#pragma unroll
+            for (int t = 0; t < 5; ++t) s[t] += T.H[h1][a][aa] * v[t];
+        }
+#pragma unroll
+        for (int t = 0; t < 5; ++t) acc[t] += T.H[h2][b][bb] * s[t];
+    }
+#pragma unroll
+    for (int t = 0; t < 5; ++t) P[t] = acc[t];
+}
+
 // =====================================================================
 // Explicit residual: fNS = M^{-1} T_NS, fS = M^{-1} T_S (momentum, energy)
 // =====================================================================
@@ -493,8 +558,13 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
     const int64_t e = act ? (elist ? (int64_t)elist[slot] : slot) : 0;
     const size_t fs = (size_t)g.E * NP;
     const R gm1 = (R)ph.gm1, igm1 = (R)ph.igm1, hfac = (R)ph.hfac;
-    if (act)
-        for (int t = 0; t < 5; ++t) s_q[le][t][node] = q[t * fs + e * NP + node];
+    // the element's own nodes as (rho, u, p): face values are their traces
+    if (act) {
+        R c[5], P[5];
+        for (int t = 0; t < 5; ++t) c[t] = q[t * fs + e * NP + node];
+        prim_of<R>(c, P, gm1);
+        for (int t = 0; t < 5; ++t) s_q[le][t][node] = P[t];
+    }
     constexpr bool slow = SLOW;
     __syncthreads();
     R acc[9];
@@ -510,13 +580,12 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
                 R qa[5], qb[5], nS[3], fl[9];
                 for (int t = 0; t < 5; ++t) qa[t] = face_value<N>(&s_q[le][t][0], T.f[s], d, pt);
                 if (kind == CONF)
-                    for (int t = 0; t < 5; ++t) qb[t] = face_value<N>(q + t * fs + (size_t)nbr * NP, T.f[1 - s], d, pt);
+                    face_value_prim<N, R>(q, fs, (size_t)nbr * NP, T.f[1 - s], d, pt, gm1, qb);
                 else if (kind == FINE)
-                    for (int t = 0; t < 5; ++t)
-                        qb[t] = coarse_point<N>(q + t * fs + (size_t)nbr * NP, T.f[1 - s], T, d,
-                                                g.aux[e * 6 + f] & 3, pt);
+                    coarse_point_prim<N, R>(q, fs, (size_t)nbr * NP, T.f[1 - s], T, d, g.aux[e * 6 + f] & 3, pt, gm1,
+                                            qb);
                 area_t<N, R, AFF>(g, T, e, f, pt, nS);
-                euler_flux<R>(qa, qb, nS, kind == WALL, gm1, igm1, hfac, fl);
+                euler_flux<R>(qa, qb, nS, kind == WALL, igm1, hfac, fl);
                 for (int o = 0; o < 9; ++o) U[(f * 9 + o) * NF + pt] = fl[o];
             }
         __syncthreads();
@@ -539,9 +608,11 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
             const int aux = act ? g.aux[e * 6 + f] : 0;
             if (act && node < NF) {
                 for (int t = 0; t < 5; ++t) s_own[t * NF + node] = face_value<N>(&s_q[le][t][0], T.f[s], d, node);
-                if (kind == CONF || kind == FINE)
-                    for (int t = 0; t < 5; ++t)
-                        s_nb[t * NF + node] = face_value<N>(q + t * fs + (size_t)nbr * NP, T.f[1 - s], d, node);
+                if (kind == CONF || kind == FINE) {
+                    R P[5];
+                    face_value_prim<N, R>(q, fs, (size_t)nbr * NP, T.f[1 - s], d, node, gm1, P);
+                    for (int t = 0; t < 5; ++t) s_nb[t * NF + node] = P[t];
+                }
             }
             __syncthreads();
             if (act) {
@@ -552,10 +623,8 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
                     bool wall = false;
                     if (kind == COARSE) {
                         const int fn = g.hang[nbr * 4 + hs];
-                        for (int t = 0; t < 5; ++t) {
-                            qa[t] = sub_interp<N>(s_own + t * NF, T, hs, pt);
-                            qb[t] = face_value<N>(q + t * fs + (size_t)fn * NP, T.f[1 - s], d, pt);
-                        }
+                        for (int t = 0; t < 5; ++t) qa[t] = sub_interp<N>(s_own + t * NF, T, hs, pt);
+                        face_value_prim<N, R>(q, fs, (size_t)fn * NP, T.f[1 - s], d, pt, gm1, qb);
                         area_t<N, R, AFF>(g, T, fn, f ^ 1, pt, nS);
                         for (int c = 0; c < 3; ++c) nS[c] = -nS[c];
                     } else {
@@ -568,7 +637,7 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
                             wall = true;
                         area_t<N, R, AFF>(g, T, e, f, pt, nS);
                     }
-                    euler_flux<R>(qa, qb, nS, wall, gm1, igm1, hfac, fl);
+                    euler_flux<R>(qa, qb, nS, wall, igm1, hfac, fl);
                     if (kind == COARSE)
                         for (int o = 0; o < 9; ++o) s_sub[(hs * 9 + o) * NF + pt] = fl[o];
                     else
@@ -595,13 +664,15 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
     __syncthreads();   // the volume staging reuses the face buffers
 
     // volume terms, three outputs per round: U[(o3*3 + d)*NP + node]
-    R rho = 1, u[3] = {0, 0, 0}, kin = 0, p = 0, wj = 1;
+    R rho = 1, u[3] = {0, 0, 0}, mom[3] = {0, 0, 0}, kin = 0, p = 0, wj = 1;
     if (act) {
         rho = s_q[le][0][node];
-        const R irho = (R)1 / rho;
-        for (int c = 0; c < 3; ++c) u[c] = s_q[le][1 + c][node] * irho;
+        for (int c = 0; c < 3; ++c) {
+            u[c] = s_q[le][1 + c][node];
+            mom[c] = rho * u[c];
+        }
         kin = (R)0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-        p = gm1 * (s_q[le][4][node] - rho * kin);
+        p = s_q[le][4][node];
         wj = AFF ? T.W3[node] * (R)g.eg[e * 8 + 6] : g.WJ[e * NP + node];
     }
     for (int r3 = 0; r3 < 3; ++r3) {
@@ -610,12 +681,12 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
                 const int o = 3 * r3 + o3;
                 R F[3];
                 if (o == 0) {
-                    for (int c = 0; c < 3; ++c) F[c] = s_q[le][1 + c][node];
+                    for (int c = 0; c < 3; ++c) F[c] = mom[c];
                 } else if (o < 4) {
-                    const R mo = s_q[le][o][node];
+                    const R mo = mom[o - 1];
                     for (int c = 0; c < 3; ++c) F[c] = mo * u[c];
                 } else if (o == 4) {
-                    for (int c = 0; c < 3; ++c) F[c] = kin * s_q[le][1 + c][node];
+                    for (int c = 0; c < 3; ++c) F[c] = kin * mom[c];
                 } else if (o < 8) {
                     for (int c = 0; c < 3; ++c) F[c] = (c == o - 5) ? p : (R)0;
                 } else {
@@ -647,7 +718,7 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
     acc[8] -= wj * rho * (R)ph.g * u[2];
     if (ph.sponge) {
         const R lam = (R)sponge[e * NP + node];
-        for (int c = 0; c < 3; ++c) acc[1 + c] -= wj * lam * (s_q[le][1 + c][node] - rho * (R)ph.su[c]);
+        for (int c = 0; c < 3; ++c) acc[1 + c] -= wj * lam * (mom[c] - rho * (R)ph.su[c]);
     }
     const R iwj = AFF ? T.iW3[node] * (R)g.eg[e * 8 + 7] : g.iWJ[e * NP + node];
     for (int t = 0; t < 5; ++t) fNS[t * fs + e * NP + node] = acc[t] * iwj;
@@ -693,8 +764,13 @@ k_explicit_gc(const int* __restrict__ elist, int64_t nel, const R* __restrict__ 
     int kf[NR], nf[NR];
     uint64_t fo[NR];
     if (act) {
+        // the own node as (rho, u, p): face values are traces of these
+        R c[5], P[5];
 #pragma unroll
-        for (int t = 0; t < 5; ++t) s_q[le][t][node] = q[t * fs + o];
+        for (int t = 0; t < 5; ++t) c[t] = q[t * fs + o];
+        prim_of<R>(c, P, gm1);
+#pragma unroll
+        for (int t = 0; t < 5; ++t) s_q[le][t][node] = P[t];
 #pragma unroll
         for (int t = 0; t < 5; ++t) gv[t] = g.G[t * fs + o];
         iwj = g.iWJ[o];
@@ -731,23 +807,26 @@ k_explicit_gc(const int* __restrict__ elist, int64_t nel, const R* __restrict__ 
                 qa[t] = trace_chain<N, R>(T.f[s], v);
             }
             if (kf[r] == FINE) {
-#pragma unroll 1
-                for (int t = 0; t < 5; ++t)
-                    qb[t] = coarse_point<N>(q + t * fs + (size_t)nf[r] * NP, T.f[1 - s], T, d,
-                                            g.aux[e * 6 + f] & 3, pt);
-            } else {
-                // the neighbour's values along the normal (conforming and periodic faces)
-                const bool ld = kf[r] == CONF;
-                const size_t nb = (size_t)(ld ? nf[r] : 0) * NP;
+                coarse_point_prim<N, R>(q, fs, (size_t)nf[r] * NP, T.f[1 - s], T, d, g.aux[e * 6 + f] & 3, pt, gm1,
+                                        qb);
+            } else if (kf[r] == CONF) {
+                // the neighbour's nodes along the normal (conforming and periodic
+                // faces), each converted to (rho, u, p), traced by the same chain
+                const size_t nb = (size_t)nf[r] * NP;
 #pragma unroll
-                for (int t = 0; t < 5; ++t) {
-                    R v[N];
+                for (int m = 0; m < N; ++m) {
+                    R c[5], v[5];
 #pragma unroll
-                    for (int m = 0; m < N; ++m) v[m] = ld ? q[t * fs + nb + fo_node(fo[r], m)] : (R)0;
-                    qb[t] = trace_chain<N, R>(T.f[1 - s], v);
+                    for (int t = 0; t < 5; ++t) c[t] = q[t * fs + nb + fo_node(fo[r], m)];
+                    prim_of<R>(c, v, gm1);
+#pragma unroll
+                    for (int t = 0; t < 5; ++t) qb[t] = m == 0 ? mul_rn(T.f[1 - s][0], v[t]) : fma_rn(T.f[1 - s][m], v[t], qb[t]);
                 }
+            } else {
+#pragma unroll
+                for (int t = 0; t < 5; ++t) qb[t] = qa[t];   // wall: mirrored inside the flux
             }
-            euler_flux<R>(qa, qb, nsv[r], kf[r] == WALL, gm1, igm1, hfac, fl);
+            euler_flux<R>(qa, qb, nsv[r], kf[r] == WALL, igm1, hfac, fl);
 #pragma unroll
             for (int k = 0; k < 9; ++k) U[(f * 9 + k) * NF + pt] = fl[k];
             // one face point at a time: keeps the next point's gathers from
@@ -768,10 +847,11 @@ k_explicit_gc(const int* __restrict__ elist, int64_t nel, const R* __restrict__ 
     if (act)
 #pragma unroll
         for (int t = 0; t < 5; ++t) qv[t] = s_q[le][t][node];
-    const R rho = qv[0], irho = (R)1 / rho;
-    const R u[3] = {qv[1] * irho, qv[2] * irho, qv[3] * irho};
+    const R rho = qv[0];
+    const R u[3] = {qv[1], qv[2], qv[3]};
+    const R mom[3] = {rho * u[0], rho * u[1], rho * u[2]};
     const R kin = (R)0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    const R p = gm1 * (qv[4] - rho * kin);
+    const R p = qv[4];
     const int ix = node % N, jy = (node / N) % N, kz = node / (N * N);
     // contravariant components of a flux vector F into U[3*a .. 3*a+2]
     auto stage3 = [&](int a, R F0, R F1, R F2) {
@@ -794,9 +874,9 @@ k_explicit_gc(const int* __restrict__ elist, int64_t nel, const R* __restrict__ 
     };
     // round 1: mass flux and the x and y momentum fluxes
     if (act) {
-        stage3(0, qv[1], qv[2], qv[3]);
-        stage3(1, qv[1] * u[0], qv[1] * u[1], qv[1] * u[2]);
-        stage3(2, qv[2] * u[0], qv[2] * u[1], qv[2] * u[2]);
+        stage3(0, mom[0], mom[1], mom[2]);
+        stage3(1, mom[0] * u[0], mom[0] * u[1], mom[0] * u[2]);
+        stage3(2, mom[1] * u[0], mom[1] * u[1], mom[1] * u[2]);
     }
     __syncthreads();
     if (act) {
@@ -807,8 +887,8 @@ k_explicit_gc(const int* __restrict__ elist, int64_t nel, const R* __restrict__ 
     __syncthreads();
     // round 2: z momentum, kinetic energy and enthalpy fluxes
     if (act) {
-        stage3(0, qv[3] * u[0], qv[3] * u[1], qv[3] * u[2]);
-        stage3(1, kin * qv[1], kin * qv[2], kin * qv[3]);
+        stage3(0, mom[2] * u[0], mom[2] * u[1], mom[2] * u[2]);
+        stage3(1, kin * mom[0], kin * mom[1], kin * mom[2]);
         const R rh = hfac * p;
         stage3(2, rh * u[0], rh * u[1], rh * u[2]);
     }
@@ -844,7 +924,7 @@ k_explicit_gc(const int* __restrict__ elist, int64_t nel, const R* __restrict__ 
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
         R v = acc[t] * iwj;
-        if (t >= 1 && t <= 3 && ph.sponge) v -= lam * (qv[t] - rho * (R)ph.su[t - 1]);
+        if (t >= 1 && t <= 3 && ph.sponge) v -= lam * (mom[t - 1] - rho * (R)ph.su[t - 1]);
         fNS[t * fs + o] = v;
     }
     fS[o] = acc[5] * iwj + rho * fc * u[1];
