@@ -541,7 +541,9 @@ __device__ __forceinline__ void coarse_point_prim(const R* q, size_t fs, size_t 
 // =====================================================================
 // Explicit residual: fNS = M^{-1} T_NS, fS = M^{-1} T_S (momentum, energy)
 // =====================================================================
-template <int N, typename R, bool SLOW, bool AFF>
+// HANG = false compiles out the coarse-neighbour interpolation, for meshes
+// without hanging faces (it sets the register count of the all-faces path).
+template <int N, typename R, bool SLOW, bool AFF, bool HANG = true>
 __global__ void __launch_bounds__(threads_of(N))
 k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, R* __restrict__ fNS, R* __restrict__ fS, Geom<R> g, const Tab<N, R>* __restrict__ Tg,
            PhysK ph, const double* __restrict__ sponge) {
@@ -581,9 +583,11 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
                 for (int t = 0; t < 5; ++t) qa[t] = face_value<N>(&s_q[le][t][0], T.f[s], d, pt);
                 if (kind == CONF)
                     face_value_prim<N, R>(q, fs, (size_t)nbr * NP, T.f[1 - s], d, pt, gm1, qb);
-                else if (kind == FINE)
-                    coarse_point_prim<N, R>(q, fs, (size_t)nbr * NP, T.f[1 - s], T, d, g.aux[e * 6 + f] & 3, pt, gm1,
-                                            qb);
+                else if (HANG && kind == FINE) {
+                    if constexpr (HANG)
+                        coarse_point_prim<N, R>(q, fs, (size_t)nbr * NP, T.f[1 - s], T, d, g.aux[e * 6 + f] & 3, pt,
+                                                gm1, qb);
+                }
                 area_t<N, R, AFF>(g, T, e, f, pt, nS);
                 euler_flux<R>(qa, qb, nS, kind == WALL, igm1, hfac, fl);
                 for (int o = 0; o < 9; ++o) U[(f * 9 + o) * NF + pt] = fl[o];
@@ -740,7 +744,7 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
 //    outputs take 23 contractions in three rounds;
 //  - the sources (gravity, Coriolis, sponge) are added after the division by
 //    W detJ, which they carry as a factor, so W detJ itself is not read.
-template <int N, typename R>
+template <int N, typename R, bool HANG = true>
 __global__ void __launch_bounds__(threads_of(N))
 k_explicit_gc(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, R* __restrict__ fNS,
               R* __restrict__ fS, Geom<R> g, const Tab<N, R>* __restrict__ Tg, PhysK ph,
@@ -806,9 +810,10 @@ k_explicit_gc(const int* __restrict__ elist, int64_t nel, const R* __restrict__ 
                 for (int m = 0; m < N; ++m) v[m] = s_q[le][t][fo_node(fo[r], m)];
                 qa[t] = trace_chain<N, R>(T.f[s], v);
             }
-            if (kf[r] == FINE) {
-                coarse_point_prim<N, R>(q, fs, (size_t)nf[r] * NP, T.f[1 - s], T, d, g.aux[e * 6 + f] & 3, pt, gm1,
-                                        qb);
+            if (HANG && kf[r] == FINE) {
+                if constexpr (HANG)
+                    coarse_point_prim<N, R>(q, fs, (size_t)nf[r] * NP, T.f[1 - s], T, d, g.aux[e * 6 + f] & 3, pt,
+                                            gm1, qb);
             } else if (kf[r] == CONF) {
                 // the neighbour's nodes along the normal (conforming and periodic
                 // faces), each converted to (rho, u, p), traced by the same chain
@@ -2233,14 +2238,21 @@ static void launch_split(const DevMesh& m, KF fast, KS slow, hipStream_t st, Arg
 template <typename R>
 void launch_explicit(const DevMesh& m, const HostTab&, const PhysK& ph, const R* q, R* fNS, R* fS,
                      hipStream_t st) {
-#define CALL(NN)                                                                                            \
-    do {                                                                                                    \
-        if (m.deformed)                                                                                     \
-            launch_split<NN, true>(m, k_explicit_gc<NN, R>, k_explicit<NN, R, true, false>, st, q, fNS,       \
-                             fS, geom<R>(m), (const Tab<NN, R>*)tab_ptr<R>(m), ph, m.sponge);              \
-        else                                                                                                \
-            launch_split<NN, true>(m, k_explicit<NN, R, false, true>, k_explicit<NN, R, true, true>, st, q, fNS,  \
-                             fS, geom<R>(m), (const Tab<NN, R>*)tab_ptr<R>(m), ph, m.sponge);               \
+#define CALL(NN)                                                                                               \
+    do {                                                                                                       \
+        const Tab<NN, R>* tb = (const Tab<NN, R>*)tab_ptr<R>(m);                                                \
+        if (m.deformed && m.ncoarse)                                                                           \
+            launch_split<NN, true>(m, k_explicit_gc<NN, R, true>, k_explicit<NN, R, true, false>, st, q, fNS, fS, \
+                                   geom<R>(m), tb, ph, m.sponge);                                              \
+        else if (m.deformed)                                                                                   \
+            launch_split<NN, true>(m, k_explicit_gc<NN, R, false>, k_explicit<NN, R, true, false>, st, q, fNS, fS, \
+                                   geom<R>(m), tb, ph, m.sponge);                                              \
+        else if (m.ncoarse)                                                                                    \
+            launch_split<NN, true>(m, k_explicit<NN, R, false, true, true>, k_explicit<NN, R, true, true>, st, q, \
+                                   fNS, fS, geom<R>(m), tb, ph, m.sponge);                                     \
+        else                                                                                                   \
+            launch_split<NN, true>(m, k_explicit<NN, R, false, true, false>, k_explicit<NN, R, true, true>, st, q, \
+                                   fNS, fS, geom<R>(m), tb, ph, m.sponge);                                     \
     } while (0)
     IMX_DISPATCH_N(m.n, CALL)
 #undef CALL
