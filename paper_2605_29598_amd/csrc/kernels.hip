@@ -282,8 +282,8 @@ __device__ __forceinline__ float div_rn(float a, float b) { return __fdiv_rn(a, 
 // value get the same bits (both sides of a face then trace the same values).
 template <typename R>
 __device__ __forceinline__ void prim_of(const R* c, R* P, R gm1) {
-    const R r = c[0];
-    const R u0 = div_rn(c[1], r), u1 = div_rn(c[2], r), u2 = div_rn(c[3], r);
+    const R r = c[0], ir = div_rn((R)1, r);
+    const R u0 = mul_rn(c[1], ir), u1 = mul_rn(c[2], ir), u2 = mul_rn(c[3], ir);
     const R kin = mul_rn((R)0.5, add_rn(add_rn(mul_rn(u0, u0), mul_rn(u1, u1)), mul_rn(u2, u2)));
     P[0] = r;
     P[1] = u0;
