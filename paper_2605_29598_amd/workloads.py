@@ -155,7 +155,7 @@ def advected_bubble(nx=8, ny=4, nz=4, degree=3, scheme=R2, amp=10.0):
         pert="gauss", pert_amp=amp, pert_a=2e3, pert_xc=8e3, pert_yc=10e3, pert_zc=4e3, seed=11)
 
 
-def hill_benchmark(rotating=True, nx=30, ny=20, nz=8, degree=4, scheme=R2):
+def hill_benchmark(rotating=True, nx=30, ny=20, nz=8, degree=4, scheme=R2, nonconforming=False):
     """Benchmark flow over orography of Sec. 4.3: a 60 x 40 x 16 km Gal-Chen box
     over the bell mountain h0 / (1 + r^2/a^2) (h0 = 400 m, a = 1 km, centre
     (30, 20) km), periodic in x and y; stratified rest-frame background
@@ -164,11 +164,28 @@ def hill_benchmark(rotating=True, nx=30, ny=20, nz=8, degree=4, scheme=R2):
     and the top 6 km, lambda*dt = 1.2; 30 x 20 x 8 elements at r = 4
     (500 m effective resolution), dt = 8 s, 8 h; f = 1e-4 (rotating run) or 0.
     With periodic y the geostrophic pressure correction of the rotating run
-    cannot be represented and is left out, as for the orography box."""
-    dt = 8.0
+    cannot be represented and is left out, as for the orography box.
+
+    Non-conforming variant (the second pair of runs of the section): base
+    elements of 4 km (1 km effective resolution at r = 4: 15 x 10 x 4), one
+    level of refinement where x in [20, 40] km, y in [10, 30] km and z <= 7 km,
+    a second where z <= 2 km, down to 1 km elements (250 m effective). The
+    second box is drawn one level-1 element inside the first in x and y so that
+    the mesh is 2:1 balanced as built (the section's mesh library balances by
+    itself, which is not specified): 1,468 elements and 183,500 nodes per
+    field, against the section's 1,594 and 199,250. dt = 4 s: at 8 s the
+    advective Courant number on the 1 km elements (about 0.1) exceeds the
+    explicit tableau's limit."""
+    dt = 4.0 if nonconforming else 8.0
+    boxes = []
+    if nonconforming:
+        nx, ny, nz = 15, 10, 4
+        boxes = [(20e3, 40e3, 10e3, 30e3, 0.0, 7e3), (22e3, 38e3, 12e3, 28e3, 0.0, 2e3)]
     return Workload(
-        name="hill_benchmark%s_%dx%dx%d_r%d" % ("_rotating" if rotating else "", nx, ny, nz, degree),
-        mesh=MeshSpec(60e3, 40e3, 16e3, nx, ny, nz, degree, terrain=BELL, h0=400.0, a=1e3, xc=30e3, yc=20e3),
+        name="hill_benchmark%s%s_%dx%dx%d_r%d" % ("_nc" if nonconforming else "", "_rotating" if rotating else "",
+                                                  nx, ny, nz, degree),
+        mesh=MeshSpec(60e3, 40e3, 16e3, nx, ny, nz, degree, terrain=BELL, h0=400.0, a=1e3, xc=30e3, yc=20e3,
+                      ref_boxes=boxes),
         phys=PhysSpec(f=1e-4 if rotating else 0.0, sponge_zB=10e3, sponge_zT=16e3, sponge_lam=1.2 / dt,
                       sponge_u=(10.0, 0.0, 0.0), sponge_xw=20e3, sponge_yw=10e3),
         num=NumSpec(dt=dt, scheme=scheme),

@@ -50,6 +50,16 @@ def test_hill_runner_short_run(rotating):
     assert len(lines) == 4 and "summary" in lines[-1]
 
 
+def test_hill_nonconforming_runner_short_run():
+    """The non-conforming benchmark mesh (terrain-following, two levels of
+    hanging faces, lateral and top sponges) advances five steps with mass
+    conserved."""
+    buf = io.StringIO()
+    summary = X.run_hill(False, 5 * 4.0 / 3600.0, 5 * 4.0 / 3600.0, W.R2, out=buf, nonconforming=True)
+    assert summary["steps"] == 5
+    assert abs(summary["final"]["mass_rel"]) < 1e-13 and 0 < summary["final"]["max_abs_w"] < 10
+
+
 def test_hill_large_runner_short_run():
     """The larger-scale hill (isothermal background, 60 km lateral layers) on a
     reduced 10^3-element mesh advances five steps with mass conserved."""

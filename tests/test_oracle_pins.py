@@ -111,6 +111,26 @@ def test_hill_benchmark_dof_count():
     assert diagnostics.dofs_per_scalar(rec["cells"], w.mesh.degree) == rec["dofs"]
 
 
+def test_hill_nonconforming_mesh():
+    # the non-conforming benchmark mesh as read: 4 km base elements, two levels
+    # of 2:1 refinement around the mountain down to 1 km, balanced as built;
+    # the printed record has 1594 cells (its mesh library balances by itself),
+    # this reading 1468, both at r = 4 with the printed DoF-per-cell relation
+    w = W.hill_benchmark(rotating=False, nonconforming=True)
+    m = Mesh(MeshDesc(**vars(w.mesh)))
+    rec = json.load(open(GOLDEN))["dofs"][1]
+    assert w.mesh.degree == rec["r"] and diagnostics.dofs_per_scalar(rec["cells"], rec["r"]) == rec["dofs"]
+    assert m.E == 1468 and abs(m.E - rec["cells"]) < 0.1 * rec["cells"]
+    # base elements meeting the first box: 5 in x, 6 in y (y = 10 and 30 km lie
+    # inside 4 km elements), 2 layers (z <= 7 km reaches the 4-8 km layer):
+    # 600 - 60 stay; 480 - 64 first-level ones stay; 64 * 8 second-level ones,
+    # 1 km across
+    lv = np.bincount(np.asarray(m.elem_level), minlength=3)
+    assert list(lv) == [540, 416, 512], lv
+    assert w.mesh.Lx / w.mesh.nx / 2 ** 2 == 1e3
+    assert abs(w.phys.sponge_lam * w.num.dt - 1.2) < 1e-15 and w.num.dt == 4.0
+
+
 def test_hill_large_matches_printed_setup():
     # the larger-scale hill workload has the mesh, degree, dt, temperature and
     # wind of the printed Sec. 4.3 record (whose Courant numbers the test above
