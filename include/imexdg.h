@@ -202,7 +202,9 @@ imx_status imx_get_state(const imx_solver* s, double* q_dev);
 /* Explicit tendencies of Sec. 3 as nodal vectors f = M^{-1} T at state q:
  * fNS [5][E][Np] (advection with Rusanov fluxes, sponge) and fS [4][E][Np]
  * (momentum and energy: pressure with centred flux, enthalpy flux with
- * Rusanov dissipation on rho e, gravity, Coriolis). */
+ * Rusanov dissipation on rho e, gravity, Coriolis). Face values are the
+ * traces of the nodal (rho, u, p), the variables on whose traces the stage
+ * operators act, so fS at a converged stage is the stage's own operator. */
 imx_status imx_explicit_residual(imx_solver* s, const double* q_dev, double* fNS_dev, double* fS_dev);
 
 /* Fixes the stage coefficients of the implicit operators for the implicit
