@@ -191,6 +191,17 @@ imx_status imx_solver_set_numerics(imx_solver* s, const imx_numerics* num);
  * the device, not in the launch calls). */
 imx_status imx_solver_set_graphs(imx_solver* s, int enable);
 
+/* Rayleigh damping layers (Sec. 4.3, eq. damping): by default they relax the
+ * momentum towards rho * sponge_u (the mass stays exactly conserved). With a
+ * target state q_target_dev (device, [5][E][Np] conserved (rho, rho u, rho E),
+ * caller-owned, retained: it must stay valid and unchanged until the next call
+ * with another pointer or NULL) they relax the whole conserved state towards
+ * it instead; the density part then changes the mass inside the layers. The
+ * section states the damping profile and lambda * dt but not the variables it
+ * acts on; both readings are offered. NULL restores the default. Takes effect
+ * from the next explicit evaluation; IMX_EINVAL for a null solver. */
+imx_status imx_solver_set_sponge_target(imx_solver* s, const double* q_target_dev);
+
 /* Copies the conserved state y = (rho, rho u, rho E) of Sec. 2 as nodal values
  * [5][E][Np] (device, caller-owned, not retained) into / out of the solver's
  * resident copy y^n that imx_step advances (Sec. 3: y^n -> y^{n+1}).

@@ -37,7 +37,9 @@ class Phys:
     g: float = 9.81
     f: float = 0.0
     # Rayleigh sponge lambda(z) = lam * sin^2(pi/2 (z-zB)/(zT-zB)) for z >= zB,
-    # relaxing the momentum towards rho * u_bg; lam = 0 switches it off.
+    # relaxing the momentum towards rho * u_bg; lam = 0 switches it off. With
+    # sponge_target (conserved state (5, E, Np)) the whole state relaxes
+    # towards it instead.
     sponge_zB: float = 0.0
     sponge_zT: float = 1.0
     sponge_lam: float = 0.0
@@ -51,6 +53,7 @@ class Phys:
     # prognostic, on a mesh with one periodic element in y; every step ends
     # with the projection onto fields constant in y (slice_project)
     slice: int = 0
+    sponge_target: object = None
 
 
 @dataclass
@@ -245,8 +248,14 @@ def explicit_residual(mesh: Mesh, phys: Phys, q):
     TS[4] -= WJ * rho * phys.g * u[2]
     if phys.sponge_lam != 0.0:
         lam = sponge_coefficient(phys, mesh.xq, mesh.desc.Lx, mesh.desc.Ly)
-        for c in range(3):
-            TNS[1 + c] -= WJ * lam * (m[c] - rho * phys.sponge_u[c])
+        if phys.sponge_target is None:
+            for c in range(3):
+                TNS[1 + c] -= WJ * lam * (m[c] - rho * phys.sponge_u[c])
+        else:
+            # Rayleigh relaxation of the whole conserved state (rho, rho u,
+            # rho E) towards the target (the variables a damping layer acts on
+            # are not stated in Sec. 4.3; this is the second of two readings)
+            TNS -= WJ * lam * (q - phys.sponge_target)
 
     def flux(PA, PB, nS):
         # PA, PB: traces of (rho, u, p) on the two sides; slip walls mirror u

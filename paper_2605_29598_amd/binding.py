@@ -98,6 +98,7 @@ SIGNATURES = {
     "imx_total_mass_noalloc": (ctypes.c_int, [_vp, _vp, _vp]),
     "imx_geo_imbalance": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
     "imx_solver_set_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "imx_solver_set_sponge_target": (ctypes.c_int, [_vp, _vp]),
     "imx_solver_destroy": (None, [_vp]),
     "imx_solver_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
     "imx_solver_timing_report": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -299,6 +300,18 @@ class Solver:
 
     def set_graphs(self, enable):
         check(lib().imx_solver_set_graphs(self.h, int(bool(enable))), "imx_solver_set_graphs", solver=self.h)
+
+    def set_sponge_target(self, q):
+        """Damping layers relax the whole state towards q (None: momentum only)."""
+        if q is None:
+            self._starget = None
+            check(lib().imx_solver_set_sponge_target(self.h, None), "imx_solver_set_sponge_target", solver=self.h)
+            return
+        q = torch.as_tensor(q, dtype=torch.float64, device=self.device).contiguous()
+        if tuple(q.shape) != (5, self.E, self.Np):
+            raise ValueError(f"sponge target must have shape (5, {self.E}, {self.Np}), got {tuple(q.shape)}")
+        self._starget = q   # the library retains the pointer: keep the tensor alive
+        check(lib().imx_solver_set_sponge_target(self.h, _ptr(q)), "imx_solver_set_sponge_target", solver=self.h)
 
     def geo_imbalance(self):
         e = ctypes.c_double()

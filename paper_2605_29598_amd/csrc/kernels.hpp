@@ -51,6 +51,7 @@ struct PhysK {
     double gm1, igm1, hfac;   // gamma - 1, 1 / (gamma - 1), gamma / (gamma - 1)
     double su[3];
     int sponge;
+    const double* starget;   // [5][E][Np] state the layers relax towards (null: momentum towards rho su)
 };
 
 struct StageK {

@@ -126,6 +126,7 @@ static const Tableau TAB;
 using namespace imx;
 
 struct imx_solver {
+    const double* starget = nullptr;   // caller's state the damping layers relax towards (null: momentum only)
     const Mesh* mesh = nullptr;
     imx_phys phys{};
     imx_numerics num{};
@@ -763,6 +764,7 @@ static PhysK phys_k(const imx_solver* s) {
     k.hfac = s->phys.gamma / (s->phys.gamma - 1.0);
     for (int c = 0; c < 3; ++c) k.su[c] = s->phys.sponge_u[c];
     k.sponge = s->phys.sponge_lambda != 0.0;
+    k.starget = s->starget;
     return k;
 }
 
@@ -1347,6 +1349,13 @@ imx_status imx_geo_imbalance(imx_solver* s, double* egeo) {
     launch_final_sum(s->partial, nb, 2, bb, s->st);
     CHK(sync_read(s, bb, 2));
     *egeo = s->hsc[0] / s->hsc[1];
+    return IMX_OK;
+}
+
+imx_status imx_solver_set_sponge_target(imx_solver* s, const double* q_target_dev) {
+    imx::ErrScope es_(s ? &s->err : nullptr);
+    if (!s) return IMX_EINVAL;
+    s->starget = q_target_dev;
     return IMX_OK;
 }
 

@@ -85,7 +85,7 @@ def run(kind, hours, every_hours, scheme, precision, load=None, save=None, dt=No
 
 
 def run_hill(rotating, hours, every_hours, scheme=W.R2, out=sys.stdout, large=False, workload=None, dt=None,
-             lambda_dt=None, nonconforming=False):
+             lambda_dt=None, nonconforming=False, relax="momentum"):
     """The flows over the bell mountain of Sec. 4.3 (`hill_benchmark`, or
     `hill_large` with large=True; `workload` replaces either): one JSON line
     per interval with the relative mass change, max|w| and the ranges the
@@ -95,7 +95,9 @@ def run_hill(rotating, hours, every_hours, scheme=W.R2, out=sys.stdout, large=Fa
     end. With dt the time step is replaced and the damping coefficient
     rescaled so that lambda * dt keeps the workload's value (Sec. 4.3 states
     the layers by lambda * dt); lambda_dt replaces that value (1.2 in the
-    paper)."""
+    paper). relax = "momentum" damps the momentum towards rho (U, 0, 0), the
+    library's default; "state" relaxes the whole conserved state towards the
+    initial one (imx_solver_set_sponge_target)."""
     import torch
     from . import binding as B
     if workload is not None:
@@ -114,6 +116,10 @@ def run_hill(rotating, hours, every_hours, scheme=W.R2, out=sys.stdout, large=Fa
     xyz = mesh.node_coords()
     q0 = W.initial_state(w, xyz)
     sol.set_state(q0)
+    if relax == "state":
+        sol.set_sponge_target(q0)
+    elif relax != "momentum":
+        raise ValueError(relax)
     mass0 = float((mesh.mass_diag() * q0[0]).sum())
     x, y, z = xyz
     near800 = np.abs(z - 800.0) <= 200.0
@@ -296,6 +302,8 @@ def main(argv=None):
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--dt", type=float, default=None, help="time step in s instead of the workload's")
     ap.add_argument("--lambda-dt", type=float, default=None, help="hills: damping strength lambda * dt (paper: 1.2)")
+    ap.add_argument("--relax", choices=["momentum", "state"], default="momentum",
+                    help="hills: damping layers relax the momentum (default) or the whole state")
     ap.add_argument("--load", default=None)
     ap.add_argument("--save", default=None)
     a = ap.parse_args(argv)
@@ -311,7 +319,7 @@ def main(argv=None):
     if a.kind.startswith("hill"):
         run_hill(a.kind.endswith("_rotating"), hours, a.every_hours if a.every_hours is not None else 1.0,
                  W.R1 if a.scheme == "R1" else W.R2, large=a.kind.startswith("hill_large"), dt=a.dt,
-                 lambda_dt=a.lambda_dt, nonconforming=a.kind.startswith("hill_nc"))
+                 lambda_dt=a.lambda_dt, nonconforming=a.kind.startswith("hill_nc"), relax=a.relax)
         return
     every = a.every_hours if a.every_hours is not None else (1.0 if a.kind == "planetary" else 0.25)
     run(a.kind, hours, every, W.R1 if a.scheme == "R1" else W.R2, a.precision, a.load, a.save, a.dt)

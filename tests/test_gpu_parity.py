@@ -86,6 +86,37 @@ def test_explicit_residual_parity(name, lateral):
         assert relerr(fS[t], TS[t + 1] / Mw) < TOL, ("S", t, relerr(fS[t], TS[t + 1] / Mw))
 
 
+@pytest.mark.parametrize("name", ["walls_r3", "terrain_r3", "hanging_r2", "hanging_terrain_r4"])
+def test_explicit_residual_parity_sponge_target(name):
+    """Damping layers relaxing the whole state towards a target state
+    (imx_solver_set_sponge_target): every field's tendency against the oracle,
+    with layers strong enough that the relaxation is a sizeable part of it;
+    clearing the target restores the momentum-only form."""
+    spec = MESHES[name]
+    phys = W.PhysSpec(f=1.3e-3, sponge_zB=1e3, sponge_zT=4e3, sponge_lam=0.5, sponge_u=(3.0, -1.0, 0.0),
+                      sponge_xw=spec.Lx / 4, sponge_yw=spec.Ly / 3)
+    sol, om, oph, _ = _pair(spec, phys)
+    q = _state(om, 11)
+    target = q * (1.0 + 0.01 * np.random.default_rng(12).uniform(-1, 1, q.shape))
+    Mw = om.W3 * om.detJ
+    sol.set_sponge_target(target)
+    oph.sponge_target = target
+    TNS, TS = dg.explicit_residual(om, oph, q)
+    fNS, fS = (_cpu(a) for a in sol.explicit_residual(q))
+    for t in range(5):
+        assert relerr(fNS[t], TNS[t] / Mw) < TOL, ("NS", t, relerr(fNS[t], TNS[t] / Mw))
+    for t in range(4):
+        assert relerr(fS[t], TS[t + 1] / Mw) < TOL, ("S", t, relerr(fS[t], TS[t + 1] / Mw))
+    # the relaxation is visible in the density tendency, which has no other sponge part
+    oph.sponge_target = None
+    TNS0, _ = dg.explicit_residual(om, oph, q)
+    assert np.abs(TNS[0] - TNS0[0]).max() > 1e-3 * np.abs(TNS[0]).max()
+    sol.set_sponge_target(None)
+    fNS0 = _cpu(sol.explicit_residual(q)[0])
+    for t in range(5):
+        assert relerr(fNS0[t], TNS0[t] / Mw) < TOL, ("NS momentum-only", t)
+
+
 @pytest.mark.parametrize("name", list(MESHES))
 @pytest.mark.parametrize("scheme", [dg.R1, dg.R2])
 def test_schur_apply_parity(name, scheme):

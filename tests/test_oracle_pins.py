@@ -143,6 +143,26 @@ def test_hill_large_matches_printed_setup():
     assert abs(w.phys.sponge_lam * w.num.dt - 1.2) < 1e-15
 
 
+def test_sponge_target_reduces_to_momentum_relaxation():
+    # relaxing the whole state towards a target whose density and energy are
+    # the state's own and whose momentum is rho * u_bg is the momentum-only
+    # relaxation towards rho * u_bg; with the state itself as target the layers
+    # contribute nothing
+    mesh = Mesh(MeshDesc(4e3, 3e3, 3e3, 2, 2, 3, 2, terrain=2, h0=300.0, a=1.5e3, xc=2e3, yc=1.5e3))
+    q = W.random_positive_state((mesh.E, mesh.Np), 4)
+    su = (4.0, -2.0, 0.5)
+    base = dict(f=1e-4, g=9.81, sponge_zB=1e3, sponge_zT=3e3, sponge_lam=0.3, sponge_u=su, sponge_xw=1e3)
+    mom, _ = dg.explicit_residual(mesh, dg.Phys(**base), q)
+    tgt = q.copy()
+    tgt[1:4] = q[0] * np.asarray(su)[:, None, None]
+    full, _ = dg.explicit_residual(mesh, dg.Phys(**base, sponge_target=tgt), q)
+    assert np.abs(full - mom).max() <= 1e-13 * np.abs(mom).max()
+    off, _ = dg.explicit_residual(mesh, dg.Phys(**dict(base, sponge_lam=0.0)), q)
+    same, _ = dg.explicit_residual(mesh, dg.Phys(**base, sponge_target=q), q)
+    assert np.abs(same - off).max() <= 1e-13 * np.abs(off).max()
+    assert np.abs(mom - off).max() > 1e-3 * np.abs(off).max()   # the layers are not negligible here
+
+
 def test_sponge_profile():
     # eq. damping: lam sin^2(pi/2 t) with t the depth into a layer; the lateral
     # layers of Sec. 4.3 use the same profile; overlapping layers take the
