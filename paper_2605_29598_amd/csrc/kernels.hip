@@ -722,16 +722,7 @@ k_explicit(const int* __restrict__ elist, int64_t nel, const R* __restrict__ q, 
     acc[8] -= wj * rho * (R)ph.g * u[2];
     if (ph.sponge) {
         const R lam = (R)sponge[e * NP + node];
-        if (ph.starget) {
-            // the whole conserved state relaxes towards the target
-            const size_t oo = (size_t)e * NP + node;
-            const R Et = p * igm1 + rho * kin;
-            acc[0] -= wj * lam * (rho - (R)ph.starget[oo]);
-            for (int c = 0; c < 3; ++c) acc[1 + c] -= wj * lam * (mom[c] - (R)ph.starget[(1 + c) * fs + oo]);
-            acc[4] -= wj * lam * (Et - (R)ph.starget[4 * fs + oo]);
-        } else {
-            for (int c = 0; c < 3; ++c) acc[1 + c] -= wj * lam * (mom[c] - rho * (R)ph.su[c]);
-        }
+        for (int c = 0; c < 3; ++c) acc[1 + c] -= wj * lam * (mom[c] - rho * (R)ph.su[c]);
     }
     const R iwj = AFF ? T.iW3[node] * (R)g.eg[e * 8 + 7] : g.iWJ[e * NP + node];
     for (int t = 0; t < 5; ++t) fNS[t * fs + e * NP + node] = acc[t] * iwj;
@@ -935,18 +926,10 @@ k_explicit_gc(const int* __restrict__ elist, int64_t nel, const R* __restrict__ 
         acc[7] += z2;
     }
     const R fc = (R)ph.f, gg = (R)ph.g;
-    const R Et = p * igm1 + rho * kin;
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
         R v = acc[t] * iwj;
-        if (ph.sponge) {
-            if (ph.starget) {
-                const R Q = t == 0 ? rho : (t == 4 ? Et : mom[t - 1]);
-                v -= lam * (Q - (R)ph.starget[t * fs + o]);
-            } else if (t >= 1 && t <= 3) {
-                v -= lam * (mom[t - 1] - rho * (R)ph.su[t - 1]);
-            }
-        }
+        if (t >= 1 && t <= 3 && ph.sponge) v -= lam * (mom[t - 1] - rho * (R)ph.su[t - 1]);
         fNS[t * fs + o] = v;
     }
     fS[o] = acc[5] * iwj + rho * fc * u[1];

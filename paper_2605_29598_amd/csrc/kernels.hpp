@@ -51,7 +51,6 @@ struct PhysK {
     double gm1, igm1, hfac;   // gamma - 1, 1 / (gamma - 1), gamma / (gamma - 1)
     double su[3];
     int sponge;
-    const double* starget;   // [5][E][Np] state the layers relax towards (null: momentum towards rho su)
 };
 
 struct StageK {
@@ -136,6 +135,9 @@ void launch_finalize(int64_t L, const double* rho, const double* p, const double
 void launch_final_update(int64_t L, const double* y, const double* const* fNS, const double* const* fS,
                          const double* b, double dt, double* ynew, hipStream_t st);
 void launch_scale_div(int64_t L, int nf, const double* in, const double* WJ, double* out, hipStream_t st);
+// damping layers relaxing the whole state: fNS[t] -= lam (q[t] - target[t]), t = 0..4 ([5][L] fields)
+void launch_sponge_relax(int64_t L, const double* q, const double* target, const double* lam, double* fNS,
+                         hipStream_t st);
 
 // --- reductions: partial sums per block then a fixed-order final sum
 constexpr int RED_BLOCKS = 4096;

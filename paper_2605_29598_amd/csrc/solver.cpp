@@ -763,9 +763,17 @@ static PhysK phys_k(const imx_solver* s) {
     k.igm1 = 1.0 / (s->phys.gamma - 1.0);
     k.hfac = s->phys.gamma / (s->phys.gamma - 1.0);
     for (int c = 0; c < 3; ++c) k.su[c] = s->phys.sponge_u[c];
-    k.sponge = s->phys.sponge_lambda != 0.0;
-    k.starget = s->starget;
+    // with a target state the element kernels leave the layers out and the
+    // relaxation of the whole state follows them (explicit_eval)
+    k.sponge = s->phys.sponge_lambda != 0.0 && !s->starget;
     return k;
+}
+
+// T_NS and T_S of Sec. 3 at q as nodal tendencies; the damping layers relax
+// the momentum inside the element kernels, or the whole state afterwards
+static void explicit_eval(imx_solver* s, const PhysK& ph, const double* q, double* fN, double* fS) {
+    launch_explicit<double>(s->dm, s->tab, ph, q, fN, fS, s->st);
+    if (s->starget && s->dm.sponge) launch_sponge_relax(s->L, q, s->starget, s->dm.sponge, fN, s->st);
 }
 
 static imx_status one_step(imx_solver* s, imx_step_stats* acc) {
@@ -774,7 +782,7 @@ static imx_status one_step(imx_solver* s, imx_step_stats* acc) {
     const PhysK ph = phys_k(s);
     HIPCHK(hipMemcpyAsync(s->ybak, s->y, 5 * L * sizeof(double), hipMemcpyDeviceToDevice, s->st));
     timed(s, IMX_K_EXPLICIT, field_bytes(s, 14 + (ph.sponge ? 1 : 0), true),
-          [&] { launch_explicit<double>(s->dm, s->tab, ph, s->y, s->fN[0], s->fS[0], s->st); });
+          [&] { explicit_eval(s, ph, s->y, s->fN[0], s->fS[0]); });
     for (int l = 1; l <= 2; ++l) {
         StageCoef c{};
         for (int mm = 0; mm < l; ++mm) {
@@ -801,7 +809,7 @@ static imx_status one_step(imx_solver* s, imx_step_stats* acc) {
         timed(s, IMX_K_STAGE, 10 * (double)L * 8.0,
               [&] { launch_finalize(L, s->rho, s->p, s->u, s->phys.gamma, s->Y, s->st); });
         timed(s, IMX_K_EXPLICIT, field_bytes(s, 14 + (ph.sponge ? 1 : 0), true),
-              [&] { launch_explicit<double>(s->dm, s->tab, ph, s->Y, s->fN[l], s->fS[l], s->st); });
+              [&] { explicit_eval(s, ph, s->Y, s->fN[l], s->fS[l]); });
     }
     timed(s, IMX_K_STAGE, (5 + 27 + 5) * (double)L * 8.0,
           [&] { launch_final_update(L, s->y, s->fN, s->fS, TAB.b, dt, s->y, s->st); });
@@ -1235,7 +1243,7 @@ imx_status imx_explicit_residual(imx_solver* s, const double* q, double* fNS, do
     if (!q || !fNS || !fS) return IMX_EINVAL;
     const PhysK ph = phys_k(s);
     timed(s, IMX_K_EXPLICIT, field_bytes(s, 14 + (ph.sponge ? 1 : 0), true),
-          [&] { launch_explicit<double>(s->dm, s->tab, ph, q, fNS, fS, s->st); });
+          [&] { explicit_eval(s, ph, q, fNS, fS); });
     HIPCHK(hipGetLastError());
     return IMX_OK;
 }

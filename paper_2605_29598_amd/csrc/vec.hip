@@ -681,6 +681,23 @@ void launch_scale_div(int64_t L, int nf, const double* in, const double* WJ, dou
     hipLaunchKernelGGL(k_scale_div, dim3(grid_for(L)), dim3(TPB), 0, st, L, nf, in, WJ, out);
 }
 
+// Rayleigh relaxation of the whole conserved state towards a target, added
+// to the non-stiff tendencies M^{-1} T_NS (the layer coefficient per node)
+__global__ void k_sponge_relax(int64_t L, const double* __restrict__ q, const double* __restrict__ target,
+                               const double* __restrict__ lam, double* __restrict__ fNS) {
+    for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) {
+        const double l = lam[x];
+        if (l == 0.0) continue;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) fNS[t * L + x] -= l * (q[t * L + x] - target[t * L + x]);
+    }
+}
+
+void launch_sponge_relax(int64_t L, const double* q, const double* target, const double* lam, double* fNS,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_sponge_relax, dim3(grid_for(L)), dim3(TPB), 0, st, L, q, target, lam, fNS);
+}
+
 __global__ void k_stage_coef(int64_t L, const double* __restrict__ rho, const double* __restrict__ WJ,
                              double* __restrict__ cr, float* __restrict__ crf) {
     for (int64_t x = blockIdx.x * (int64_t)TPB + threadIdx.x; x < L; x += (int64_t)gridDim.x * TPB) {
