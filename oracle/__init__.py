@@ -22,8 +22,11 @@ Courant numbers printed in Sec. 4.
 
 The Rayleigh sponge term of Sec. 4.3 is pinned by hand values of its profile
 and by its closed form on a free stream; its place in the IMEX split (the
-non-stiff part) and its target state (rho u_target) are a reading, not stated
-in the paper.
+non-stiff part) and what it relaxes are readings, not stated in the paper:
+by default the momentum towards rho u_target, or, with Phys.sponge_target, the
+whole conserved state towards a given state (pinned against the first: with
+the state's own density and energy and momentum rho u_target as the target
+the two agree, and with the state itself as the target the layers vanish).
 
 Face values are formed from the traces of the nodal (rho, u, p), the
 variables in which Sec. 3 writes its averages and jumps and on whose traces
