@@ -62,7 +62,17 @@ struct Mesh {
     std::vector<double> G;                   // [9][E][Np] W detJ dxi_d/dx_c, deformed only
     std::vector<double> nS;                  // [E][6][3][Nf] W2 * outward area vector, deformed only
     std::vector<double> xyz;                 // [3][E][Np]
+    // terrain-following elements, compact form of the metric: J22 = dz/dxi_z at
+    // the Gauss points of the element's (x, y) plane, J20 and J21 there divided
+    // by phi = 1 - zeta / Lz, J22 on the x- and y-faces, and phi at the node
+    // levels and the two z-faces; per element cm_stride(n) values (deformed only)
+    std::vector<double> cm;
 };
+
+// entries per element of Mesh::cm: [NF] J22, [NF] J20 / phi, [NF] J21 / phi,
+// [2n] J22 on the x-faces (side s, y index a: s n + a), [2n] J22 on the
+// y-faces (side s, x index a), [n] phi at the node levels, [2] phi at z = 0, 1
+constexpr int cm_stride(int n) { return 3 * n * n + 5 * n + 2; }
 
 imx_status build_mesh(const imx_mesh_desc& d, Mesh& m);
 

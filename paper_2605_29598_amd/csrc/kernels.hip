@@ -141,6 +141,7 @@ struct Geom {
     const R* iWJ;         // 1 / WJ (deformed meshes)
     const uint64_t* fofs; // face-point words per (round, lane), see fo_node
     int gnx, gny, gnz, gpx, gpy;   // unrefined box meshes: base grid and periodicity
+    const R* cm;          // compact terrain metric [E][cm_stride(N)] or null
 };
 
 template <typename R>
@@ -148,12 +149,12 @@ static Geom<R> geom(const DevMesh& m);
 template <>
 Geom<double> geom<double>(const DevMesh& m) {
     return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJ, m.G, m.nS, m.eg, m.iWJ, m.fofs,
-            m.gnx, m.gny, m.gnz, m.gpx, m.gpy};
+            m.gnx, m.gny, m.gnz, m.gpx, m.gpy, m.cm};
 }
 template <>
 Geom<float> geom<float>(const DevMesh& m) {
     return {m.E, m.deformed, m.kind, m.nbr, m.aux, m.hang, m.h, m.hinv, m.WJf, m.Gf, m.nSf, m.eg, m.iWJf, m.fofs,
-            m.gnx, m.gny, m.gnz, m.gpx, m.gpy};
+            m.gnx, m.gny, m.gnz, m.gpx, m.gpy, m.cmf};
 }
 
 constexpr int epb_of(int N) { return N == 2 ? 16 : (N == 3 ? 9 : (N == 4 ? 4 : 2)); }
@@ -390,6 +391,55 @@ __device__ __forceinline__ R G_gc(const Geom<R>& g, size_t fsz, int dd, int c, s
     if (dd == 0) return c == 0 ? g.G[o] : (R)0;
     if (dd == 1) return c == 1 ? g.G[fsz + o] : (R)0;
     return g.G[(size_t)(2 + c) * fsz + o];
+}
+
+// The same entries from the compact metric (meshes without hanging faces):
+// J20 = (J20 / phi) phi, J21 likewise, J22 from the element's (x, y) plane,
+// J00 = h_x, J11 = h_y, multiplied in the host geometry's order; the weights
+// come from the global copy of the tables (read before the first barrier).
+template <int N, typename R>
+__device__ __forceinline__ void cm_node(const Geom<R>& g, const Tab<N, R>* __restrict__ Tg, int64_t e, int node,
+                                        R J00, R J11, R gv[5], R& iwj) {
+    constexpr int NF = N * N;
+    const R* c = g.cm + (size_t)e * cm_stride(N);
+    const int ij = node % NF, k = node / NF;
+    const R W = Tg->W3[node];
+    const R J22 = c[ij], ph = c[3 * NF + 4 * N + k];
+    const R J20 = c[NF + ij] * ph, J21 = c[2 * NF + ij] * ph;
+    gv[0] = W * (J11 * J22);
+    gv[1] = W * (J00 * J22);
+    gv[2] = W * (-(J11 * J20));
+    gv[3] = W * (-(J00 * J21));
+    gv[4] = W * (J00 * J11);
+    iwj = (R)1 / (W * (J00 * (J11 * J22)));
+}
+// W detJ at a node from the compact metric
+template <int N, typename R>
+__device__ __forceinline__ R cm_wj(const Geom<R>& g, const Tab<N, R>* __restrict__ Tg, int64_t e, int node) {
+    const R J22 = g.cm[(size_t)e * cm_stride(N) + node % (N * N)];
+    return Tg->W3[node] * ((R)g.h[3 * e] * ((R)g.h[3 * e + 1] * J22));
+}
+// n dS of face f at point pt (a + N b) from the compact metric: on x-faces
+// J11 J22, on y-faces J00 J22 (J22 at the face), on z-faces the third row of
+// cof(J) with phi at the face
+template <int N, typename R>
+__device__ __forceinline__ void cm_area(const Geom<R>& g, const Tab<N, R>* __restrict__ Tg, int64_t e, R J00, R J11,
+                                        int f, int pt, R nS[3]) {
+    constexpr int NF = N * N;
+    const R* c = g.cm + (size_t)e * cm_stride(N);
+    const int d = f >> 1, s = f & 1, a = pt % N;
+    const R w2 = Tg->W2[pt], W2 = s ? w2 : -w2;
+    nS[0] = nS[1] = nS[2] = 0;
+    if (d == 0) {
+        nS[0] = W2 * (J11 * c[3 * NF + s * N + a]);
+    } else if (d == 1) {
+        nS[1] = W2 * (J00 * c[3 * NF + 2 * N + s * N + a]);
+    } else {
+        const R ph = c[3 * NF + 5 * N + s];
+        nS[0] = W2 * (-(J11 * (c[NF + pt] * ph)));
+        nS[1] = W2 * (-(J00 * (c[2 * NF + pt] * ph)));
+        nS[2] = W2 * (J00 * J11);
+    }
 }
 
 // W2-weighted outward area vector of face f of element e at point pt
@@ -1634,7 +1684,7 @@ k_mv1(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
 // D_x^T(G00 p) + D_z^T(G20 p), D_y^T(G11 p) + D_z^T(G21 p) and D_z^T(G22 p),
 // five 1D contractions staged together, instead of nine in three rounds.
 // Four barriers in all.
-template <int N, typename R, int SCH>
+template <int N, typename R, int SCH, bool CM>
 __global__ void __launch_bounds__(threads_mv(N))
 k_mv1_gc(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
          const R* __restrict__ cr, const R* __restrict__ pk, const R* __restrict__ rho, R* __restrict__ w,
@@ -1664,10 +1714,17 @@ k_mv1_gc(const int* __restrict__ elist, int nel, const R* __restrict__ p, const 
         s_p[le][node] = pv;
         s_pk[le][node] = pk[o];
         crv = cr[o];
-        iwj = g.iWJ[o];
         if constexpr (SCH == 2) rl = rho[o];
+        R J00 = 0, J11 = 0;
+        if constexpr (CM) {
+            J00 = (R)g.h[3 * e];
+            J11 = (R)g.h[3 * e + 1];
+            cm_node<N, R>(g, Tg, e, node, J00, J11, gv, iwj);
+        } else {
+            iwj = g.iWJ[o];
 #pragma unroll
-        for (int t = 0; t < 5; ++t) gv[t] = g.G[t * fs + o];
+            for (int t = 0; t < 5; ++t) gv[t] = g.G[t * fs + o];
+        }
         lp.init(g.fofs, node);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -1677,7 +1734,8 @@ k_mv1_gc(const int* __restrict__ elist, int nel, const R* __restrict__ p, const 
             const int fc = has ? f : 5;
             kf[r] = has ? g.kind[e * 6 + fc] : WALL;
             nf[r] = g.nbr[e * 6 + fc];
-            nS_gc<N, R>(g, e, fc, lp.point(r), nsv[r]);
+            if constexpr (CM) cm_area<N, R>(g, Tg, e, J00, J11, fc, lp.point(r), nsv[r]);
+            else nS_gc<N, R>(g, e, fc, lp.point(r), nsv[r]);
             const bool ld = kf[r] == CONF;
             const R* src = p + (size_t)(unsigned)(ld ? nf[r] : 0) * NP;
 #pragma unroll
@@ -1812,7 +1870,7 @@ k_mv1_gc(const int* __restrict__ elist, int nel, const R* __restrict__ p, const 
 // off the path to the neighbour's face buffer (orography box: 166 -> 127 us;
 // the same change made Schur pass 1 slower, 400 -> 560 us, and is not used
 // there).
-template <int N, typename R, bool AFF, bool ST>
+template <int N, typename R, bool AFF, bool ST, bool CM>
 __global__ void __launch_bounds__(threads_mv(N))
 k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* __restrict__ pscale,
       const R* __restrict__ qw, const R* __restrict__ FB,
@@ -1837,7 +1895,10 @@ k_mv2(const int* __restrict__ elist, int nel, const R* __restrict__ p, const R* 
         eg.load(g.eg, e);
         qv = qw[o];
         pv = (pscale ? pscale[0] : (R)1) * p[o];
-        if constexpr (!AFF) {
+        if constexpr (CM) {
+            wjd = cm_wj<N, R>(g, Tg, e, node);
+            iwj = (R)1 / wjd;
+        } else if constexpr (!AFF) {
             iwj = g.iWJ[o];
             if (dual) wjd = g.WJ[o];
         }
@@ -2320,7 +2381,7 @@ template void launch_pass2<float>(const DevMesh&, const HostTab&, const StageK&,
                                   const float*, float*, double, int, hipStream_t, const float*, int, double*,
                                   double*);
 
-template <typename R, int N, bool AFF, int SCH>
+template <typename R, int N, bool AFF, int SCH, bool CM>
 static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, const R* cr, const R* rho,
                  const R* pk, R* w, R* FB, R* FBh, R* out, int dual, hipStream_t st, const int* ctrl) {
     constexpr int EPB = epb_of(N), EPBM = epb_mv(N);
@@ -2337,7 +2398,7 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
                         hipLaunchKernelGGL((k_mv1<N, R, AFF, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s,
                                            fl, (int)nf, x, xs, cr, pk, rho, w, FB, geom<R>(m), T, sk, ctrl);
                     else
-                        hipLaunchKernelGGL((k_mv1_gc<N, R, SCH>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
+                        hipLaunchKernelGGL((k_mv1_gc<N, R, SCH, CM>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s, fl,
                                            (int)nf, x, xs, cr, pk, rho, w, FB, geom<R>(m), T, sk, ctrl);
                 }
             },
@@ -2354,11 +2415,11 @@ static void mv_n(const DevMesh& m, const StageK& sk, const R* x, const R* xs, co
             [&](hipStream_t s) {
                 if (bf > 0) {
                     if (m.structured)
-                        hipLaunchKernelGGL((k_mv2<N, R, AFF, true>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s,
+                        hipLaunchKernelGGL((k_mv2<N, R, AFF, true, CM>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s,
                                            fl, (int)nf, x, xs, (const R*)w, (const R*)FB, (const R*)FBh, out, dual,
                                            geom<R>(m), T, sk, ctrl);
                     else
-                        hipLaunchKernelGGL((k_mv2<N, R, AFF, false>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s,
+                        hipLaunchKernelGGL((k_mv2<N, R, AFF, false, CM>), dim3((unsigned)bf), dim3(threads_mv(N)), 0, s,
                                            fl, (int)nf, x, xs, (const R*)w, (const R*)FB, (const R*)FBh, out, dual,
                                            geom<R>(m), T, sk, ctrl);
                 }
@@ -2391,14 +2452,19 @@ static void mv_dispatch(const DevMesh& m, const StageK& sk, const R* x, const R*
         mv2w<R>(m, sk, x, xs, w, FB, out, dual, st, ctrl);
         return;
     }
+    // terrain-following meshes without hanging faces form their metric from the compact form
+    const bool cm = geom<R>(m).cm != nullptr;
 #define MV(NN)                                                                                            \
     do {                                                                                                  \
         if (!m.deformed) {                                                                                \
-            if (sk.scheme == 2) mv_n<R, NN, true, 2>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);  \
-            else mv_n<R, NN, true, 1>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);                 \
+            if (sk.scheme == 2) mv_n<R, NN, true, 2, false>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl); \
+            else mv_n<R, NN, true, 1, false>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);       \
+        } else if (cm) {                                                                                  \
+            if (sk.scheme == 2) mv_n<R, NN, false, 2, true>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl); \
+            else mv_n<R, NN, false, 1, true>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);       \
         } else {                                                                                          \
-            if (sk.scheme == 2) mv_n<R, NN, false, 2>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl); \
-            else mv_n<R, NN, false, 1>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);                \
+            if (sk.scheme == 2) mv_n<R, NN, false, 2, false>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl); \
+            else mv_n<R, NN, false, 1, false>(m, sk, x, xs, cr, rho, pk, w, FB, FBh, out, dual, st, ctrl);      \
         }                                                                                                 \
     } while (0)
     IMX_DISPATCH_N(m.n, MV)

@@ -30,6 +30,11 @@ struct DevMesh {
     const double* eg = nullptr;     // [E*8] affine elements: h[3], 1/h[3], det J, 1/det J
     const double* iWJ = nullptr;    // [E*Np] 1 / WJ (deformed meshes)
     const float* iWJf = nullptr;
+    // terrain-following meshes without hanging faces: the compact metric
+    // ([E][cm_stride(n)], Mesh::cm) from which the Krylov passes form W cof(J),
+    // 1 / W detJ and n dS instead of reading them
+    const double* cm = nullptr;
+    const float* cmf = nullptr;
     const uint64_t* fofs = nullptr; // [fofs_count(n)] face-point words of the all-faces kernels
     // unrefined box meshes: element e = bz + nz (bx + nx by), so neighbours and
     // face kinds follow from the index (structured != 0 once the host has
@@ -147,12 +152,17 @@ constexpr int MAXV = 33;   // restart length <= 32
 // Source of the weights W detJ of the Krylov inner products: the stored
 // array WJ, or on affine meshes the tensor weight of the node times the
 // element's det J (per-element constants, 8 per element, det J at index 6),
-// which saves one vector read per launch. Entries at and beyond nreal (the
+// which saves one vector read per launch; on terrain-following meshes with
+// the compact metric, the tensor weight times h_x (h_y J22). Entries at and beyond nreal (the
 // padding of the basis) weigh 0.
 struct WSrc {
     const double* W3 = nullptr;   // null: read the stored array
     const double* eg = nullptr;
     int E = 0, np = 0;
+    // terrain-following meshes with the compact metric: det J = h_x (h_y J22),
+    // J22 from the element's (x, y) plane (entry n % nf of its K values)
+    const double* cm = nullptr;
+    int nf = 0, K = 0;
 };
 // out[i] = sum WJ * V_i * z  (i < nv), V_i = V + i*ldv, all length L (R = double or float)
 template <typename R>

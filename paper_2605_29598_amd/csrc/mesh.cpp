@@ -1,6 +1,7 @@
 // Host-side mesh construction: leaves of the nested 2:1 refinement, face
 // connectivity (conforming, periodic, wall, hanging) and the isoparametric
 // geometry of every element at its Gauss-Legendre points.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -113,6 +114,105 @@ static double surface(const imx_mesh_desc& d, double x, double y) {
 }
 
 static const int TANG[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+
+// Compact metric of terrain-following element e (layout at cm_stride). The
+// Gal-Chen map interpolated on the base cell is z = S (1 - zeta / Lz) + zeta,
+// with S the surface interpolated on the cell's Gauss-Lobatto points and zeta
+// the undeformed height, linear in the reference coordinate (the interpolant of
+// a linear function is that function). So dz/dxi_x = sc S_x phi and
+// dz/dxi_y = sc S_y phi with phi = 1 - zeta / Lz, and dz/dxi_z = sc h0z (1 - S / Lz)
+// does not depend on zeta. Every entry of W cof(J), W det J and n dS is a
+// product of these and the affine h_x, h_y; the result is checked against the
+// mapped geometry of the element at 1e-12 of its largest entry (false: it
+// does not reproduce it).
+static bool compact_metric(Mesh& m, int64_t e, const std::vector<double>& hsv, const double h0[3]) {
+    const int n = m.n, Nf = m.Nf, Np = m.Np, K = cm_stride(n);
+    const int64_t E = m.E;
+    const Basis1D& B = m.basis;
+    const imx_mesh_desc& d = m.desc;
+    const double sc = std::ldexp(1.0, -m.level[e]);
+    const int* b = &m.base[3 * e];
+    const int* sb = &m.sub[3 * e];
+    double* cme = &m.cm[(size_t)e * K];
+    auto surf = [&](double ex, double ey, double& S, double& Sx, double& Sy) {
+        double lx[8], dx[8], ly[8], dy[8];
+        lagrange(B.gll, ex, lx, dx);
+        lagrange(B.gll, ey, ly, dy);
+        S = Sx = Sy = 0.0;
+        for (int a = 0; a < n; ++a)
+            for (int bb = 0; bb < n; ++bb) {
+                const double v = hsv[a * n + bb];
+                S += lx[a] * ly[bb] * v;
+                Sx += dx[a] * ly[bb] * v;
+                Sy += lx[a] * dy[bb] * v;
+            }
+    };
+    auto j22 = [&](double S) { return h0[2] * (1.0 - S / d.Lz) * sc; };
+    auto phi = [&](double xi) { return 1.0 - (b[2] + (sb[2] + xi) * sc) * h0[2] / d.Lz; };
+    double S, Sx, Sy;
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            surf((sb[0] + B.x[i]) * sc, (sb[1] + B.x[j]) * sc, S, Sx, Sy);
+            cme[i + n * j] = j22(S);
+            cme[Nf + i + n * j] = Sx * sc;
+            cme[2 * Nf + i + n * j] = Sy * sc;
+        }
+    for (int s = 0; s < 2; ++s)
+        for (int a = 0; a < n; ++a) {
+            surf((sb[0] + s) * sc, (sb[1] + B.x[a]) * sc, S, Sx, Sy);
+            cme[3 * Nf + s * n + a] = j22(S);
+            surf((sb[0] + B.x[a]) * sc, (sb[1] + s) * sc, S, Sx, Sy);
+            cme[3 * Nf + 2 * n + s * n + a] = j22(S);
+        }
+    for (int k = 0; k < n; ++k) cme[3 * Nf + 4 * n + k] = phi(B.x[k]);
+    cme[3 * Nf + 5 * n] = phi(0.0);
+    cme[3 * Nf + 5 * n + 1] = phi(1.0);
+    // the entries the kernels form from it, against the mapped geometry
+    const double J00 = m.h[3 * e], J11 = m.h[3 * e + 1];
+    const int keep[5][2] = {{0, 0}, {1, 1}, {2, 0}, {2, 1}, {2, 2}};
+    double gmax = 0, gdev = 0, wdev = 0, nmax = 0, ndev = 0;
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                const int node = i + n * (j + n * k), ij = i + n * j;
+                const double W = B.w[i] * B.w[j] * B.w[k];
+                const double J22 = cme[ij], ph = cme[3 * Nf + 4 * n + k];
+                const double J20 = cme[Nf + ij] * ph, J21 = cme[2 * Nf + ij] * ph;
+                const double g5[5] = {W * (J11 * J22), W * (J00 * J22), W * (-(J11 * J20)), W * (-(J00 * J21)),
+                                      W * (J00 * J11)};
+                for (int t = 0; t < 5; ++t) {
+                    const double ref = m.G[((size_t)(keep[t][0] * 3 + keep[t][1]) * E + e) * Np + node];
+                    gmax = std::max(gmax, std::fabs(ref));
+                    gdev = std::max(gdev, std::fabs(g5[t] - ref));
+                }
+                const double wj = W * (J00 * (J11 * J22)), wref = m.WJ[e * Np + node];
+                wdev = std::max(wdev, std::fabs(wj - wref) / wref);
+            }
+    for (int dd = 0; dd < 3; ++dd)
+        for (int side = 0; side < 2; ++side)
+            for (int bq = 0; bq < n; ++bq)
+                for (int aq = 0; aq < n; ++aq) {
+                    const int f = 2 * dd + side, pt = aq + n * bq;
+                    const double W2 = B.w[aq] * B.w[bq] * (side ? 1.0 : -1.0);
+                    double v[3] = {0, 0, 0};
+                    if (dd == 0) {
+                        v[0] = W2 * (J11 * cme[3 * Nf + side * n + aq]);
+                    } else if (dd == 1) {
+                        v[1] = W2 * (J00 * cme[3 * Nf + 2 * n + side * n + aq]);
+                    } else {
+                        const double ph = cme[3 * Nf + 5 * n + side];
+                        v[0] = W2 * (-(J11 * (cme[Nf + pt] * ph)));
+                        v[1] = W2 * (-(J00 * (cme[2 * Nf + pt] * ph)));
+                        v[2] = W2 * (J00 * J11);
+                    }
+                    for (int c = 0; c < 3; ++c) {
+                        const double ref = m.nS[((e * 6 + f) * 3 + c) * Nf + pt];
+                        nmax = std::max(nmax, std::fabs(ref));
+                        ndev = std::max(ndev, std::fabs(v[c] - ref));
+                    }
+                }
+    return gdev <= 1e-12 * gmax && ndev <= 1e-12 * nmax && wdev <= 1e-12;
+}
 
 imx_status build_mesh(const imx_mesh_desc& d, Mesh& m) {
     if (d.nx < 1 || d.ny < 1 || d.nz < 1 || d.degree < 1 || d.degree > 4 || !(d.Lx > 0) ||
@@ -264,9 +364,10 @@ imx_status build_mesh(const imx_mesh_desc& d, Mesh& m) {
     if (m.deformed) {
         m.G.assign(9 * E * Np, 0.0);
         m.nS.assign(E * 6 * 3 * Nf, 0.0);
+        m.cm.assign((size_t)E * cm_stride(n), 0.0);
     }
-    bool inverted = false;
-#pragma omp parallel for schedule(static) reduction(|| : inverted)
+    bool inverted = false, cm_bad = false;
+#pragma omp parallel for schedule(static) reduction(|| : inverted, cm_bad)
     for (int64_t e = 0; e < E; ++e) {
         const int L = m.level[e];
         const double sc = std::ldexp(1.0, -L);
@@ -274,13 +375,15 @@ imx_status build_mesh(const imx_mesh_desc& d, Mesh& m) {
         const int* sb = &m.sub[3 * e];
         for (int c = 0; c < 3; ++c) m.h[3 * e + c] = h0[c] * sc;
         // Gal-Chen heights at the Gauss-Lobatto points of the base cell
-        std::vector<double> zg;
+        std::vector<double> zg, hsv;
         if (m.deformed) {
             zg.assign(n * n * n, 0.0);
+            hsv.assign(n * n, 0.0);
             for (int a = 0; a < n; ++a)
                 for (int bb = 0; bb < n; ++bb) {
                     double xa = (b[0] + B.gll[a]) * h0[0], yb = (b[1] + B.gll[bb]) * h0[1];
                     double hs = surface(d, xa, yb);
+                    hsv[a * n + bb] = hs;
                     for (int c = 0; c < n; ++c) {
                         double zeta = (b[2] + B.gll[c]) * h0[2];
                         zg[(a * n + bb) * n + c] = hs + zeta * (d.Lz - hs) / d.Lz;
@@ -370,9 +473,14 @@ imx_status build_mesh(const imx_mesh_desc& d, Mesh& m) {
                             for (int c = 0; c < 3; ++c)
                                 m.nS[((e * 6 + f) * 3 + c) * Nf + pt] = W2 * C[dd][c];
                         }
+        if (m.deformed && !compact_metric(m, e, hsv, h0)) cm_bad = true;
     }
     if (inverted) {
         set_error("imx_mesh_create: inverted element (non-positive Jacobian)");
+        return IMX_EINVAL;
+    }
+    if (cm_bad) {
+        set_error("imx_mesh_create: the compact terrain metric does not reproduce the mapped geometry");
         return IMX_EINVAL;
     }
     return IMX_OK;

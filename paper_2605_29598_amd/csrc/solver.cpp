@@ -227,6 +227,7 @@ static size_t layout(imx_solver* s, char* base) {
         dm.G = D(5 * L);
         dm.nS = D((size_t)E * 10 * Nf);
         dm.iWJ = D(L);
+        if (m.nh == 0) dm.cm = D((size_t)E * cm_stride(m.n));
     }
     s->cr = D(L);
     if (s->phys.sponge_lambda != 0.0) dm.sponge = D(L);
@@ -278,6 +279,7 @@ static size_t layout(imx_solver* s, char* base) {
             dm.Gf = s->Gf;
             dm.nSf = s->nSf;
             dm.iWJf = F(L);
+            if (m.nh == 0) dm.cmf = F((size_t)E * cm_stride(m.n));
         }
     }
     return Lo.off;
@@ -381,14 +383,22 @@ static double field_bytes(const imx_solver* s, double nfields, bool geometry) {
 
 // algorithmic bytes of the matrix-vector product's two passes. Pass 1 reads
 // x, rho_l (as cr) and p^k (and rho_l itself for R2 on terrain-following
-// meshes) and the stored geometry, and writes the element's own part of
-// pass 2 (1 field: volume divergence of (rho h)^k w and the R2 gravity term);
-// pass 2 reads x and that field (and W detJ^{-1} on terrain-following meshes)
-// and writes S x. The face buffers are not counted.
+// meshes) and the geometry, and writes the element's own part of pass 2
+// (1 field: volume divergence of (rho h)^k w and the R2 gravity term); pass 2
+// reads x and that field (and W detJ^{-1} on terrain-following meshes) and
+// writes S x. The face buffers are not counted. Where the mesh has the
+// compact terrain metric, pass 1 reads it (cm_stride(n) values and h_x, h_y per
+// element) in place of the stored geometry, and pass 2 forms W detJ^{-1} from
+// its J22 values (Nf and h_x, h_y per element).
 static double mv1_bytes(const imx_solver* s, int scheme) {
-    return field_bytes(s, 4.0 + (s->mesh->deformed && scheme == 2 ? 1.0 : 0.0), true);
+    const double nf = 4.0 + (s->mesh->deformed && scheme == 2 ? 1.0 : 0.0);
+    if (s->dm.cm) return nf * (double)s->L * 8.0 + (double)s->E * (cm_stride(s->mesh->n) + 2.0) * 8.0;
+    return field_bytes(s, nf, true);
 }
-static double mv2_bytes(const imx_solver* s) { return field_bytes(s, 3.0 + (s->mesh->deformed ? 1.0 : 0.0), false); }
+static double mv2_bytes(const imx_solver* s) {
+    if (s->dm.cm) return 3.0 * (double)s->L * 8.0 + (double)s->E * (s->Nf + 2.0) * 8.0;
+    return field_bytes(s, 3.0 + (s->mesh->deformed ? 1.0 : 0.0), false);
+}
 
 // ------------------------------------------------------------ stage context
 struct StageCtx {
@@ -503,7 +513,9 @@ static imx_status arnoldi_cycle(imx_solver* s, R* V, const R* WJ, int m, double 
         R* Vn = V + (size_t)(j + 1) * L;
         double* raw = raw2p ? raw2 : raw1;
         const int nd = raw2p ? j + 1 : j + 2;   // the second pass needs no |z|^2
-        const double wb = s->wsrc.W3 ? 0.0 : vb;   // the weight vector, unless taken from the tables
+        // the weight vector, unless taken from the tables (with the compact
+        // metric, binary64 only: the J22 plane of each element)
+        const double wb = s->wsrc.cm ? (sizeof(R) == 8 ? (double)s->E * s->Nf * 8.0 : vb) : (s->wsrc.W3 ? 0.0 : vb);
         timed(s, IMX_K_DOTS, nd * vb + wb,
               [&] { launch_dots<R>(L, nd, V, L, Vn, WJ, s->partial, raw, s->st, c, s->wsrc); });
         timed(s, IMX_K_ORTHO, (j + 3) * vb + wb, [&] {
@@ -1098,11 +1110,14 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
                 for (int i = 0; i < n; ++i) w3[i + n * (j + n * k)] = s->tab.w[i] * s->tab.w[j] * s->tab.w[k];
         CHK(up(s->w3, w3.data(), w3.size() * sizeof(double)));
         s->wsrc = WSrc();
-        if (!m.deformed) {
+        if (!m.deformed || s->dm.cm) {
             s->wsrc.W3 = s->w3;
             s->wsrc.eg = s->dm.eg;
             s->wsrc.E = (int)s->E;
             s->wsrc.np = s->Np;
+            s->wsrc.cm = s->dm.cm;
+            s->wsrc.nf = s->Nf;
+            s->wsrc.K = cm_stride(m.n);
         }
     }
     std::vector<char> tabimg(tab_bytes(m.n, 0)), tabimgf(tab_bytes(m.n, 1));
@@ -1154,6 +1169,7 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
         iwj.resize(s->L);
         for (int64_t i = 0; i < s->L; ++i) iwj[i] = 1.0 / m.WJ[i];
         CHK(up(s->dm.iWJ, iwj.data(), iwj.size() * sizeof(double)));
+        if (s->dm.cm) CHK(up(s->dm.cm, m.cm.data(), m.cm.size() * sizeof(double)));
     }
     std::vector<double> spl;
     if (s->dm.sponge) {
@@ -1192,6 +1208,10 @@ imx_status imx_solver_bind_workspace(imx_solver* s, void* dev, size_t bytes) {
             CHK(up(s->nSf, tmp.data(), tmp.size() * sizeof(float)));
             std::vector<float> iwf(iwj.begin(), iwj.end());
             CHK(up(s->dm.iWJf, iwf.data(), iwf.size() * sizeof(float)));
+            if (s->dm.cmf) {
+                tmp.assign(m.cm.begin(), m.cm.end());
+                CHK(up(s->dm.cmf, tmp.data(), tmp.size() * sizeof(float)));
+            }
         }
     }
     HIPCHK(hipMemsetAsync(s->dsc, 0, imx_solver::S_N * sizeof(double), s->st));

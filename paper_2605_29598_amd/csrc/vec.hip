@@ -128,7 +128,8 @@ static unsigned stream_grid(int64_t L) {
     return (unsigned)g;
 }
 
-// W detJ from the tables (affine meshes) for the entries a lane visits: the
+// W detJ from the tables (affine meshes, or terrain-following ones with the
+// compact metric) for the entries a lane visits: the
 // element e and node n of its first entry are advanced by the grid stride
 // (de elements and dn nodes) instead of dividing every index by Np. The
 // binary32 weights are the rounded binary64 products, as in the stored array.
@@ -150,8 +151,9 @@ struct TabWalk {
     }
 };
 
-// the W lanes' weights of 16-byte lane x (TABW: from the tables)
-template <typename R, typename VT, int W, bool TABW>
+// the W lanes' weights of 16-byte lane x (TABW 0: the stored array; 1: from
+// the tables, affine; 2: from the tables and the compact terrain metric)
+template <typename R, typename VT, int W, int TABW>
 __device__ __forceinline__ void lane_weights(const R* WJ, const WSrc& ws, const TabWalk& tw, int64_t x, double* wv) {
     if constexpr (TABW) {
 #pragma unroll
@@ -162,7 +164,11 @@ __device__ __forceinline__ void lane_weights(const R* WJ, const WSrc& ws, const 
                 ++e;
             }
             const int ec = e < ws.E ? e : ws.E - 1;   // padding entries: load in bounds, weigh 0
-            const double v = (double)(R)(ws.W3[n] * ws.eg[8 * (int64_t)ec + 6]);
+            const double* q = ws.eg + 8 * (int64_t)ec;
+            double dj;
+            if constexpr (TABW == 2) dj = q[0] * (q[1] * ws.cm[(int64_t)ec * ws.K + n % ws.nf]);
+            else dj = q[6];
+            const double v = (double)(R)(ws.W3[n] * dj);
             wv[k] = e < ws.E ? v : 0.0;
         }
     } else {
@@ -189,7 +195,7 @@ __device__ __forceinline__ uint32_t lane_offset(uint32_t off) {
 // occupancy): every chunk walks the same entries at the same time, so z and the
 // weights come from HBM once and from the compute unit's caches for the other
 // chunks.
-template <typename R, int NG, int CH, bool TABW>
+template <typename R, int NG, int CH, int TABW>
 __global__ void __launch_bounds__(TPB)
 k_dots(int64_t L, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z, const R* __restrict__ WJ,
        double* __restrict__ partial, int nvtot, const int* __restrict__ ctrl, WSrc ws) {
@@ -261,7 +267,7 @@ k_dots(int64_t L, const R* __restrict__ V, int64_t ldv, const R* __restrict__ z,
 // one running sum per vector of a chunk: the chunk length (nv / NG rounded up)
 // is the template's CH, so that no load repeats an address except in the
 // last chunk
-template <typename R, bool TABW>
+template <typename R, int TABW>
 static void dots_launch(unsigned g, int nv, int64_t L, const R* V, int64_t ldv, const R* z, const R* WJ,
                         double* partial, hipStream_t st, const int* ctrl, const WSrc& ws) {
 #define IMX_DOTS(NG, CH) \
@@ -300,10 +306,15 @@ void launch_dots(int64_t L, int nv, const R* V, int64_t ldv, const R* z, const R
     // compute unit) for every vector count; 256, 384, 1024 and 2048 were slower
     const unsigned gmax = 512;
     const unsigned g = stream_grid(L) > gmax ? gmax : stream_grid(L);
-    if (ws.W3)
-        dots_launch<R, true>(g, nv, L, V, ldv, z, WJ, partial, st, ctrl, ws);
+    // binary32 vectors read their stored weights on terrain-following meshes:
+    // for them the 4-byte weight costs less than forming it from the metric
+    constexpr int TCM = sizeof(R) == 8 ? 2 : 0;
+    if (ws.cm)
+        dots_launch<R, TCM>(g, nv, L, V, ldv, z, WJ, partial, st, ctrl, ws);
+    else if (ws.W3)
+        dots_launch<R, 1>(g, nv, L, V, ldv, z, WJ, partial, st, ctrl, ws);
     else
-        dots_launch<R, false>(g, nv, L, V, ldv, z, WJ, partial, st, ctrl, ws);
+        dots_launch<R, 0>(g, nv, L, V, ldv, z, WJ, partial, st, ctrl, ws);
     hipLaunchKernelGGL(k_final_sum_t, dim3(nv), dim3(TPB), 0, st, partial, (int)g, out, ctrl);
 }
 template void launch_dots<double>(int64_t, int, const double*, int64_t, const double*, const double*, double*,
@@ -314,7 +325,7 @@ template void launch_dots<float>(int64_t, int, const float*, int64_t, const floa
 // --------------------------------------------------- Gram-Schmidt update
 // z1 = z - sum_i raw[i] s[i]^2 V_i and its squared M-norm (no basis vector
 // kept live: one running value per lane)
-template <typename R, int CH, bool TABW>
+template <typename R, int CH, int TABW>
 __global__ void __launch_bounds__(TPB)
 k_axpy_norm(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const double* __restrict__ raw,
             const double* __restrict__ s, const R* z, R* z1, const R* __restrict__ WJ, double* __restrict__ partial,
@@ -362,7 +373,7 @@ k_axpy_norm(int64_t L, int nv, const R* __restrict__ V, int64_t ldv, const doubl
 
 int axpy_norm_blocks(int64_t L) { return (int)stream_grid(L); }
 
-template <typename R, bool TABW>
+template <typename R, int TABW>
 static void axpy_norm_launch(unsigned g, int64_t L, int nv, const R* V, int64_t ldv, const double* raw,
                              const double* s, const R* z, R* z1, const R* WJ, double* partial, hipStream_t st,
                              const int* ctrl, const WSrc& ws) {
@@ -381,10 +392,13 @@ template <typename R>
 void launch_axpy_norm(int64_t L, int nv, const R* V, int64_t ldv, const double* raw, const double* s, const R* z,
                       R* z1, const R* WJ, double* partial, hipStream_t st, const int* ctrl, WSrc ws) {
     const unsigned g = stream_grid(L);
-    if (ws.W3)
-        axpy_norm_launch<R, true>(g, L, nv, V, ldv, raw, s, z, z1, WJ, partial, st, ctrl, ws);
+    constexpr int TCM = sizeof(R) == 8 ? 2 : 0;   // binary32: the stored weights, as for the dots
+    if (ws.cm)
+        axpy_norm_launch<R, TCM>(g, L, nv, V, ldv, raw, s, z, z1, WJ, partial, st, ctrl, ws);
+    else if (ws.W3)
+        axpy_norm_launch<R, 1>(g, L, nv, V, ldv, raw, s, z, z1, WJ, partial, st, ctrl, ws);
     else
-        axpy_norm_launch<R, false>(g, L, nv, V, ldv, raw, s, z, z1, WJ, partial, st, ctrl, ws);
+        axpy_norm_launch<R, 0>(g, L, nv, V, ldv, raw, s, z, z1, WJ, partial, st, ctrl, ws);
 }
 template void launch_axpy_norm<double>(int64_t, int, const double*, int64_t, const double*, const double*,
                                        const double*, double*, const double*, double*, hipStream_t, const int*, WSrc);

@@ -55,6 +55,11 @@ MESHES = {
     "r1_periodic": W.MeshSpec(4e3, 3e3, 2e3, 4, 3, 2, 1),
     "r4_ragged": W.MeshSpec(5e3, 3e3, 2e3, 3, 1, 3, 4),       # E = 9, not a multiple of the 2 elements/block
     "terrain_r3": W.MeshSpec(8e3, 8e3, 4e3, 3, 3, 2, 3, terrain=W.GAUSS, h0=400, a=2e3, xc=4e3, yc=4e3),
+    # conforming terrain-following meshes at other degrees: the Krylov passes
+    # form their metric from the compact form (E = 18 and 15, ragged blocks)
+    "terrain_r2": W.MeshSpec(8e3, 8e3, 4e3, 3, 3, 2, 2, terrain=W.BELL, h0=500, a=1.5e3, xc=3e3, yc=5e3),
+    "terrain_r4": W.MeshSpec(10e3, 6e3, 4e3, 5, 3, 1, 4, terrain=W.GAUSS, h0=600, a=2e3, xc=6e3, yc=2e3,
+                             periodic_x=0),
     "hanging_r2": W.MeshSpec(8e3, 8e3, 4e3, 4, 4, 2, 2,
                              ref_boxes=[(2e3, 6e3, 2e3, 6e3, 0, 2e3), (3.5e3, 4.5e3, 3.5e3, 4.5e3, 0, 0.5e3)]),
     "hanging_terrain_r4": W.MeshSpec(8e3, 8e3, 4e3, 3, 3, 2, 4, terrain=W.BELL, h0=300, a=1.5e3, xc=4e3, yc=4e3,
@@ -149,7 +154,7 @@ def _stage_inputs(om, oph, y, dt):
     return rho, F, G0, p0, u0
 
 
-@pytest.mark.parametrize("name", ["periodic_r2", "hanging_r2", "terrain_r3"])
+@pytest.mark.parametrize("name", ["periodic_r2", "hanging_r2", "terrain_r3", "terrain_r2", "terrain_r4"])
 @pytest.mark.parametrize("scheme", [dg.R1, dg.R2])
 def test_implicit_solve_parity_fixed(name, scheme):
     spec = MESHES[name]
