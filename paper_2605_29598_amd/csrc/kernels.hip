@@ -1762,8 +1762,15 @@ k_mv1_gc(const int* __restrict__ elist, int nel, const R* __restrict__ p, const 
             else if (kf[r] == FINE)
                 pb = sc * coarse_point<N>(p + (size_t)(unsigned)nf[r] * NP, T.f[1 - s], T, d, g.aux[e * 6 + f] & 3, pt);
             const R avg = (R)0.5 * (pa + pb);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) U[(f * 3 + c) * NF + pt] = avg * nsv[r][c];
+            // the n dS of an x- or y-face has only its own component (terrain-following
+            // map; the other two are exactly zero, so the sum of the first two is that
+            // component): one value there, three on the z-faces (lanes with f >= 4 only)
+            const int c0 = f < 4 ? d : 0;
+            U[(f * 3 + c0) * NF + pt] = avg * (f < 4 ? nsv[r][0] + nsv[r][1] : nsv[r][0]);
+            if (f >= 4) {
+                U[(f * 3 + 1) * NF + pt] = avg * nsv[r][1];
+                U[(f * 3 + 2) * NF + pt] = avg * nsv[r][2];
+            }
         }
     // volume: -int (sc p) div(phi_c) from the five metric-weighted pressures
     R vol[3] = {0, 0, 0};
@@ -1793,12 +1800,17 @@ k_mv1_gc(const int* __restrict__ elist, int nel, const R* __restrict__ p, const 
     R hq[3] = {0, 0, 0}, wz = 0;
     if (act) {
         R acc[3] = {0, 0, 0};
+#pragma unroll
         for (int f = 0; f < 6; ++f) {
             int m, pt;
             split_node<N>(f >> 1, node, m, pt);
             const R lf = T.f[f & 1][m];
+            if (f < 4) {
+                acc[f >> 1] += lf * U[(f * 3 + (f >> 1)) * NF + pt];
+            } else {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) acc[c] += lf * U[(f * 3 + c) * NF + pt];
+                for (int c = 0; c < 3; ++c) acc[c] += lf * U[(f * 3 + c) * NF + pt];
+            }
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[c] -= vol[c];
@@ -1837,13 +1849,19 @@ k_mv1_gc(const int* __restrict__ elist, int nel, const R* __restrict__ p, const 
 #pragma unroll
             for (int m = 0; m < N; ++m) vk[m] = s_pk[le][lp.off(r, m)];
             const R hk = hfac * trace_chain<N, R>(T.f[s], vk);
-            R wn = 0;
+            // x- and y-faces: the normal component of w only (as for {p} n dS above)
+            const int c0 = f < 4 ? f >> 1 : 0;
+            R vw[N];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                R vw[N];
+            for (int m = 0; m < N; ++m) vw[m] = s_a[le][c0][lp.off(r, m)];
+            R wn = trace_chain<N, R>(T.f[s], vw) * (f < 4 ? nsv[r][0] + nsv[r][1] : nsv[r][0]);
+            if (f >= 4) {
 #pragma unroll
-                for (int m = 0; m < N; ++m) vw[m] = s_a[le][c][lp.off(r, m)];
-                wn += trace_chain<N, R>(T.f[s], vw) * nsv[r][c];
+                for (int c = 1; c < 3; ++c) {
+#pragma unroll
+                    for (int m = 0; m < N; ++m) vw[m] = s_a[le][c][lp.off(r, m)];
+                    wn += trace_chain<N, R>(T.f[s], vw) * nsv[r][c];
+                }
             }
             FB[(size_t)(unsigned)(e * 6 + f) * NF + pt] = hk * wn;
         }

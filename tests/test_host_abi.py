@@ -63,6 +63,26 @@ def test_host_mesh_matches_oracle(spec):
     assert np.abs(wj - WJo).max() < 1e-12 * WJo.max()
 
 
+@pytest.mark.parametrize("degree", [1, 2, 3, 4])
+def test_compact_terrain_metric_reproduces_the_mapped_geometry(degree):
+    """Mesh creation forms the compact terrain metric of every terrain-following
+    element (per element: J22 and the two slopes over phi on the element's plane,
+    J22 on the side faces, phi per level) and fails unless its products reproduce
+    the mapped W cof(J), W detJ and n dS to 1e-12 of their largest entry. Each
+    creation below is that check, on a uniform mesh with walls, a refined mesh
+    with two nested boxes and, at r = 4, the non-conforming hill of Sec. 4.3."""
+    B = _binding()
+    specs = [W.MeshSpec(8e3, 6e3, 4e3, 4, 3, 2, degree, terrain=W.GAUSS, h0=600, a=1.5e3, xc=3e3, yc=4e3,
+                        periodic_x=0),
+             W.MeshSpec(8e3, 8e3, 4e3, 4, 4, 2, degree, terrain=W.BELL, h0=400, a=1e3, xc=4e3, yc=4e3,
+                        ref_boxes=[(2e3, 6e3, 2e3, 6e3, 0, 2e3), (3e3, 5e3, 3e3, 5e3, 0, 1e3)])]
+    if degree == 4:
+        specs.append(W.hill_benchmark(nonconforming=True).mesh)
+    for spec in specs:
+        m = B.Mesh(spec)
+        assert m.deformed
+
+
 def test_config_sizes():
     B = _binding()
     m = B.Mesh(W.orography(32, 32, 12, 4, refined=True).mesh)
