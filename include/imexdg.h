@@ -147,7 +147,10 @@ typedef struct {
 
 /* ---------------------------------------------------------------- mesh */
 /* Builds the mesh and its geometry on the host. Errors: IMX_EINVAL for bad
- * sizes, unbalanced refinement or inverted elements. */
+ * sizes, unbalanced refinement or inverted elements, and on terrain-following
+ * meshes when the compact per-element form of the metric (from which the
+ * Krylov passes form it) does not reproduce the mapped geometry to 1e-12 of
+ * its largest entry. */
 imx_status imx_mesh_create(const imx_mesh_desc* desc, imx_mesh** out);
 /* The same call under the name of the box-mesh constructor (every mesh of the
  * library is such a box, optionally refined and terrain-following). */
