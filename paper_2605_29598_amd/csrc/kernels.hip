@@ -195,7 +195,9 @@ __device__ __forceinline__ int fo_point(uint64_t w) { return (int)((w >> 48) & 0
 // WALL, computed instead of read from the face tables.
 template <typename R>
 __device__ __forceinline__ void grid_nbr(const Geom<R>& g, int e, int f, int& kind, int& nb) {
-    const int bz = e % g.gnz, t = e / g.gnz, bx = t % g.gnx, by = t / g.gnx;
+    // element indices are non-negative: unsigned division needs no sign handling
+    const unsigned nz = (unsigned)g.gnz, nx = (unsigned)g.gnx, t = (unsigned)e / nz, u = t / nx;
+    const int bz = (int)((unsigned)e - t * nz), bx = (int)(t - u * nx), by = (int)u;
     const int d = f >> 1, step = (f & 1) ? 1 : -1;
     int c[3] = {bx, by, bz};
     const int n[3] = {g.gnx, g.gny, g.gnz}, per[3] = {g.gpx, g.gpy, 0};
