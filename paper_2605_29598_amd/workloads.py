@@ -92,7 +92,7 @@ class Workload:
         return asdict(self)
 
 
-# ----------------------------------------------------------------- configs
+# --------------------------------------------------------------- workloads
 def tiny_box(degree=2, scheme=R2):
     """10x10x10 km box, 4x4x4 elements, isothermal 250 K rest state, f = 1e-4,
     Gaussian theta' 0.01 K of radius 2 km at the centre, 1e-6 noise, dt = 2 s."""

@@ -19,7 +19,7 @@ meshes (more terms per value). The floor is therefore
 with K_CANCEL = 1024. Measured on the GPU against the oracle, the momentum
 errors of every parity case lie at 0.01-0.15 of this floor with K = 256,
 except the r = 4 terrain-following mesh with hanging faces (1.0 of it): the
-bar keeps a factor 4 over the worst case. In config 1 (dt = 2 s,
+bar keeps a factor 4 over the worst case. In the tiny isothermal box (dt = 2 s,
 p = 1e5 Pa, h = 2.5 km) it is 1.8e-11 kg m^-2 s^-1 per step, against
 max|rho u| = 6e-4 and max|rho w| = 0.17; a bar of 1e-12 p / c would be
 3e-10. The velocity of a stage solve gets the same floor divided by the

@@ -193,7 +193,7 @@ def test_ark2_steps_parity_fixed(scheme):
 
 
 def test_ark2_steps_tiny_box_tolerance_mode():
-    """Config 1 (10x10x10 km, 4^3 elements, r = 2, 10 steps of 2 s, GMRES tol 1e-10)."""
+    """The tiny isothermal box (10x10x10 km, 4^3 elements, r = 2, 10 steps of 2 s, GMRES tol 1e-10)."""
     w = W.tiny_box()
     g, o, y0, gst, ost, sol = _run_steps(w.mesh, w.phys, w.num, w, 10)
     assert gst.gmres_iters == sum(s["gmres"] for s in ost)
@@ -238,7 +238,7 @@ MIXED_PER_STEP = 1e-10
 
 
 def test_mixed_precision_tiny_box_vs_oracle():
-    """Config 1 in the mixed mode: binary32 Krylov inner loop inside binary64
+    """The tiny isothermal box in the mixed mode: binary32 Krylov inner loop inside binary64
     defect correction to the same tolerance, against the FP64 oracle."""
     B = _B()
     w = W.tiny_box()
