@@ -55,6 +55,29 @@ def measured_traffic(workload, classes):
     return tot
 
 
+def measured_limiters(workload, stems):
+    """Busy fractions and occupancy of the binary64 kernels behind the timed
+    classes ({class: kernel-name pattern}; the most dispatched match is taken)
+    from the committed counter record of this workload, if the kernels have not
+    changed since it was taken: what bounds them, beside the HBM fraction."""
+    path = os.path.join(ROOT, "profiles", f"pmc_limiters_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    from paper_2605_29598_amd.profiling import kernel_source_hash
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    out = {}
+    for cls, stem in stems.items():
+        cands = [(v["dispatches"], k) for k, v in rec.get("kernels", {}).items() if stem in k and "double" in k]
+        if not cands:
+            return None
+        k = max(cands)[1]
+        out[cls] = {"kernel": k, **{c: x for c, x in rec["kernels"][k].items() if c != "dispatches"}}
+    return out
+
+
 def _oracle_worker(args):
     """One host process: the oracle's ARK2 steps on its own copy of the sample."""
     spec, phys, num, steps = args
@@ -342,6 +365,7 @@ def main():
     traffic = measured_traffic(w.name, ["pass1", "pass2"])
     roof = roofline_of(rep, ["pass1", "pass2"], args.steps, traffic,
                        note + "; one Schur-complement apply = one pass-1 and one pass-2 launch")
+    roof["limiters"] = measured_limiters(w.name, {"pass1": "k_mv1", "pass2": "k_mv2<"})
     operators = {}
     for name, cls in (("schur_apply", ["pass1", "pass2"]), ("explicit_residual", ["explicit"]),
                       ("picard_refresh", ["lambda"])):

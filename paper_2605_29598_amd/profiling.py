@@ -15,6 +15,13 @@ Any other counters (occupancy, VALU and LDS activity, instruction counts) are
 averaged per kernel and printed as a markdown table:
 
     python -m paper_2605_29598_amd.profiling counters A.csv [B.csv ...] [--match REGEX]
+
+The busy fractions and occupancy that say what bounds each kernel (VALUBusy,
+LdsUtil, LDSBankConflict, OccupancyPercent) are kept per kernel, stamped with
+the same hash, for the bench line's roofline object:
+
+    python -m paper_2605_29598_amd.profiling limiters A.csv [B.csv ...] [--match REGEX] \
+        --out profiles/pmc_limiters_<workload>.json
 """
 import argparse
 import collections
@@ -88,9 +95,10 @@ def summarize(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes):
     }
 
 
-def counter_table(paths, match=None):
-    """Mean value per dispatch of every counter in the given rocprofv3 CSVs,
-    per kernel (kernels whose name matches `match`, if given)."""
+def counter_means(paths, match=None):
+    """Per kernel (those whose name matches `match`, if given): the number of
+    dispatches, the compiler's resources as the profiler reports them, and the
+    mean value per dispatch of every counter in the given rocprofv3 CSVs."""
     per = collections.defaultdict(lambda: collections.defaultdict(list))
     res = {}
     for path in paths:
@@ -102,17 +110,47 @@ def counter_table(paths, match=None):
                 per[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
                 res[k] = (r["VGPR_Count"], r["Accum_VGPR_Count"], r["SGPR_Count"], r["LDS_Block_Size"],
                           r["Workgroup_Size"])
-    names = sorted({c for v in per.values() for c in v})
+    out = {}
+    for k in sorted(per):
+        rec = {"dispatches": max(len(v) for v in per[k].values()),
+               "resources": dict(zip(("VGPR", "AGPR", "SGPR", "LDS B", "WG"), res[k]))}
+        rec["counters"] = {c: sum(v) / len(v) for c, v in sorted(per[k].items())}
+        out[k] = rec
+    return out
+
+
+def counter_table(paths, match=None):
+    """Mean value per dispatch of every counter in the given rocprofv3 CSVs,
+    per kernel (kernels whose name matches `match`, if given), as a table."""
+    means = counter_means(paths, match)
+    names = sorted({c for v in means.values() for c in v["counters"]})
     head = ["kernel", "dispatches", "VGPR", "AGPR", "SGPR", "LDS B", "WG"] + names
     rows = ["| " + " | ".join(head) + " |", "|---" * len(head) + "|"]
-    for k in sorted(per):
-        n = max(len(v) for v in per[k].values())
-        cells = [f"`{k}`", str(n)] + list(res[k])
+    for k, v in means.items():
+        cells = [f"`{k}`", str(v["dispatches"])] + list(v["resources"].values())
         for c in names:
-            v = per[k].get(c)
-            cells.append("" if not v else f"{sum(v) / len(v):.4g}")
+            x = v["counters"].get(c)
+            cells.append("" if x is None else f"{x:.4g}")
         rows.append("| " + " | ".join(cells) + " |")
     return "\n".join(rows)
+
+
+# counters that say what bounds an element kernel, and how each reads
+LIMITER_COUNTERS = ("VALUBusy", "LdsUtil", "LDSBankConflict", "OccupancyPercent")
+
+
+def limiter_record(paths, match=None, command=""):
+    """Busy fractions and occupancy per kernel from rocprofv3 counter CSVs,
+    stamped with the kernel sources' hash (used only while the sources hash to
+    it). waves_per_simd = OccupancyPercent x 32 / 100 / 4 (32 wave slots per
+    compute unit, 4 SIMDs)."""
+    rec = {"kernel_source_hash": kernel_source_hash(), "command": command, "kernels": {}}
+    for k, v in counter_means(paths, match).items():
+        c = {n: v["counters"][n] for n in LIMITER_COUNTERS if n in v["counters"]}
+        if "OccupancyPercent" in c:
+            c["waves_per_simd"] = c["OccupancyPercent"] * 32 / 100 / 4
+        rec["kernels"][k] = {"dispatches": v["dispatches"], **c}
+    return rec
 
 
 WORKLOADS = {
@@ -289,6 +327,17 @@ def main():
         ap.add_argument("--match", default=None, help="regular expression on the kernel name")
         a = ap.parse_args()
         print(counter_table(a.csv, a.match))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "limiters":
+        ap = argparse.ArgumentParser(description="busy fractions and occupancy per kernel, hash-stamped")
+        ap.add_argument("mode")
+        ap.add_argument("csv", nargs="+")
+        ap.add_argument("--match", default=None, help="regular expression on the kernel name")
+        ap.add_argument("--out", required=True)
+        ap.add_argument("--command", default="")
+        a = ap.parse_args()
+        with open(a.out, "w") as fh:
+            json.dump(limiter_record(a.csv, a.match, a.command), fh, indent=1)
         return
     ap = argparse.ArgumentParser()
     for a in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--out"):

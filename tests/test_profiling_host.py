@@ -51,3 +51,34 @@ def test_counter_table_means_per_kernel(tmp_path):
     assert lines[0] == "| kernel | dispatches | VGPR | AGPR | SGPR | LDS B | WG | SQ_WAVES | VALUBusy |"
     assert len(lines) == 3
     assert lines[2] == "| `imx::k_explicit_gc<5, double>` | 2 | 64 | 0 | 32 | 1024 | 256 | 20 | 12.5 |"
+
+
+def test_limiter_record_keeps_busy_fractions_and_waves(tmp_path):
+    k1 = "void imx::k_mv1_gc<5, double, 2, true>(int const*)"
+    k2 = "void imx::k_mv1_gc<5, float, 2, true>(int const*)"
+    a = _csv(tmp_path / "a.csv", [(k1, "VALUBusy", 50.0), (k1, "VALUBusy", 60.0), (k1, "OccupancyPercent", 50.0),
+                                  (k1, "SQ_WAVES", 7.0), (k2, "LdsUtil", 40.0)])
+    rec = P.limiter_record([a], match="k_mv1", command="cmd")
+    assert rec["kernel_source_hash"] == P.kernel_source_hash() and rec["command"] == "cmd"
+    r1 = rec["kernels"]["imx::k_mv1_gc<5, double, 2, true>"]
+    # the means per dispatch, 32 wave slots over 4 SIMDs, and no counter outside the limiter set
+    assert r1["VALUBusy"] == 55.0 and r1["waves_per_simd"] == 4.0 and "SQ_WAVES" not in r1
+    assert rec["kernels"]["imx::k_mv1_gc<5, float, 2, true>"] == {"dispatches": 1, "LdsUtil": 40.0}
+
+
+def test_bench_reads_limiters_only_for_the_current_kernels(tmp_path, monkeypatch):
+    import json
+    import bench
+    k = "void imx::k_mv2<5, double, false, true, true>(int const*)"
+    a = _csv(tmp_path / "a.csv", [(k, "VALUBusy", 61.0), (k, "LdsUtil", 17.0)])
+    rec = P.limiter_record([a])
+    (tmp_path / "profiles").mkdir()
+    path = tmp_path / "profiles" / "pmc_limiters_w.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    got = bench.measured_limiters("w", {"pass2": "k_mv2<"})
+    assert got == {"pass2": {"kernel": "imx::k_mv2<5, double, false, true, true>", "VALUBusy": 61.0,
+                             "LdsUtil": 17.0}}
+    rec["kernel_source_hash"] = "0" * 16   # taken from other kernels: not used
+    path.write_text(json.dumps(rec))
+    assert bench.measured_limiters("w", {"pass2": "k_mv2<"}) is None
