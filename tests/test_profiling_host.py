@@ -1,6 +1,7 @@
-"""Host logic of the counter summaries: the copy calibration and the per-class
-byte counts, and the per-kernel counter table, on small synthetic rocprofv3
-CSV files (no GPU)."""
+"""Host logic of the measurement, without a GPU: the counter summaries (the
+copy calibration, the per-class byte counts, the per-kernel counter table and
+the limiter record) on small synthetic rocprofv3 CSV files, the bench's use of
+the hash-stamped records, and its refusal of more than one GPU."""
 import csv
 
 from paper_2605_29598_amd import profiling as P
@@ -82,3 +83,17 @@ def test_bench_reads_limiters_only_for_the_current_kernels(tmp_path, monkeypatch
     rec["kernel_source_hash"] = "0" * 16   # taken from other kernels: not used
     path.write_text(json.dumps(rec))
     assert bench.measured_limiters("w", {"pass2": "k_mv2<"}) is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The build runs on one GPU: bench.py --gpus N with N > 1 exits with a
+    message instead of timing anything."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
